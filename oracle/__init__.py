@@ -1,0 +1,37 @@
+"""CPU oracle for the FEA + sensitivity step of dp-adaptive multiresolution
+topology optimization (Gupta, van Keulen, Langelaar, arXiv 1811.09821).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library (its own basis, quadrature, numbering, assembly and solve), and it
+imports nothing from ``paper_1811_09821_amd``.
+
+What it computes, in plain FP64 (longdouble for residual accumulation):
+
+* the element stiffness of Sec. 2.2 (K_e as a sum of B^T D B over quadrature
+  points) in the composite per-density-cell form of Appendix B: one matrix
+  K_s per density cell, integrated exactly with (p+1)^2 Gauss points;
+* the modified SIMP modulus of Sec. 2.2, E(rho) = Emin + rho^q (E0 - Emin);
+* the assembled global K, the solve Ku = f (Eq. ``eq_comp_1``) by a sparse
+  direct factorisation followed by extended-precision iterative refinement;
+* compliance c = f^T u (Sec. 4.1, z = f) and the per-cell sensitivity
+  dc/drho = -E'(rho) u_e^T K_s u_e (the paper names the sensitivity analysis
+  in Sec. 1 and Sec. 2.1 but prints no formula; this is the adjoint result for
+  the self-adjoint compliance, lambda = -u).
+
+Every function cites the passage it follows.  Readings of points the paper
+leaves open (basis, mixed-p compatibility, layouts) are listed in the design doc of
+the repository.  Parity status: every function is pinned by ``-m "not gpu"``
+tests in ``tests/test_oracle_pins.py``; none is "parity unpinned".
+"""
+
+from .fem import (  # noqa: F401
+    basis_1d,
+    constitutive_plane_stress,
+    subcell_stiffness,
+    simp_modulus,
+    simp_modulus_derivative,
+)
+from .space import DofSpace, build_space  # noqa: F401
+from .solve import oracle_solve, assemble, element_dofs_global  # noqa: F401
