@@ -1,0 +1,232 @@
+/*
+ * mto.h: C ABI of the MI355X (gfx950) library for the finite element analysis
+ * and sensitivity step of dp-adaptive multiresolution topology optimization
+ * (Gupta, van Keulen, Langelaar, arXiv 1811.09821).
+ *
+ * What one solve computes, for every design instance and load case:
+ *   - the modified SIMP modulus of every density cell (Sec. 2.2):
+ *       E(rho) = Emin + rho^q (E0 - Emin);
+ *   - the element stiffness of Sec. 2.2 in the composite per-density-cell
+ *     form of Appendix B: K_e = sum_s E(rho_{e,s}) K_s, with K_s the exact
+ *     integral of B^T D0 B (plane stress) over density cell s;
+ *   - the displacement u solving K u = f (Eq. eq_comp_1) with supported DOFs
+ *     eliminated, by matrix-free Jacobi-preconditioned conjugate gradients
+ *     (K is never assembled);
+ *   - the compliance c = f^T u (the objective z^T u with z = f, Sec. 4.1);
+ *   - the sensitivity dc/drho_{e,s} = -E'(rho_{e,s}) u_e^T K_s u_e.  The paper
+ *     names the sensitivity analysis (Sec. 1, Sec. 2.1) without printing it;
+ *     compliance is self-adjoint (adjoint = -u), so no second solve is needed.
+ *
+ * Discretisation (readings of points the paper leaves open):
+ *   - structured mesh of unit-square elements, element e = ey*nelx + ex, origin
+ *     bottom-left, y up; vertex (vx, vy) with 0 <= vx <= nelx, 0 <= vy <= nely;
+ *   - each element has its own order p (1..MTO_MAX_P) and its own d x d grid of
+ *     density cells (d in 1..MTO_MAX_D), cell s = sy*d + sx (Sec. 2.1 background
+ *     mesh; the paper's "number of design points" is d*d here);
+ *   - hierarchic basis: (1 -/+ xi)/2 and integrated Legendre polynomials
+ *     int_{-1}^{xi} P_{k-1}, k = 2..p;
+ *   - mixed orders are made compatible by the conforming "minimum rule": a
+ *     shared edge carries the edge modes 2..min(p_left, p_right) (the
+ *     conforming continuous piecewise-Q_p space; the paper requires a compatible
+ *     mixed-p field, Sec. 3, without spelling out the construction).
+ *
+ * Layouts (all arrays FP64, contiguous, device memory unless stated):
+ *   - densities rho and sensitivities g: per instance, element-major cells
+ *     (instance i starts at its cell offset, mto_instance_info); g has one
+ *     block of n_cells per load case: [L_i][n_cells_i];
+ *   - displacements u: per instance [L_i][n_dof_i], scalar function id k has
+ *     DOFs 2k (x) and 2k+1 (y).  Ids: vertices vy*(nelx+1)+vx; then horizontal
+ *     edges (index vy*nelx+ex) each with modes 2..deg; then vertical edges
+ *     (index ey*(nelx+1)+vx); then element interiors (i, j >= 2, i fastest).
+ *     Supported DOFs hold 0;
+ *   - compliances c: per instance [L_i].
+ *   Instances are concatenated in the order they were given.
+ *
+ * Conventions: every function returns MTO_OK (0) or a negative error code and
+ * never throws; mto_last_error() gives a thread-local message.  Device work is
+ * enqueued on the HIP stream passed as `stream` (NULL: the null stream).
+ * A plan owns its device buffers and may be used by one stream at a time.
+ */
+#ifndef MTO_H
+#define MTO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MTO_MAX_P 4
+#define MTO_MAX_D 8
+
+enum {
+  MTO_OK = 0,
+  MTO_EINVAL = -1,      /* bad argument: shape, range, NULL pointer, load on a support */
+  MTO_ESINGULAR = -2,   /* supports leave a rigid-body mode free */
+  MTO_ENOCONV = -3,     /* PCG hit max_iter before reaching rtol (outputs still written) */
+  MTO_EBREAKDOWN = -4,  /* p^T K p <= 0 or non-finite value in PCG */
+  MTO_EHIP = -5,        /* HIP runtime error */
+  MTO_ENOMEM = -6       /* device allocation failed */
+};
+
+enum { /* support kinds */
+  MTO_SUP_VERTEX = 0,      /* vertex (a, b) */
+  MTO_SUP_EDGE_LEFT = 1,   /* whole boundary x = 0: its vertices and edge modes */
+  MTO_SUP_EDGE_RIGHT = 2,  /* x = nelx */
+  MTO_SUP_EDGE_BOTTOM = 3, /* y = 0 */
+  MTO_SUP_EDGE_TOP = 4     /* y = nely */
+};
+
+enum { /* element contraction kernels */
+  MTO_PATH_MFMA = 0,  /* per-(p,d) group, FP64 MFMA tiles (default) */
+  MTO_PATH_PLAIN = 1  /* one thread per element column, FP64 VALU (comparison path) */
+};
+
+typedef struct {
+  int32_t nelx, nely;
+  const int8_t* p; /* host [nelx*nely], order per element */
+  const int8_t* d; /* host [nelx*nely], density cells per side per element */
+} mto_mesh;
+
+typedef struct {
+  int32_t kind;      /* MTO_SUP_* */
+  int32_t a, b;      /* vertex coordinates for MTO_SUP_VERTEX, else ignored */
+  int32_t comp_mask; /* bit 0: fix x, bit 1: fix y */
+} mto_support;
+
+typedef struct {
+  int32_t vx, vy;    /* loaded vertex */
+  double fx, fy;     /* force components */
+  int32_t load_case; /* 0 .. n_load_cases-1 */
+} mto_point_load;
+
+typedef struct {
+  double E0;      /* solid Young's modulus (Sec. 2.2) */
+  double Emin;    /* void modulus, typically 1e-9 E0 (Sec. 2.2) */
+  double nu;      /* Poisson ratio */
+  double q;       /* SIMP penalisation power */
+  double rtol;    /* PCG stop: ||r||_2 <= rtol ||f||_2 */
+  int32_t max_iter;         /* PCG iteration cap per system (<= 0: 20 * n_free) */
+  int32_t kernel_path;      /* MTO_PATH_* */
+  int32_t iters_per_launch; /* PCG iterations per captured graph launch (<= 0: 32) */
+  int32_t max_restarts;     /* restarts from the true residual when it misses rtol (< 0: 2) */
+} mto_params;
+
+typedef struct {
+  mto_mesh mesh;
+  const mto_support* supports; /* host [n_supports] */
+  int32_t n_supports;
+  const mto_point_load* loads; /* host [n_loads] */
+  int32_t n_loads;
+  int32_t n_load_cases;        /* >= 1 */
+} mto_problem;
+
+typedef struct {
+  int32_t status;            /* MTO_OK, MTO_ENOCONV or MTO_EBREAKDOWN */
+  int32_t n_systems;         /* instances x load cases */
+  int32_t max_iterations;    /* over systems */
+  int32_t restarts;          /* restarts taken */
+  int32_t* iterations;       /* host [n_systems] or NULL: PCG iterations per system */
+  double* true_rel_residual; /* host [n_systems] or NULL: ||f - K u|| / ||f|| at exit */
+  double solve_ms;           /* host wall time of the call */
+} mto_solve_stats;
+
+typedef struct {
+  int32_t n_instances;
+  int32_t n_systems;     /* sum of load cases */
+  int32_t n_groups;      /* distinct (p, d) pairs */
+  int32_t reserved;
+  int64_t n_cells;       /* length of rho */
+  int64_t n_u;           /* length of u */
+  int64_t n_g;           /* length of g */
+  int64_t n_free_total;  /* sum over systems of free DOFs */
+  int64_t n_elements;
+  double flops_per_matvec; /* algorithmic contraction flops, all systems: sum 2 S n_e^2 */
+} mto_plan_info_t;
+
+typedef struct mto_plan mto_plan;
+
+/* Thread-local description of the last error (empty string if none). */
+const char* mto_last_error(void);
+
+/* Library version string. */
+const char* mto_version(void);
+
+/* Builds a plan for one design (Sec. 2.2 problem, Eq. eq_comp_1): checks the
+ * mesh, numbers the conforming space, groups elements by (p, d), uploads the
+ * K_s tables and the gather/scatter descriptors.  Host inputs are copied.
+ * Uses the current HIP device.  Errors: MTO_EINVAL (p or d out of range, a
+ * support or load outside the mesh, a load on a supported DOF),
+ * MTO_ESINGULAR (supports do not remove all three rigid-body modes),
+ * MTO_ENOMEM, MTO_EHIP.  *out receives the plan (caller destroys it). */
+int mto_plan_create(const mto_problem* prob, const mto_params* params, mto_plan** out);
+
+/* Same for n_instances independent designs (each with its own mesh, p, d,
+ * supports and load cases), solved together: all (p, d) groups of all
+ * instances share each kernel launch. */
+int mto_batch_plan_create(const mto_problem* probs, int32_t n_instances, const mto_params* params,
+                          mto_plan** out);
+
+/* Sizes of the plan's arrays (host struct filled). */
+int mto_plan_info(const mto_plan* plan, mto_plan_info_t* info);
+
+/* Offsets of instance `inst` in rho/g (cells), u and c, its sizes and free DOFs.
+ * Any output pointer may be NULL. */
+int mto_instance_info(const mto_plan* plan, int32_t inst, int64_t* cell_off, int64_t* n_cells,
+                      int64_t* u_off, int64_t* n_dof, int64_t* g_off, int64_t* c_off,
+                      int64_t* n_free, int32_t* n_load_cases);
+
+/* One FEA + sensitivity step.  rho [n_cells] in; u [n_u], c [n_load total] out;
+ * g [n_g] out (dc/drho per load case) or NULL to skip the sensitivity; u0 [n_u]
+ * initial guess or NULL (zero).  Blocks the calling thread until the PCG
+ * convergence of every system is known (it polls device flags once per
+ * graph launch).  stats (host, may be NULL) receives iteration counts.
+ * Returns MTO_OK, MTO_ENOCONV or MTO_EBREAKDOWN (outputs are written in all
+ * three cases), or an argument / HIP error. */
+int mto_solve(mto_plan* plan, const double* rho, double* u, double* c, double* g, const double* u0,
+              void* stream, mto_solve_stats* stats);
+
+/* Binds device buffers (rho in; u, c, g out; g may be NULL) and records the
+ * setup, one block of PCG iterations and the finishing steps as HIP graphs. */
+int mto_batch_capture(mto_plan* plan, const double* rho, double* u, double* c, double* g,
+                      void* stream);
+
+/* Replays the graphs bound by mto_batch_capture with the current contents of
+ * the bound rho: same results and return codes as mto_solve. */
+int mto_batch_replay(mto_plan* plan, void* stream, mto_solve_stats* stats);
+
+/* y = K x for every system of the plan (x, y in the u layout).  Supported
+ * DOFs of x are ignored and those of y are set to 0, i.e. y = K_ff x_f. */
+int mto_apply_stiffness(mto_plan* plan, const double* rho, const double* x, double* y, void* stream);
+
+/* g = -E'(rho) u_e^T K_s u_e for given displacements u (u layout). */
+int mto_sensitivity(mto_plan* plan, const double* rho, const double* u, double* g, void* stream);
+
+/* Jacobi preconditioner diagonal: diag(K) per instance in the u layout of its
+ * first load case (length sum_i n_dof_i); supported DOFs get 0. */
+int mto_jacobi_diagonal(mto_plan* plan, const double* rho, double* diag, void* stream);
+
+/* Times the element contraction of every (p, d) group of the plan for each
+ * tile shape (columns per wave) and keeps the fastest per group.  rho is a
+ * representative density field.  report (host, may be NULL) receives a text
+ * summary of at most report_len bytes. */
+int mto_autotune(mto_plan* plan, const double* rho, void* stream, char* report, int32_t report_len);
+
+/* Sets the tile shape (columns of 16 elements per wave: 1, 2 or 4) used for
+ * the group with order p and cell grid d (all groups if p <= 0). */
+int mto_set_tile(mto_plan* plan, int32_t p, int32_t d, int32_t ncol);
+
+/* Average time (ms, host float from HIP events on `stream`) of one PCG
+ * search-direction product K p, i.e. the element contraction kernels of all
+ * (p, d) groups, over `reps` launches after 3 warm-ups.  Runs the solve setup
+ * for rho first (overwrites the plan's PCG state). */
+int mto_time_contraction(mto_plan* plan, const double* rho, int32_t reps, void* stream, double* ms_per_matvec);
+
+/* Frees the plan and its device buffers (NULL is a no-op). */
+void mto_plan_destroy(mto_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTO_H */

@@ -1,0 +1,88 @@
+// Internal data structures shared by the host plan builder, the kernels and
+// the C ABI.  Nothing here crosses the ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mto.h"
+
+namespace mto {
+
+// Sizes of the element of order p: n_e = 2 (p+1)^2 local DOFs; NEP pads n_e
+// to a multiple of 4 (the k-width of one f64 MFMA step) and MB counts the
+// 16-row MFMA blocks that cover n_e output rows.
+constexpr int ne_of(int p) { return 2 * (p + 1) * (p + 1); }
+constexpr int nep_of(int p) { return (ne_of(p) + 3) / 4 * 4; }
+constexpr int mb_of(int p) { return (ne_of(p) + 15) / 16; }
+
+// Host-side K_s tables of Appendix B's composite integration:
+// ks[s*ne*ne + i*ne + j] for density cell s of a d x d grid.
+std::vector<double> subcell_tables(int p, int d, double nu);
+
+// Rearranges K_s into the MFMA A-operand order: for k-step t (4 consecutive
+// reduction indices k = s*NEP + j) and row block mb, lane l holds
+// Kcat[mb*16 + l%16][4t + l/16], with Kcat[row][s*NEP + j] = K_s[row][j]
+// (zero outside n_e).  Result length T*MB*64 with T = d*d*NEP/4.
+std::vector<double> mfma_fragments(const std::vector<double>& ks, int p, int d);
+
+// One design instance after numbering.
+struct InstanceHost {
+  int nelx = 0, nely = 0, L = 1;
+  std::vector<int8_t> p, d;
+  int64_t n_scalar = 0, n_dof = 0, n_cells = 0;
+  std::vector<int64_t> cell_off;     // [nel+1]
+  // free DOF numbering
+  std::vector<int32_t> full_to_free; // [n_dof], -1 if supported
+  std::vector<int32_t> free_to_full; // [n_free]
+  int32_t n_free = 0, nfv = 0, nfe = 0, nfi = 0;  // free vertex / edge / interior DOFs
+  int64_t n_slots = 0;
+  // per element: free DOF and slot of each local DOF (-1: absent or supported)
+  std::vector<int32_t> elem_free;    // [nel][ne(p_e)] packed by elem_dof_off
+  std::vector<int32_t> elem_slot;
+  std::vector<int64_t> elem_dof_off; // [nel+1]
+  // loads: rhs per load case in the free numbering, [L][n_free]
+  std::vector<double> f;
+};
+
+// Builds the numbering; returns MTO_OK or an error code with `err` filled.
+int build_instance(const mto_problem& prob, InstanceHost& out, std::string& err);
+
+// Per-iteration scalar state lives in partial-sum arrays; see the kernels.
+enum SysStatus : int32_t { SYS_RUNNING = 0, SYS_CONVERGED = 1, SYS_BREAKDOWN = 2 };
+
+// Descriptor of one tile of element columns: elements
+// [elem_begin, elem_begin + count) of group `group`, all for system `sys`.
+struct Tile {
+  int32_t group;
+  int32_t sys;
+  int32_t elem_begin;
+  int32_t count;
+};
+
+// A chunk of the free DOFs of one system for the vector kernels.
+struct Chunk {
+  int32_t sys;
+  int32_t begin;  // first DOF, relative to the system
+  int32_t end;
+  int32_t pad;
+};
+
+// Per-system constants on the device.
+struct SysDesc {
+  int64_t dof_off;     // offset in the PCG vectors
+  int64_t slot_off;    // offset in the slot array
+  int64_t u_off;       // offset of this system's block of u
+  int64_t g_off;       // offset of this system's block of g
+  int64_t inst_free_off;  // offset of the instance's free DOFs (dinv, free_to_full)
+  int64_t diag_off;    // offset of the instance in the per-instance (one load case) u layout
+  int32_t n_free;
+  int32_t nfv, nfe;
+  int32_t chunk_begin, chunk_end;
+  int32_t inst;
+  int32_t load;
+  int32_t c_index;     // index into c
+};
+
+}  // namespace mto

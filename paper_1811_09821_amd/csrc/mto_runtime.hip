@@ -1,0 +1,834 @@
+// Host runtime and C ABI: plan construction (groups, tiles, chunks, device
+// buffers), the PCG driver (captured HIP graphs of PCG iterations, polled
+// convergence), the true-residual check with restarts, outputs, and autotuning.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mto_internal.hpp"
+#include "mto_kernels.hpp"
+
+using namespace mto;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? MTO_ENOMEM : MTO_EHIP,                        \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                       \
+  } while (0)
+
+constexpr int CHUNK = 2048;  // free DOFs per vector-kernel block
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct GroupHost {
+  int p = 0, d = 0, S = 0, ne = 0, nep = 0, mb = 0;
+  int n_elems = 0, npad = 0, ncol = 4;
+  // per instance: element range [inst_begin[i], inst_begin[i+1]) in the group arrays
+  std::vector<int32_t> inst_begin;
+  double* kfrag = nullptr;
+  double* ks = nullptr;
+  double* kdiag = nullptr;
+  int32_t* gidx = nullptr;
+  int32_t* sidx = nullptr;
+  int32_t* cell = nullptr;
+  int tile_begin = 0, n_tiles = 0;
+  double flops = 0.0;  // 2 S ne^2 per element column
+};
+
+struct mto_plan {
+  int device = 0;
+  mto_params prm{};
+  int n_inst = 0, n_sys = 0;
+  // per instance
+  std::vector<int64_t> cell_off, n_cells, u_off, n_dof, g_off, c_off, n_free, free_off;
+  std::vector<int32_t> L;
+  int64_t n_cells_tot = 0, n_u = 0, n_g = 0, n_c = 0, n_free_inst_tot = 0, n_vec = 0, n_slots_tot = 0;
+  int64_t n_elements = 0;
+  std::vector<SysDesc> sys;
+  std::vector<Chunk> chunks;
+  std::vector<GroupHost> groups;
+  std::vector<Tile> tiles;
+  std::vector<DevBuf> allocs;
+  // device arrays
+  SysDesc* d_sys = nullptr;
+  Chunk* d_chunks = nullptr;
+  Tile* d_tiles = nullptr;
+  size_t tiles_cap = 0;
+  double *E = nullptr, *dE = nullptr;
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *f = nullptr, *dinv = nullptr;
+  double* slots = nullptr;
+  double *part_pq = nullptr, *part_rz = nullptr, *part_rr = nullptr, *part_aux = nullptr;
+  int32_t *status = nullptr, *iters = nullptr, *it_base = nullptr, *n_active = nullptr;
+  double *tol2 = nullptr, *sys_out = nullptr;
+  int32_t* f2f = nullptr;
+  // host pinned
+  int32_t* h_active = nullptr;  // [2]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
+  // graphs
+  hipGraphExec_t chunk_exec = nullptr;
+  int chunk_G = 0;
+  // bound (captured) buffers
+  bool bound = false;
+  const double* b_rho = nullptr;
+  double *b_u = nullptr, *b_c = nullptr, *b_g = nullptr;
+  hipGraphExec_t setup_exec = nullptr, resid_exec = nullptr, restart_exec = nullptr, out_exec = nullptr;
+
+  PcgDev pcg() const {
+    PcgDev s{};
+    s.sys = d_sys;
+    s.chunks = d_chunks;
+    s.n_chunks = (int32_t)chunks.size();
+    s.n_sys = n_sys;
+    s.x = x;
+    s.r = r;
+    s.z = z;
+    s.p = p;
+    s.q = q;
+    s.f = f;
+    s.dinv = dinv;
+    s.slots = slots;
+    s.part_pq = part_pq;
+    s.part_rz = part_rz;
+    s.part_rr = part_rr;
+    s.part_aux = part_aux;
+    s.status = status;
+    s.iters = iters;
+    s.tol2 = tol2;
+    s.sys_out = sys_out;
+    s.it_base = it_base;
+    s.n_active = n_active;
+    return s;
+  }
+  GroupDev gdev(const GroupHost& g) const {
+    GroupDev o{};
+    o.p = g.p;
+    o.d = g.d;
+    o.S = g.S;
+    o.npad = g.npad;
+    o.n_elems = g.n_elems;
+    o.tile_begin = g.tile_begin;
+    o.n_tiles = g.n_tiles;
+    o.ncol = g.ncol;
+    o.kfrag = g.kfrag;
+    o.ks = g.ks;
+    o.kdiag = g.kdiag;
+    o.gidx = g.gidx;
+    o.sidx = g.sidx;
+    o.cell = g.cell;
+    return o;
+  }
+};
+
+namespace {
+
+template <class T>
+int dev_alloc(mto_plan* P, T** out, size_t count) {
+  void* ptr = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) return fail(MTO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  P->allocs.push_back({ptr, bytes});
+  *out = (T*)ptr;
+  return MTO_OK;
+}
+
+template <class T>
+int dev_upload(mto_plan* P, T** out, const std::vector<T>& h) {
+  int rc = dev_alloc(P, out, h.size());
+  if (rc) return rc;
+  if (!h.empty()) HIP_TRY(hipMemcpy(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return MTO_OK;
+}
+
+void destroy_graphs(mto_plan* P) {
+  hipGraphExec_t* gs[] = {&P->chunk_exec, &P->setup_exec, &P->resid_exec, &P->restart_exec, &P->out_exec};
+  for (auto g : gs)
+    if (*g) {
+      (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+  P->bound = false;
+}
+
+// Tiles for every group with its current ncol; uploads them.
+int rebuild_tiles(mto_plan* P) {
+  P->tiles.clear();
+  for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+    GroupHost& g = P->groups[gi];
+    if (P->prm.kernel_path == MTO_PATH_PLAIN) g.ncol = 4;  // one 64-thread block per 64-column tile
+    const int tile_cols = 16 * g.ncol;
+    g.tile_begin = (int)P->tiles.size();
+    for (int i = 0; i < P->n_inst; ++i) {
+      const int a = g.inst_begin[i], b = g.inst_begin[i + 1];
+      if (a == b) continue;
+      for (int l = 0; l < P->L[i]; ++l) {
+        int sysi = 0;
+        for (int k = 0; k < i; ++k) sysi += P->L[k];
+        sysi += l;
+        for (int e = a; e < b; e += tile_cols)
+          P->tiles.push_back(Tile{(int32_t)gi, sysi, e, std::min(tile_cols, b - e)});
+      }
+    }
+    g.n_tiles = (int)P->tiles.size() - g.tile_begin;
+  }
+  if (P->tiles.size() > P->tiles_cap) {
+    if (P->d_tiles) {
+      (void)hipFree(P->d_tiles);
+      for (auto& a : P->allocs)
+        if (a.ptr == P->d_tiles) a.ptr = nullptr;
+    }
+    int rc = dev_alloc(P, &P->d_tiles, P->tiles.size());
+    if (rc) return rc;
+    P->tiles_cap = P->tiles.size();
+  }
+  if (!P->tiles.empty())
+    HIP_TRY(hipMemcpy(P->d_tiles, P->tiles.data(), P->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  destroy_graphs(P);
+  return MTO_OK;
+}
+
+int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MTO_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return MTO_OK;
+}
+
+int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan** out) {
+  if (!out) return fail(MTO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!probs || n < 1 || !prm) return fail(MTO_EINVAL, "no problems or params");
+  if (!(prm->rtol > 0.0) || !(prm->E0 > 0.0) || !(prm->Emin >= 0.0) || !(prm->Emin <= prm->E0) ||
+      !(prm->nu > -1.0 && prm->nu < 0.5) || !(prm->q >= 1.0))
+    return fail(MTO_EINVAL, "params out of range (rtol > 0, 0 <= Emin <= E0, -1 < nu < 0.5, q >= 1)");
+  if (prm->kernel_path != MTO_PATH_MFMA && prm->kernel_path != MTO_PATH_PLAIN)
+    return fail(MTO_EINVAL, "unknown kernel_path");
+  std::vector<InstanceHost> I(n);
+  for (int i = 0; i < n; ++i) {
+    std::string err;
+    int rc = build_instance(probs[i], I[i], err);
+    if (rc) return fail(rc, "instance " + std::to_string(i) + ": " + err);
+  }
+  mto_plan* P = new mto_plan();
+  P->prm = *prm;
+  if (P->prm.iters_per_launch <= 0) P->prm.iters_per_launch = 32;
+  if (P->prm.iters_per_launch % 2) P->prm.iters_per_launch += 1;  // keeps the parity of it_base even
+  if (P->prm.max_restarts < 0) P->prm.max_restarts = 2;
+  (void)hipGetDevice(&P->device);
+  P->n_inst = n;
+  auto cleanup = [&](int rc) {
+    mto_plan_destroy(P);
+    return rc;
+  };
+
+  // instance offsets and systems
+  P->cell_off.resize(n);
+  P->n_cells.resize(n);
+  P->u_off.resize(n);
+  P->n_dof.resize(n);
+  P->g_off.resize(n);
+  P->c_off.resize(n);
+  P->n_free.resize(n);
+  P->free_off.resize(n);
+  P->L.resize(n);
+  int64_t slot_acc = 0, vec_acc = 0, diag_acc = 0;
+  for (int i = 0; i < n; ++i) {
+    P->cell_off[i] = P->n_cells_tot;
+    P->n_cells[i] = I[i].n_cells;
+    P->u_off[i] = P->n_u;
+    P->n_dof[i] = I[i].n_dof;
+    P->g_off[i] = P->n_g;
+    P->c_off[i] = P->n_c;
+    P->n_free[i] = I[i].n_free;
+    P->free_off[i] = P->n_free_inst_tot;
+    P->L[i] = I[i].L;
+    P->n_cells_tot += I[i].n_cells;
+    P->n_u += (int64_t)I[i].L * I[i].n_dof;
+    P->n_g += (int64_t)I[i].L * I[i].n_cells;
+    P->n_c += I[i].L;
+    P->n_free_inst_tot += I[i].n_free;
+    P->n_elements += (int64_t)I[i].nelx * I[i].nely;
+    for (int l = 0; l < I[i].L; ++l) {
+      SysDesc sd{};
+      sd.dof_off = vec_acc;
+      sd.slot_off = slot_acc;
+      sd.u_off = P->u_off[i] + (int64_t)l * I[i].n_dof;
+      sd.g_off = P->g_off[i] + (int64_t)l * I[i].n_cells - P->cell_off[i];
+      sd.inst_free_off = P->free_off[i];
+      sd.diag_off = diag_acc;
+      sd.n_free = I[i].n_free;
+      sd.nfv = I[i].nfv;
+      sd.nfe = I[i].nfe;
+      sd.inst = i;
+      sd.load = l;
+      sd.c_index = (int32_t)(P->c_off[i] + l);
+      sd.chunk_begin = (int32_t)P->chunks.size();
+      for (int b = 0; b < I[i].n_free; b += CHUNK)
+        P->chunks.push_back(Chunk{(int32_t)P->sys.size(), b, std::min(I[i].n_free, b + CHUNK), 0});
+      sd.chunk_end = (int32_t)P->chunks.size();
+      P->sys.push_back(sd);
+      vec_acc += I[i].n_free;
+      slot_acc += I[i].n_slots;
+    }
+    diag_acc += I[i].n_dof;
+  }
+  P->n_sys = (int)P->sys.size();
+  P->n_vec = vec_acc;
+  P->n_slots_tot = slot_acc;
+  if (P->n_cells_tot >= ((int64_t)1 << 31) || vec_acc >= ((int64_t)1 << 31))
+    return cleanup(fail(MTO_EINVAL, "plan too large for 32-bit cell or DOF indices"));
+
+  // groups by (p, d), elements in instance order then element order
+  std::map<std::pair<int, int>, int> gid;
+  for (int i = 0; i < n; ++i)
+    for (size_t e = 0; e < I[i].p.size(); ++e) {
+      auto key = std::make_pair((int)I[i].p[e], (int)I[i].d[e]);
+      if (!gid.count(key)) {
+        int k = (int)gid.size();
+        gid[key] = k;
+      }
+    }
+  P->groups.resize(gid.size());
+  for (auto& kv : gid) {
+    GroupHost& g = P->groups[kv.second];
+    g.p = kv.first.first;
+    g.d = kv.first.second;
+    g.S = g.d * g.d;
+    g.ne = ne_of(g.p);
+    g.nep = nep_of(g.p);
+    g.mb = mb_of(g.p);
+    g.ncol = g.p >= 4 ? 2 : 4;
+  }
+  // order groups by (p, d) for stable output
+  for (int gi = 0; gi < (int)P->groups.size(); ++gi) {
+    GroupHost& g = P->groups[gi];
+    std::vector<std::pair<int, int>> elems;  // (instance, element)
+    g.inst_begin.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      g.inst_begin[i] = (int32_t)elems.size();
+      for (size_t e = 0; e < I[i].p.size(); ++e)
+        if (I[i].p[e] == g.p && I[i].d[e] == g.d) elems.emplace_back(i, (int)e);
+    }
+    g.inst_begin[n] = (int32_t)elems.size();
+    g.n_elems = (int)elems.size();
+    g.npad = std::max(64, (g.n_elems + 63) / 64 * 64);
+    std::vector<int32_t> gidx((size_t)g.nep * g.npad, -1), sidx((size_t)g.ne * g.npad, -1), cell(g.npad, 0);
+    for (int k = 0; k < g.n_elems; ++k) {
+      const int i = elems[k].first, e = elems[k].second;
+      const int64_t o = I[i].elem_dof_off[e];
+      for (int j = 0; j < g.ne; ++j) {
+        gidx[(size_t)j * g.npad + k] = I[i].elem_free[o + j];
+        sidx[(size_t)j * g.npad + k] = I[i].elem_slot[o + j];
+      }
+      cell[k] = (int32_t)(P->cell_off[i] + I[i].cell_off[e]);
+    }
+    std::vector<double> ks = subcell_tables(g.p, g.d, P->prm.nu);
+    std::vector<double> kfr = mfma_fragments(ks, g.p, g.d);
+    std::vector<double> kdiag((size_t)g.S * g.ne);
+    for (int s = 0; s < g.S; ++s)
+      for (int j = 0; j < g.ne; ++j) kdiag[(size_t)s * g.ne + j] = ks[(size_t)s * g.ne * g.ne + j * g.ne + j];
+    int rc;
+    if ((rc = dev_upload(P, &g.gidx, gidx)) || (rc = dev_upload(P, &g.sidx, sidx)) ||
+        (rc = dev_upload(P, &g.cell, cell)) || (rc = dev_upload(P, &g.ks, ks)) || (rc = dev_upload(P, &g.kfrag, kfr)) ||
+        (rc = dev_upload(P, &g.kdiag, kdiag)))
+      return cleanup(rc);
+    double per_col = 2.0 * g.S * g.ne * g.ne;
+    int64_t cols = 0;
+    for (int i = 0; i < n; ++i) cols += (int64_t)(g.inst_begin[i + 1] - g.inst_begin[i]) * P->L[i];
+    g.flops = per_col * (double)cols;
+  }
+
+  // vectors and state
+  std::vector<double> fh(P->n_vec, 0.0);
+  std::vector<int32_t> f2f(P->n_free_inst_tot);
+  for (int s = 0; s < P->n_sys; ++s) {
+    const SysDesc& sd = P->sys[s];
+    const InstanceHost& Ii = I[sd.inst];
+    std::copy(Ii.f.begin() + (size_t)sd.load * Ii.n_free, Ii.f.begin() + (size_t)(sd.load + 1) * Ii.n_free,
+              fh.begin() + sd.dof_off);
+  }
+  for (int i = 0; i < n; ++i) std::copy(I[i].free_to_full.begin(), I[i].free_to_full.end(), f2f.begin() + P->free_off[i]);
+  const size_t nch = P->chunks.size();
+  int rc;
+  if ((rc = dev_upload(P, &P->d_sys, P->sys)) || (rc = dev_upload(P, &P->d_chunks, P->chunks)) ||
+      (rc = dev_alloc(P, &P->E, P->n_cells_tot)) || (rc = dev_alloc(P, &P->dE, P->n_cells_tot)) ||
+      (rc = dev_alloc(P, &P->x, P->n_vec)) || (rc = dev_alloc(P, &P->r, P->n_vec)) ||
+      (rc = dev_alloc(P, &P->z, P->n_vec)) || (rc = dev_alloc(P, &P->p, P->n_vec)) ||
+      (rc = dev_alloc(P, &P->q, P->n_vec)) || (rc = dev_upload(P, &P->f, fh)) ||
+      (rc = dev_alloc(P, &P->dinv, P->n_free_inst_tot)) || (rc = dev_alloc(P, &P->slots, P->n_slots_tot)) ||
+      (rc = dev_alloc(P, &P->part_pq, nch)) || (rc = dev_alloc(P, &P->part_rz, 2 * nch)) ||
+      (rc = dev_alloc(P, &P->part_rr, 2 * nch)) || (rc = dev_alloc(P, &P->part_aux, 3 * nch)) ||
+      (rc = dev_alloc(P, &P->status, P->n_sys)) || (rc = dev_alloc(P, &P->iters, P->n_sys)) ||
+      (rc = dev_alloc(P, &P->it_base, 1)) || (rc = dev_alloc(P, &P->n_active, 1)) ||
+      (rc = dev_alloc(P, &P->tol2, P->n_sys)) || (rc = dev_alloc(P, &P->sys_out, 4 * (size_t)P->n_sys)) ||
+      (rc = dev_upload(P, &P->f2f, f2f)))
+    return cleanup(rc);
+  // slots that no element writes (missing neighbours) must read as zero forever
+  launch_fill(P->slots, 0.0, P->n_slots_tot, 0);
+  launch_fill(P->x, 0.0, P->n_vec, 0);
+  if ((rc = check_launch("fill"))) return cleanup(rc);
+  if (hipHostMalloc((void**)&P->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(MTO_ENOMEM, "hipHostMalloc failed"));
+  for (int k = 0; k < 2; ++k)
+    if (hipEventCreateWithFlags(&P->ev[k], hipEventDisableTiming) != hipSuccess)
+      return cleanup(fail(MTO_EHIP, "hipEventCreate failed"));
+  if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(fail(MTO_EHIP, "hipStreamCreate failed"));
+  if ((rc = rebuild_tiles(P))) return cleanup(rc);
+  HIP_TRY(hipDeviceSynchronize());
+  *out = P;
+  return MTO_OK;
+}
+
+// ---- enqueue helpers (all launches on st; usable under stream capture) ----
+
+void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_t st) {
+  const PcgDev s = P->pcg();
+  for (auto& g : P->groups) launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, xin, s, mode, it_k, st);
+}
+
+void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st) {
+  const PcgDev s = P->pcg();
+  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  for (auto& g : P->groups) launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, st);
+  launch_dinv(s, P->dinv, st);
+  if (u0) {
+    launch_gather_free(s, P->f2f, u0, P->x, st);
+    enq_elem_all(P, P->x, ELEM_APPLY, 0, st);
+    launch_init(s, 1, st);
+  } else {
+    launch_fill(P->x, 0.0, P->n_vec, st);
+    launch_init(s, 0, st);
+  }
+  launch_sys_setup(s, P->prm.rtol, st);
+}
+
+void enq_chunk(mto_plan* P, int G, hipStream_t st) {
+  const PcgDev s = P->pcg();
+  for (int k = 0; k < G; ++k) {
+    enq_elem_all(P, P->p, ELEM_PCG, k, st);
+    launch_dof1(s, k, st);
+    launch_dof2(s, k, st);
+  }
+  launch_advance(s, G, st);
+}
+
+void enq_residual(mto_plan* P, hipStream_t st) {
+  enq_elem_all(P, P->x, ELEM_APPLY, 0, st);
+  launch_residual(P->pcg(), st);
+}
+
+void enq_restart(mto_plan* P, hipStream_t st) {
+  // slots hold K x from the residual step
+  launch_init(P->pcg(), 1, st);
+  launch_sys_setup(P->pcg(), P->prm.rtol, st);
+}
+
+void enq_outputs(mto_plan* P, double* u, double* c, double* g, hipStream_t st) {
+  const PcgDev s = P->pcg();
+  launch_compliance(s, c, st);
+  launch_fill(u, 0.0, P->n_u, st);
+  launch_scatter_full(s, P->f2f, P->x, u, st);
+  if (g)
+    for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->x, g, P->d_sys, st);
+}
+
+int capture(mto_plan* P, hipGraphExec_t* exec, const std::function<void(hipStream_t)>& body) {
+  if (*exec) {
+    (void)hipGraphExecDestroy(*exec);
+    *exec = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+  body(P->cap_stream);
+  hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
+  if (e != hipSuccess) return fail(MTO_EHIP, std::string("stream capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(MTO_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return MTO_OK;
+}
+
+int ensure_chunk_graph(mto_plan* P) {
+  const int G = P->prm.iters_per_launch;
+  if (P->chunk_exec && P->chunk_G == G) return MTO_OK;
+  int rc = capture(P, &P->chunk_exec, [&](hipStream_t st) { enq_chunk(P, G, st); });
+  if (rc) return rc;
+  P->chunk_G = G;
+  return MTO_OK;
+}
+
+// Runs PCG iterations until every system has stopped or the cap is reached.
+int iterate(mto_plan* P, hipStream_t st, int64_t& launched) {
+  int rc = ensure_chunk_graph(P);
+  if (rc) return rc;
+  const int G = P->chunk_G;
+  int64_t cap = P->prm.max_iter;
+  if (cap <= 0) {
+    int64_t mx = 0;
+    for (int i = 0; i < P->n_inst; ++i) mx = std::max(mx, P->n_free[i]);
+    cap = std::max<int64_t>(20 * mx, 1000);
+  }
+  int64_t k = 0;
+  launched = 0;
+  while (true) {
+    HIP_TRY(hipGraphLaunch(P->chunk_exec, st));
+    HIP_TRY(hipMemcpyAsync(&P->h_active[k & 1], P->n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(P->ev[k & 1], st));
+    launched += G;
+    if (k >= 1) {
+      HIP_TRY(hipEventSynchronize(P->ev[(k - 1) & 1]));
+      if (P->h_active[(k - 1) & 1] == 0) break;
+    }
+    if (launched >= cap) break;
+    ++k;
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return MTO_OK;
+}
+
+struct SysResult {
+  std::vector<int32_t> status, iters;
+  std::vector<double> out;
+};
+
+int fetch(mto_plan* P, hipStream_t st, SysResult& R) {
+  R.status.resize(P->n_sys);
+  R.iters.resize(P->n_sys);
+  R.out.resize(4 * (size_t)P->n_sys);
+  HIP_TRY(hipMemcpyAsync(R.status.data(), P->status, P->n_sys * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(R.iters.data(), P->iters, P->n_sys * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(R.out.data(), P->sys_out, 4 * P->n_sys * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return MTO_OK;
+}
+
+// The shared solve driver; `graphs` selects captured setup/residual/outputs.
+int run_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, const double* u0, hipStream_t st,
+              mto_solve_stats* stats, bool graphs) {
+  auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if (graphs) {
+    HIP_TRY(hipGraphLaunch(P->setup_exec, st));
+  } else {
+    enq_setup(P, rho, u0, st);
+    if ((rc = check_launch("setup"))) return rc;
+  }
+  SysResult R;
+  int restarts = 0;
+  std::vector<int32_t> iters_total(P->n_sys, 0);
+  std::vector<double> prev_res(P->n_sys, 0.0);
+  int final_status = MTO_OK;
+  while (true) {
+    int64_t launched = 0;
+    if ((rc = iterate(P, st, launched))) return rc;
+    if (graphs) {
+      HIP_TRY(hipGraphLaunch(P->resid_exec, st));
+    } else {
+      enq_residual(P, st);
+      if ((rc = check_launch("residual"))) return rc;
+    }
+    if ((rc = fetch(P, st, R))) return rc;
+    bool any_breakdown = false, any_running = false, need_restart = false;
+    for (int s = 0; s < P->n_sys; ++s) {
+      iters_total[s] += R.iters[s];
+      if (R.status[s] == SYS_BREAKDOWN) any_breakdown = true;
+      else if (R.status[s] == SYS_RUNNING) any_running = true;
+      const double ff = R.out[4 * s + 0], res = R.out[4 * s + 2];
+      // Restart from the true residual while it misses rtol and the last
+      // restart still halved it; once it stalls it sits at the FP64 rounding
+      // floor of K u and further restarts cannot lower it.
+      const bool misses = res > P->prm.rtol * P->prm.rtol * ff;
+      const bool improving = restarts == 0 || res < 0.25 * prev_res[s];
+      if (R.status[s] == SYS_CONVERGED && misses && improving) need_restart = true;
+      prev_res[s] = res;
+    }
+    if (any_breakdown) {
+      final_status = MTO_EBREAKDOWN;
+      break;
+    }
+    if (any_running) {
+      final_status = MTO_ENOCONV;
+      break;
+    }
+    if (!need_restart || restarts >= P->prm.max_restarts) break;
+    ++restarts;
+    if (graphs) {
+      HIP_TRY(hipGraphLaunch(P->restart_exec, st));
+    } else {
+      enq_restart(P, st);
+      if ((rc = check_launch("restart"))) return rc;
+    }
+  }
+  if (graphs) {
+    HIP_TRY(hipGraphLaunch(P->out_exec, st));
+  } else {
+    enq_outputs(P, u, c, g, st);
+    if ((rc = check_launch("outputs"))) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (stats) {
+    stats->status = final_status;
+    stats->n_systems = P->n_sys;
+    stats->restarts = restarts;
+    stats->max_iterations = 0;
+    for (int s = 0; s < P->n_sys; ++s) {
+      stats->max_iterations = std::max(stats->max_iterations, iters_total[s]);
+      if (stats->iterations) stats->iterations[s] = iters_total[s];
+      if (stats->true_rel_residual) {
+        const double ff = R.out[4 * s + 0], res = R.out[4 * s + 2];
+        stats->true_rel_residual[s] = ff > 0 ? std::sqrt(res / ff) : std::sqrt(res);
+      }
+    }
+    stats->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (final_status == MTO_EBREAKDOWN) return fail(MTO_EBREAKDOWN, "PCG breakdown (p^T K p <= 0 or non-finite)");
+  if (final_status == MTO_ENOCONV) return fail(MTO_ENOCONV, "PCG reached max_iter before rtol");
+  return MTO_OK;
+}
+
+}  // namespace
+
+// ============================== C ABI ======================================
+
+extern "C" {
+
+const char* mto_last_error(void) { return g_err.c_str(); }
+
+const char* mto_version(void) { return "mto-mi355x 0.1 (gfx950)"; }
+
+int mto_plan_create(const mto_problem* prob, const mto_params* params, mto_plan** out) {
+  g_err.clear();
+  return build_plan(prob, 1, params, out);
+}
+
+int mto_batch_plan_create(const mto_problem* probs, int32_t n_instances, const mto_params* params,
+                          mto_plan** out) {
+  g_err.clear();
+  return build_plan(probs, n_instances, params, out);
+}
+
+int mto_plan_info(const mto_plan* P, mto_plan_info_t* info) {
+  if (!P || !info) return fail(MTO_EINVAL, "NULL argument");
+  info->n_instances = P->n_inst;
+  info->n_systems = P->n_sys;
+  info->n_groups = (int32_t)P->groups.size();
+  info->reserved = 0;
+  info->n_cells = P->n_cells_tot;
+  info->n_u = P->n_u;
+  info->n_g = P->n_g;
+  info->n_free_total = P->n_vec;
+  info->n_elements = P->n_elements;
+  double fl = 0.0;
+  for (auto& g : P->groups) fl += g.flops;
+  info->flops_per_matvec = fl;
+  return MTO_OK;
+}
+
+int mto_instance_info(const mto_plan* P, int32_t i, int64_t* cell_off, int64_t* n_cells, int64_t* u_off,
+                      int64_t* n_dof, int64_t* g_off, int64_t* c_off, int64_t* n_free, int32_t* n_load_cases) {
+  if (!P || i < 0 || i >= P->n_inst) return fail(MTO_EINVAL, "bad plan or instance index");
+  if (cell_off) *cell_off = P->cell_off[i];
+  if (n_cells) *n_cells = P->n_cells[i];
+  if (u_off) *u_off = P->u_off[i];
+  if (n_dof) *n_dof = P->n_dof[i];
+  if (g_off) *g_off = P->g_off[i];
+  if (c_off) *c_off = P->c_off[i];
+  if (n_free) *n_free = P->n_free[i];
+  if (n_load_cases) *n_load_cases = P->L[i];
+  return MTO_OK;
+}
+
+int mto_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, const double* u0, void* stream,
+              mto_solve_stats* stats) {
+  g_err.clear();
+  if (!P || !rho || !u || !c) return fail(MTO_EINVAL, "NULL plan, rho, u or c");
+  return run_solve(P, rho, u, c, g, u0, (hipStream_t)stream, stats, false);
+}
+
+int mto_batch_capture(mto_plan* P, const double* rho, double* u, double* c, double* g, void* stream) {
+  g_err.clear();
+  if (!P || !rho || !u || !c) return fail(MTO_EINVAL, "NULL plan, rho, u or c");
+  (void)stream;
+  int rc;
+  if ((rc = capture(P, &P->setup_exec, [&](hipStream_t st) { enq_setup(P, rho, nullptr, st); }))) return rc;
+  if ((rc = capture(P, &P->resid_exec, [&](hipStream_t st) { enq_residual(P, st); }))) return rc;
+  if ((rc = capture(P, &P->restart_exec, [&](hipStream_t st) { enq_restart(P, st); }))) return rc;
+  if ((rc = capture(P, &P->out_exec, [&](hipStream_t st) { enq_outputs(P, u, c, g, st); }))) return rc;
+  if ((rc = ensure_chunk_graph(P))) return rc;
+  P->bound = true;
+  P->b_rho = rho;
+  P->b_u = u;
+  P->b_c = c;
+  P->b_g = g;
+  return MTO_OK;
+}
+
+int mto_batch_replay(mto_plan* P, void* stream, mto_solve_stats* stats) {
+  g_err.clear();
+  if (!P) return fail(MTO_EINVAL, "NULL plan");
+  if (!P->bound || !P->setup_exec) return fail(MTO_EINVAL, "no captured buffers: call mto_batch_capture first");
+  return run_solve(P, P->b_rho, P->b_u, P->b_c, P->b_g, nullptr, (hipStream_t)stream, stats, true);
+}
+
+int mto_apply_stiffness(mto_plan* P, const double* rho, const double* x, double* y, void* stream) {
+  g_err.clear();
+  if (!P || !rho || !x || !y) return fail(MTO_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const PcgDev s = P->pcg();
+  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  launch_gather_free(s, P->f2f, x, P->q, st);
+  enq_elem_all(P, P->q, ELEM_APPLY, 0, st);
+  launch_fill(y, 0.0, P->n_u, st);
+  launch_assemble_to_full(s, P->f2f, y, 0, st);
+  return check_launch("apply_stiffness");
+}
+
+int mto_sensitivity(mto_plan* P, const double* rho, const double* u, double* g, void* stream) {
+  g_err.clear();
+  if (!P || !rho || !u || !g) return fail(MTO_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const PcgDev s = P->pcg();
+  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  launch_gather_free(s, P->f2f, u, P->q, st);
+  for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->q, g, P->d_sys, st);
+  return check_launch("sensitivity");
+}
+
+int mto_jacobi_diagonal(mto_plan* P, const double* rho, double* diag, void* stream) {
+  g_err.clear();
+  if (!P || !rho || !diag) return fail(MTO_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const PcgDev s = P->pcg();
+  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  for (auto& g : P->groups) launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, st);
+  int64_t acc = 0;
+  for (int i = 0; i < P->n_inst; ++i) acc += P->n_dof[i];
+  launch_fill(diag, 0.0, acc, st);
+  launch_assemble_to_full(s, P->f2f, diag, 1, st);
+  return check_launch("jacobi_diagonal");
+}
+
+int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol) {
+  g_err.clear();
+  if (!P || (ncol != 1 && ncol != 2 && ncol != 4)) return fail(MTO_EINVAL, "ncol must be 1, 2 or 4");
+  for (auto& g : P->groups)
+    if (p <= 0 || (g.p == p && g.d == d)) g.ncol = ncol;
+  return rebuild_tiles(P);
+}
+
+int mto_autotune(mto_plan* P, const double* rho, void* stream, char* report, int32_t report_len) {
+  g_err.clear();
+  if (!P || !rho) return fail(MTO_EINVAL, "NULL argument");
+  if (P->prm.kernel_path != MTO_PATH_MFMA) return MTO_OK;
+  hipStream_t st = (hipStream_t)stream;
+  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  launch_fill(P->q, 1.0, P->n_vec, st);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::string rep;
+  const int cand[3] = {1, 2, 4};
+  for (auto& g : P->groups) {
+    double best = 1e30;
+    int best_nc = g.ncol;
+    for (int nc : cand) {
+      g.ncol = nc;
+      int rc = rebuild_tiles(P);
+      if (rc) return rc;
+      const GroupDev gd = P->gdev(g);
+      const PcgDev s = P->pcg();
+      for (int w = 0; w < 3; ++w) launch_elem(gd, P->prm.kernel_path, P->d_tiles, P->E, P->q, s, ELEM_APPLY, 0, st);
+      const int reps = 20;
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int w = 0; w < reps; ++w) launch_elem(gd, P->prm.kernel_path, P->d_tiles, P->E, P->q, s, ELEM_APPLY, 0, st);
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      const double t = ms / reps;
+      char line[160];
+      snprintf(line, sizeof line, "p=%d d=%d ncol=%d: %.3f us (%.1f GF/s)\n", g.p, g.d, nc, 1e3 * t,
+               g.flops / (t * 1e6));
+      rep += line;
+      if (t < best) {
+        best = t;
+        best_nc = nc;
+      }
+    }
+    g.ncol = best_nc;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int rc = rebuild_tiles(P);
+  if (rc) return rc;
+  if (report && report_len > 0) {
+    snprintf(report, (size_t)report_len, "%s", rep.c_str());
+  }
+  return check_launch("autotune");
+}
+
+int mto_time_contraction(mto_plan* P, const double* rho, int32_t reps, void* stream, double* ms_per_matvec) {
+  g_err.clear();
+  if (!P || !rho || !ms_per_matvec || reps < 1) return fail(MTO_EINVAL, "bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  // PCG state of iteration 0 (x = 0, p = 0, beta = 0): each launch is the
+  // search-direction product of the first iteration, identical every time.
+  enq_setup(P, rho, nullptr, st);
+  int rc = check_launch("time_contraction setup");
+  if (rc) return rc;
+  for (int w = 0; w < 3; ++w) enq_elem_all(P, P->p, ELEM_PCG, 0, st);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, st));
+  for (int w = 0; w < reps; ++w) enq_elem_all(P, P->p, ELEM_PCG, 0, st);
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_per_matvec = (double)ms / reps;
+  return check_launch("time_contraction");
+}
+
+void mto_plan_destroy(mto_plan* P) {
+  if (!P) return;
+  (void)hipDeviceSynchronize();
+  destroy_graphs(P);
+  for (auto& a : P->allocs)
+    if (a.ptr) (void)hipFree(a.ptr);
+  if (P->h_active) (void)hipHostFree(P->h_active);
+  for (int k = 0; k < 2; ++k)
+    if (P->ev[k]) (void)hipEventDestroy(P->ev[k]);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  delete P;
+}
+
+}  // extern "C"

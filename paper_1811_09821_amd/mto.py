@@ -1,0 +1,318 @@
+"""Thin ctypes binding of libmto.so (include/mto.h).
+
+Argument marshalling only: every step of the FEA + sensitivity path runs in
+the HIP kernels of the library.  PyTorch supplies device memory and the
+current HIP stream.  There is no CPU fallback: if the library is missing the
+import of this module fails.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmto.so")
+
+MTO_OK, MTO_EINVAL, MTO_ESINGULAR, MTO_ENOCONV, MTO_EBREAKDOWN, MTO_EHIP, MTO_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+PATH_MFMA, PATH_PLAIN = 0, 1
+ERROR_NAMES = {MTO_EINVAL: "MTO_EINVAL", MTO_ESINGULAR: "MTO_ESINGULAR", MTO_ENOCONV: "MTO_ENOCONV",
+               MTO_EBREAKDOWN: "MTO_EBREAKDOWN", MTO_EHIP: "MTO_EHIP", MTO_ENOMEM: "MTO_ENOMEM"}
+
+
+class MtoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("nelx", ctypes.c_int32), ("nely", ctypes.c_int32),
+                ("p", ctypes.POINTER(ctypes.c_int8)), ("d", ctypes.POINTER(ctypes.c_int8))]
+
+
+class _Support(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("comp_mask", ctypes.c_int32)]
+
+
+class _Load(ctypes.Structure):
+    _fields_ = [("vx", ctypes.c_int32), ("vy", ctypes.c_int32), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("load_case", ctypes.c_int32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("E0", ctypes.c_double), ("Emin", ctypes.c_double), ("nu", ctypes.c_double),
+                ("q", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("kernel_path", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("mesh", _Mesh), ("supports", ctypes.POINTER(_Support)), ("n_supports", ctypes.c_int32),
+                ("loads", ctypes.POINTER(_Load)), ("n_loads", ctypes.c_int32),
+                ("n_load_cases", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_systems", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("iterations", ctypes.POINTER(ctypes.c_int32)),
+                ("true_rel_residual", ctypes.POINTER(ctypes.c_double)), ("solve_ms", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_int32), ("n_systems", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_cells", ctypes.c_int64), ("n_u", ctypes.c_int64),
+                ("n_g", ctypes.c_int64), ("n_free_total", ctypes.c_int64), ("n_elements", ctypes.c_int64),
+                ("flops_per_matvec", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run paper_1811_09821_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "mto_last_error": ([], ctypes.c_char_p),
+        "mto_version": ([], ctypes.c_char_p),
+        "mto_plan_create": ([ctypes.POINTER(_Problem), ctypes.POINTER(_Params), ctypes.POINTER(vp)], i32),
+        "mto_batch_plan_create": ([ctypes.POINTER(_Problem), i32, ctypes.POINTER(_Params), ctypes.POINTER(vp)],
+                                  i32),
+        "mto_plan_info": ([vp, ctypes.POINTER(_Info)], i32),
+        "mto_instance_info": ([vp, i32, i64p, i64p, i64p, i64p, i64p, i64p, i64p, ctypes.POINTER(i32)], i32),
+        "mto_solve": ([vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Stats)], i32),
+        "mto_batch_capture": ([vp, vp, vp, vp, vp, vp], i32),
+        "mto_batch_replay": ([vp, vp, ctypes.POINTER(_Stats)], i32),
+        "mto_apply_stiffness": ([vp, vp, vp, vp, vp], i32),
+        "mto_sensitivity": ([vp, vp, vp, vp, vp], i32),
+        "mto_jacobi_diagonal": ([vp, vp, vp, vp], i32),
+        "mto_autotune": ([vp, vp, vp, ctypes.c_char_p, i32], i32),
+        "mto_set_tile": ([vp, i32, i32, i32], i32),
+        "mto_time_contraction": ([vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
+        "mto_plan_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("mto_last_error", "mto_version", "mto_plan_create", "mto_batch_plan_create", "mto_plan_info",
+            "mto_instance_info", "mto_solve", "mto_batch_capture", "mto_batch_replay", "mto_apply_stiffness",
+            "mto_sensitivity", "mto_jacobi_diagonal", "mto_autotune", "mto_set_tile", "mto_time_contraction",
+            "mto_plan_destroy")
+
+
+def lib():
+    return _lib
+
+
+def version():
+    return _lib.mto_version().decode()
+
+
+def _check(rc, allow=()):
+    if rc != MTO_OK and rc not in allow:
+        raise MtoError(rc, _lib.mto_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _f64_cuda(t, n, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t
+
+
+def default_params(**kw):
+    prm = dict(E0=1.0, Emin=1e-9, nu=0.3, q=3.0, rtol=1e-11, max_iter=0, kernel_path=PATH_MFMA,
+               iters_per_launch=32, max_restarts=2)
+    prm.update(kw)
+    return prm
+
+
+class Plan:
+    """A plan for one or several design instances (batch), see mto.h.
+
+    `problems` are objects with attributes nelx, nely, p, d, supports,
+    loads, n_load_cases (e.g. ``problems.Problem``)."""
+
+    def __init__(self, problems, **params):
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        prm = default_params(**params)
+        self.params = prm
+        self._keep = []
+        arr = (_Problem * len(problems))()
+        for k, pr in enumerate(problems):
+            p = np.ascontiguousarray(pr.p, dtype=np.int8)
+            d = np.ascontiguousarray(pr.d, dtype=np.int8)
+            sup = (_Support * max(1, len(pr.supports)))(*[_Support(*map(int, s)) for s in pr.supports])
+            lds = (_Load * max(1, len(pr.loads)))(
+                *[_Load(int(l[0]), int(l[1]), float(l[2]), float(l[3]), int(l[4])) for l in pr.loads])
+            self._keep += [p, d, sup, lds]
+            arr[k].mesh = _Mesh(int(pr.nelx), int(pr.nely), p.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                                d.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+            arr[k].supports = ctypes.cast(sup, ctypes.POINTER(_Support))
+            arr[k].n_supports = len(pr.supports)
+            arr[k].loads = ctypes.cast(lds, ctypes.POINTER(_Load))
+            arr[k].n_loads = len(pr.loads)
+            arr[k].n_load_cases = int(pr.n_load_cases)
+        cp = _Params(prm["E0"], prm["Emin"], prm["nu"], prm["q"], prm["rtol"], prm["max_iter"],
+                     prm["kernel_path"], prm["iters_per_launch"], prm["max_restarts"])
+        h = ctypes.c_void_p()
+        _check(_lib.mto_batch_plan_create(arr, len(problems), ctypes.byref(cp), ctypes.byref(h)))
+        self._keep = []
+        self.handle = h
+        info = _Info()
+        _check(_lib.mto_plan_info(self.handle, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        self.n_instances = info.n_instances
+        self.n_systems = info.n_systems
+        self.instances = []
+        for i in range(info.n_instances):
+            v = [ctypes.c_int64() for _ in range(7)]
+            nl = ctypes.c_int32()
+            _check(_lib.mto_instance_info(self.handle, i, *[ctypes.byref(x) for x in v], ctypes.byref(nl)))
+            keys = ("cell_off", "n_cells", "u_off", "n_dof", "g_off", "c_off", "n_free")
+            rec = {k: x.value for k, x in zip(keys, v)}
+            rec["n_load_cases"] = nl.value
+            self.instances.append(rec)
+        self.n_c = sum(r["n_load_cases"] for r in self.instances)
+        self._bound = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.mto_plan_destroy(h)
+            self.handle = None
+
+    def close(self):
+        self.__del__()
+
+    # -- helpers --
+    def _empty(self, n, like):
+        import torch
+
+        return torch.empty(n, dtype=torch.float64, device=like.device)
+
+    def _stats(self):
+        st = _Stats()
+        it = (ctypes.c_int32 * self.n_systems)()
+        rr = (ctypes.c_double * self.n_systems)()
+        st.iterations = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+        st.true_rel_residual = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
+        return st, it, rr
+
+    @staticmethod
+    def _stats_dict(st, it, rr):
+        return dict(status=st.status, restarts=st.restarts, max_iterations=st.max_iterations,
+                    iterations=list(it), true_rel_residual=list(rr), solve_ms=st.solve_ms)
+
+    # -- operations --
+    def solve(self, rho, u0=None, sensitivities=True, stream=None, allow_noconv=False):
+        """Returns (u, c, g or None, stats) for densities rho (float64 device)."""
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        u = self._empty(self.info["n_u"], rho)
+        c = self._empty(self.n_c, rho)
+        g = self._empty(self.info["n_g"], rho) if sensitivities else None
+        if u0 is not None:
+            _f64_cuda(u0, self.info["n_u"], "u0")
+        st, it, rr = self._stats()
+        rc = _lib.mto_solve(self.handle, _ptr(rho), _ptr(u), _ptr(c), _ptr(g), _ptr(u0), _stream(stream),
+                            ctypes.byref(st))
+        _check(rc, allow=(MTO_ENOCONV,) if allow_noconv else ())
+        return u, c, g, self._stats_dict(st, it, rr)
+
+    def capture(self, rho, sensitivities=True, stream=None):
+        """Binds output buffers and captures the solve as HIP graphs."""
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        u = self._empty(self.info["n_u"], rho)
+        c = self._empty(self.n_c, rho)
+        g = self._empty(self.info["n_g"], rho) if sensitivities else None
+        _check(_lib.mto_batch_capture(self.handle, _ptr(rho), _ptr(u), _ptr(c), _ptr(g), _stream(stream)))
+        self._bound = (rho, u, c, g)
+        return u, c, g
+
+    def replay(self, stream=None, allow_noconv=False):
+        if self._bound is None:
+            raise RuntimeError("capture() first")
+        st, it, rr = self._stats()
+        rc = _lib.mto_batch_replay(self.handle, _stream(stream), ctypes.byref(st))
+        _check(rc, allow=(MTO_ENOCONV,) if allow_noconv else ())
+        return self._stats_dict(st, it, rr)
+
+    def apply_stiffness(self, rho, x, stream=None):
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        _f64_cuda(x, self.info["n_u"], "x")
+        y = self._empty(self.info["n_u"], rho)
+        _check(_lib.mto_apply_stiffness(self.handle, _ptr(rho), _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def sensitivity(self, rho, u, stream=None):
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        _f64_cuda(u, self.info["n_u"], "u")
+        g = self._empty(self.info["n_g"], rho)
+        _check(_lib.mto_sensitivity(self.handle, _ptr(rho), _ptr(u), _ptr(g), _stream(stream)))
+        return g
+
+    def jacobi_diagonal(self, rho, stream=None):
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        n = sum(r["n_dof"] for r in self.instances)
+        dg = self._empty(n, rho)
+        _check(_lib.mto_jacobi_diagonal(self.handle, _ptr(rho), _ptr(dg), _stream(stream)))
+        return dg
+
+    def autotune(self, rho, stream=None):
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        buf = ctypes.create_string_buffer(8192)
+        _check(_lib.mto_autotune(self.handle, _ptr(rho), _stream(stream), buf, len(buf)))
+        self._bound = None
+        return buf.value.decode()
+
+    def time_contraction(self, rho, reps=50, stream=None):
+        """Average ms of one PCG product K p (all groups), HIP events."""
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        ms = ctypes.c_double()
+        _check(_lib.mto_time_contraction(self.handle, _ptr(rho), int(reps), _stream(stream), ctypes.byref(ms)))
+        return ms.value
+
+    def set_tile(self, ncol, p=0, d=0):
+        _check(_lib.mto_set_tile(self.handle, int(p), int(d), int(ncol)))
+        self._bound = None
+
+    # -- layout helpers --
+    def split_u(self, u):
+        """Per instance [L, n_dof] views of the u layout."""
+        return [u[r["u_off"]:r["u_off"] + r["n_load_cases"] * r["n_dof"]].view(r["n_load_cases"], r["n_dof"])
+                for r in self.instances]
+
+    def split_g(self, g):
+        return [g[r["g_off"]:r["g_off"] + r["n_load_cases"] * r["n_cells"]].view(r["n_load_cases"], r["n_cells"])
+                for r in self.instances]
+
+    def split_c(self, c):
+        return [c[r["c_off"]:r["c_off"] + r["n_load_cases"]] for r in self.instances]

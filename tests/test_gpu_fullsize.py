@@ -1,0 +1,56 @@
+"""Full-size parity: the benchmark workloads in the launch configuration the
+benchmark times (autotuned tiles, captured graphs), against the CPU oracle's
+direct solve of the same design (it finishes in seconds at these sizes), plus
+properties that hold at any size."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle_solve, simp_modulus, simp_modulus_derivative
+from paper_1811_09821_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_fullsize_against_oracle(cuda, cfg):
+    from paper_1811_09821_amd import mto
+
+    pr = P.config(cfg)
+    print(f"\nfull-size config {cfg}: {pr.name}", flush=True)
+    plan = mto.Plan(pr)
+    rho = torch.tensor(pr.rho, device=cuda)
+    plan.autotune(rho)
+    u, c, g = plan.capture(rho)
+    st = plan.replay()
+    torch.cuda.synchronize()
+    print(f"iterations {st['iterations']} true residual {st['true_rel_residual']}", flush=True)
+    o = oracle_solve(**pr.oracle_args())
+    un, cn, gn = u.cpu().numpy(), c.cpu().numpy(), g.cpu().numpy()
+    assert rel(un, o["u"].ravel()) < 1e-8
+    assert abs(cn[0] - o["c"][0]) < 1e-8 * abs(o["c"][0])
+    assert rel(gn, o["g"].ravel()) < 1e-7
+    assert np.abs(gn - o["g"].ravel()).max() < 1e-7 * np.abs(o["g"]).max()
+    # PCG stopped at recursive residual 1e-11; the true residual ||f - K u||
+    # evaluated in FP64 cannot drop below the rounding of the product K u,
+    # about eps || |K| |u| || (the oracle refines in longdouble instead).
+    K = oracle_solve(**pr.oracle_args(), want_K=True)["K"]
+    floor = np.finfo(float).eps * np.linalg.norm(abs(K) @ np.abs(o["u"].ravel())) / np.linalg.norm(o["f"])
+    print(f"FP64 residual floor {floor:.3e}", flush=True)
+    assert st["true_rel_residual"][0] <= max(1e-11, 10 * floor)
+
+    # properties at full size: c = u^T K u, Euler identity, sign of g
+    Ku = plan.apply_stiffness(rho, u).cpu().numpy()
+    assert abs(float(un @ Ku) - cn[0]) < 1e-9 * cn[0]
+    w = -gn / simp_modulus_derivative(pr.rho, pr.E0, pr.Emin, pr.q)
+    lhs = float(np.dot(pr.rho, gn))
+    rhs = -pr.q * (cn[0] - pr.Emin * w.sum())
+    assert abs(lhs - rhs) < 1e-8 * abs(rhs)
+    # g <= 0 up to the rounding of u_e^T K_s u_e (near-rigid void cells)
+    assert (gn <= 1e-10 * np.abs(gn).max()).all()
+    assert abs(float(np.dot(simp_modulus(pr.rho, pr.E0, pr.Emin, pr.q), w)) - cn[0]) < 1e-8 * cn[0]

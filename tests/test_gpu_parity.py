@@ -1,0 +1,235 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Tolerances (relative, norm-wise, written here): u and c within 1e-8, dc/drho
+within 1e-7 (both the 2-norm and the max-norm ratios), with PCG run to a
+relative residual of 1e-11.  The element contraction itself (no solve) is
+compared at 1e-13: it is one FP64 product with a different summation order.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle_solve, simp_modulus_derivative, subcell_stiffness
+from oracle.solve import assemble, element_dofs_global, free_mask
+from oracle.space import build_space
+from paper_1811_09821_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+U_TOL, C_TOL, G_TOL = 1e-8, 1e-8, 1e-7
+
+
+def mto():
+    from paper_1811_09821_amd import mto as m
+
+    return m
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def rel_max(a, b):
+    mb = np.abs(b).max()
+    return float(np.abs(a - b).max() / mb) if mb > 0 else float(np.abs(a).max())
+
+
+def oracle_sens_given_u(pr, u_full):
+    """Oracle formula g = -E'(rho) u_e^T K_s u_e for given displacements."""
+    space = build_space(pr.nelx, pr.nely, pr.p)
+    off = pr.cell_offsets()
+    dE = simp_modulus_derivative(pr.rho, pr.E0, pr.Emin, pr.q)
+    L = u_full.shape[0]
+    g = np.zeros((L, pr.n_cells))
+    cache = {}
+    for e in range(pr.nel):
+        key = (int(pr.p[e]), int(pr.d[e]))
+        if key not in cache:
+            cache[key] = subcell_stiffness(key[0], key[1], pr.nu)
+        Ks = cache[key]
+        G = element_dofs_global(space, e)
+        for lc in range(L):
+            ue = np.where(G >= 0, u_full[lc][np.maximum(G, 0)], 0.0)
+            g[lc, off[e]:off[e + 1]] = -dE[off[e]:off[e + 1]] * np.einsum("i,sij,j->s", ue, Ks, ue)
+    return g
+
+
+def check_solution(plan, prs, u, c, g, stats):
+    us, cs, gs = plan.split_u(u), plan.split_c(c), plan.split_g(g)
+    for i, pr in enumerate(prs):
+        o = oracle_solve(**pr.oracle_args())
+        uu = us[i].cpu().numpy()
+        assert rel(uu, o["u"]) < U_TOL, (pr.name, rel(uu, o["u"]))
+        cc = cs[i].cpu().numpy()
+        assert np.all(np.abs(cc - o["c"]) <= C_TOL * np.abs(o["c"])), (pr.name, cc, o["c"])
+        gg = gs[i].cpu().numpy()
+        for lc in range(pr.n_load_cases):
+            assert rel(gg[lc], o["g"][lc]) < G_TOL, (pr.name, lc, rel(gg[lc], o["g"][lc]))
+            assert rel_max(gg[lc], o["g"][lc]) < G_TOL, (pr.name, lc, rel_max(gg[lc], o["g"][lc]))
+    assert stats["status"] == 0, stats
+
+
+GROUPS = [(p, d) for p in (1, 2, 3, 4) for d in (1, 2, 3, 4, 5)]
+
+
+@pytest.mark.parametrize("p,d", GROUPS)
+def test_matvec_every_group(cuda, p, d):
+    """y = K x (element contraction + slot assembly) for all 20 (p, d) groups,
+    on a 7 x 5 mesh (35 elements: several 16-column tiles and a ragged tail)
+    with each tile width."""
+    pr = P.uniform_random(7, 5, p, d, seed=100 + 10 * p + d)
+    K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
+    free = free_mask(space, pr.supports)
+    x = np.random.default_rng(p * d).standard_normal(space.n_dof)
+    x[~free] = 0.0
+    yref = K @ x
+    yref[~free] = 0.0
+    plan = mto().Plan(pr)
+    rho = torch.tensor(pr.rho, device=cuda)
+    xt = torch.tensor(x, device=cuda)
+    for ncol in (1, 2, 4):
+        plan.set_tile(ncol)
+        y = plan.apply_stiffness(rho, xt).cpu().numpy()
+        assert rel(y, yref) < 1e-13, (p, d, ncol, rel(y, yref))
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_matvec_mixed_and_diag(cuda, path):
+    """Mixed mesh (minimum-rule edges, all four groups of the dp rule) and the
+    Jacobi diagonal, MFMA and plain comparison paths."""
+    pr = P.small_mixed(13, 7, seed=5)
+    K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
+    free = free_mask(space, pr.supports)
+    x = np.random.default_rng(1).standard_normal(space.n_dof)
+    x[~free] = 0.0
+    yref = K @ x
+    yref[~free] = 0.0
+    plan = mto().Plan(pr, kernel_path=path)
+    rho = torch.tensor(pr.rho, device=cuda)
+    y = plan.apply_stiffness(rho, torch.tensor(x, device=cuda)).cpu().numpy()
+    assert rel(y, yref) < 1e-13
+    dg = plan.jacobi_diagonal(rho).cpu().numpy()
+    dref = K.diagonal().copy()
+    dref[~free] = 0.0
+    assert rel(dg, dref) < 1e-14
+
+
+def test_sensitivity_kernel_given_u(cuda):
+    """g = -E' u_e^T K_s u_e from given (random) displacements, mixed mesh,
+    two load cases."""
+    pr = P.small_mixed(11, 6, seed=8, n_loads=2)
+    space = build_space(pr.nelx, pr.nely, pr.p)
+    free = free_mask(space, pr.supports)
+    u = np.random.default_rng(2).standard_normal((2, space.n_dof))
+    u[:, ~free] = 0.0
+    gref = oracle_sens_given_u(pr, u)
+    plan = mto().Plan(pr)
+    for ncol in (1, 2, 4):
+        plan.set_tile(ncol)
+        g = plan.sensitivity(torch.tensor(pr.rho, device=cuda), torch.tensor(u.ravel(), device=cuda))
+        g = g.cpu().numpy().reshape(2, -1)
+        assert rel(g, gref) < 1e-12
+        assert rel_max(g, gref) < 1e-12
+
+
+CASES = {
+    "mbb20x10": lambda: [P.mbb_20x10()],
+    "uniform_p1d3": lambda: [P.uniform_random(9, 4, 1, 3, 1)],
+    "uniform_p2d2": lambda: [P.uniform_random(9, 4, 2, 2, 2)],
+    "uniform_p3d4": lambda: [P.uniform_random(8, 4, 3, 4, 3)],
+    "uniform_p4d5": lambda: [P.uniform_random(6, 3, 4, 5, 4)],
+    "mixed16x8": lambda: [P.small_mixed(16, 8, seed=3)],
+    "mixed_3loads": lambda: [P.small_mixed(14, 7, seed=4, n_loads=3)],
+    "cantilever_field": lambda: [P.cantilever_uniform(24, 12, 3, 4, sigma=3.0, volfrac=0.4, seed=2)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_solve_parity(cuda, name):
+    """u, c and dc/drho against the oracle (direct solve)."""
+    prs = CASES[name]()
+    plan = mto().Plan(prs)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
+
+
+def test_solve_parity_plain_path(cuda):
+    prs = [P.small_mixed(12, 6, seed=6, n_loads=2)]
+    plan = mto().Plan(prs, kernel_path=1)
+    rho = torch.tensor(prs[0].rho, device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
+
+
+def test_batch_parity_uneven_instances(cuda):
+    """Several independent designs of uneven size, order mix and load count in
+    one plan: each instance against its own oracle solve."""
+    prs = [P.small_mixed(10, 5, seed=21, n_loads=1), P.mbb_20x10(),
+           P.small_mixed(18, 9, seed=22, n_loads=3), P.uniform_random(5, 3, 4, 5, 23),
+           P.small_mixed(8, 4, seed=24, n_loads=2)]
+    plan = mto().Plan(prs)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
+
+
+def test_capture_replay_matches_eager(cuda):
+    """hipGraph capture of the whole step, replayed several times with eager
+    work and synchronisation in between and densities changed in place: every
+    replay equals the eager solve of the same densities."""
+    prs = [P.small_mixed(12, 6, seed=31, n_loads=2), P.mbb_20x10()]
+    plan = mto().Plan(prs)
+    rho0 = np.concatenate([p.rho for p in prs])
+    rho = torch.tensor(rho0, device=cuda)
+    ub, cb, gb = plan.capture(rho)
+    eager = mto().Plan(prs)
+    for k in range(3):
+        scale = 1.0 - 0.1 * k
+        rho.copy_(torch.tensor(np.clip(rho0 * scale, 1e-3, 1.0), device=cuda))
+        st = plan.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device=cuda, dtype=torch.float64).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        u, c, g, st2 = eager.solve(rho)
+        assert torch.equal(ub, u) and torch.equal(cb, c) and torch.equal(gb, g), k
+
+
+def test_warm_start(cuda):
+    """u0 = the solution: PCG stops at once with the same outputs."""
+    pr = P.small_mixed(12, 6, seed=41)
+    plan = mto().Plan(pr)
+    rho = torch.tensor(pr.rho, device=cuda)
+    u, c, g, st = plan.solve(rho)
+    u2, c2, g2, st2 = plan.solve(rho, u0=u)
+    assert st2["max_iterations"] <= 2
+    assert rel(u2.cpu().numpy(), u.cpu().numpy()) < 1e-10
+    assert abs(c2.item() - c.item()) <= 1e-10 * abs(c.item())
+
+
+def test_noconv_reported(cuda):
+    """max_iter too small: MTO_ENOCONV, outputs still written."""
+    m = mto()
+    pr = P.small_mixed(12, 6, seed=42)
+    plan = m.Plan(pr, max_iter=4, iters_per_launch=2, max_restarts=0)
+    rho = torch.tensor(pr.rho, device=cuda)
+    with pytest.raises(m.MtoError) as ei:
+        plan.solve(rho)
+    assert ei.value.code == m.MTO_ENOCONV
+    u, c, g, st = plan.solve(rho, allow_noconv=True)
+    assert st["status"] == m.MTO_ENOCONV and torch.isfinite(u).all()
+
+
+def test_repeat_solve_is_deterministic(cuda):
+    """No atomics: two solves give bit-identical outputs."""
+    pr = P.small_mixed(16, 8, seed=51, n_loads=2)
+    plan = mto().Plan(pr)
+    rho = torch.tensor(pr.rho, device=cuda)
+    a = plan.solve(rho)
+    b = plan.solve(rho)
+    for x, y in zip(a[:3], b[:3]):
+        assert torch.equal(x, y)
