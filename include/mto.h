@@ -109,7 +109,7 @@ typedef struct {
   int32_t max_iter;         /* PCG iteration cap per system (<= 0: 20 * n_free) */
   int32_t kernel_path;      /* MTO_PATH_* */
   int32_t iters_per_launch; /* PCG iterations per captured graph launch (<= 0: 32) */
-  int32_t max_restarts;     /* restarts from the true residual when it misses rtol (< 0: 2) */
+  int32_t max_restarts;     /* refinement restarts from the true residual when it misses rtol (< 0: 3) */
 } mto_params;
 
 typedef struct {
@@ -127,7 +127,8 @@ typedef struct {
   int32_t max_iterations;    /* over systems */
   int32_t restarts;          /* restarts taken */
   int32_t* iterations;       /* host [n_systems] or NULL: PCG iterations per system */
-  double* true_rel_residual; /* host [n_systems] or NULL: ||f - K u|| / ||f|| at exit */
+  double* true_rel_residual; /* host [n_systems] or NULL: ||f - K u|| / ||f|| at exit, with
+                                f - K u evaluated in double-double arithmetic */
   double solve_ms;           /* host wall time of the call */
 } mto_solve_stats;
 
@@ -202,19 +203,29 @@ int mto_apply_stiffness(mto_plan* plan, const double* rho, const double* x, doub
 /* g = -E'(rho) u_e^T K_s u_e for given displacements u (u layout). */
 int mto_sensitivity(mto_plan* plan, const double* rho, const double* u, double* g, void* stream);
 
+/* Backward of the map densities -> compliances: out[cell] = sum over the
+ * load cases l of the cell's instance of w[l] g_l[cell], with g as written by
+ * mto_solve (layout [L_i][n_cells_i] per instance) and w [total load cases]
+ * in the c layout; out [n_cells] in the rho layout.  Compliance is
+ * self-adjoint, so g_l = dc_l/drho already is the adjoint product. */
+int mto_weighted_sensitivity(mto_plan* plan, const double* g, const double* w, double* out, void* stream);
+
 /* Jacobi preconditioner diagonal: diag(K) per instance in the u layout of its
  * first load case (length sum_i n_dof_i); supported DOFs get 0. */
 int mto_jacobi_diagonal(mto_plan* plan, const double* rho, double* diag, void* stream);
 
 /* Times the element contraction of every (p, d) group of the plan for each
- * tile shape (columns per wave) and keeps the fastest per group.  rho is a
+ * tile shape (ncol x ks, see mto_set_tile) and keeps the fastest per group.  rho is a
  * representative density field.  report (host, may be NULL) receives a text
  * summary of at most report_len bytes. */
 int mto_autotune(mto_plan* plan, const double* rho, void* stream, char* report, int32_t report_len);
 
-/* Sets the tile shape (columns of 16 elements per wave: 1, 2 or 4) used for
- * the group with order p and cell grid d (all groups if p <= 0). */
-int mto_set_tile(mto_plan* plan, int32_t p, int32_t d, int32_t ncol);
+/* Sets the tile shape of the element contraction for the group with order p
+ * and cell grid d (all groups if p <= 0): ncol blocks of 16 element columns
+ * per tile (1, 2 or 4) and ks waves per tile splitting the density cells
+ * (1..8, clamped to d*d).  MTO_EINVAL if the shape needs more than 64 KB of
+ * LDS.  Invalidates captured graphs. */
+int mto_set_tile(mto_plan* plan, int32_t p, int32_t d, int32_t ncol, int32_t ks);
 
 /* Average time (ms, host float from HIP events on `stream`) of one PCG
  * search-direction product K p, i.e. the element contraction kernels of all

@@ -1,0 +1,39 @@
+"""torch.autograd.Function: densities -> compliances, with the hand-written
+adjoint.
+
+Forward: one FEA + sensitivity step through the C ABI (u, c = f^T u and
+g = dc/drho per load case).  Compliance is self-adjoint (the adjoint state is
+-u), so g is the whole backward and no second solve is needed; backward
+returns sum_l grad_l g_l, combined by a library kernel.
+"""
+
+import torch
+
+from . import mto
+
+
+class MTOCompliance(torch.autograd.Function):
+    """c = MTOCompliance.apply(rho, plan): compliances [total load cases] of
+    every instance of ``plan`` (layout of mto.h) for densities rho."""
+
+    @staticmethod
+    def forward(ctx, rho, plan):
+        need_grad = ctx.needs_input_grad[0]
+        u, c, g, stats = plan.solve(rho.detach().contiguous(), sensitivities=need_grad)
+        ctx.plan = plan
+        ctx.stats = stats
+        if need_grad:
+            ctx.save_for_backward(g)
+        return c
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        (g,) = ctx.saved_tensors
+        grad_rho = ctx.plan.weighted_sensitivity(g, grad_c.detach().contiguous().to(torch.float64))
+        return grad_rho, None
+
+
+def total_compliance(rho, plan):
+    """Sum of the compliances of all load cases and instances (the objective
+    of a multi-load compliance design)."""
+    return MTOCompliance.apply(rho, plan).sum()

@@ -54,19 +54,32 @@ enum SysStatus : int32_t { SYS_RUNNING = 0, SYS_CONVERGED = 1, SYS_BREAKDOWN = 2
 
 // Descriptor of one tile of element columns: elements
 // [elem_begin, elem_begin + count) of group `group`, all for system `sys`.
+// The system's offsets and partial-sum range are copied in, so a kernel
+// needs one descriptor load before its data loads.
 struct Tile {
+  int64_t dof_off;    // system offset in the PCG vectors
+  int64_t slot_off;   // system offset in the slot array
   int32_t group;
   int32_t sys;
   int32_t elem_begin;
   int32_t count;
+  int32_t pc_begin;   // the system's chunk (partial-sum) range
+  int32_t pc_end;
 };
 
-// A chunk of the free DOFs of one system for the vector kernels.
+// A chunk of the free DOFs of one system for the vector kernels, with the
+// system's constants copied in.
 struct Chunk {
+  int64_t dof_off;
+  int64_t slot_off;
+  int64_t inst_free_off;
   int32_t sys;
-  int32_t begin;  // first DOF, relative to the system
+  int32_t begin;      // first DOF, relative to the system
   int32_t end;
-  int32_t pad;
+  int32_t nfv, nfe;
+  int32_t pc_begin;   // the system's chunk range
+  int32_t pc_end;
+  int32_t load;
 };
 
 // Per-system constants on the device.

@@ -32,6 +32,9 @@ namespace {
 
 constexpr int BLOCK = 256;
 constexpr int WAVES = BLOCK / 64;
+// Vector kernels: one block per chunk of VBLOCK free DOFs of one system.
+constexpr int VBLOCK = 1024;
+constexpr int VWAVES = VBLOCK / 64;
 
 // Sum of arr[a..b) by one wave: strided sequential sums per lane, then a xor
 // butterfly.  Every lane ends with the same bits, and so does every wave that
@@ -44,7 +47,8 @@ __device__ __forceinline__ double wave_sum(const double* __restrict__ arr, int a
   return v;
 }
 
-// Deterministic block sum (BLOCK threads), valid in thread 0.
+// Deterministic block sum (NW waves), valid in thread 0.
+template <int NW>
 __device__ __forceinline__ double block_sum(double v, double* lds) {
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -53,7 +57,7 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   __syncthreads();
   double t = 0.0;
   if (threadIdx.x == 0)
-    for (int w = 0; w < WAVES; ++w) t += lds[w];
+    for (int w = 0; w < NW; ++w) t += lds[w];
   return t;
 }
 
@@ -62,21 +66,23 @@ struct Scal {
   double beta;
 };
 
-// Convergence state and beta of system `sys` at iteration `it` (see header
-// comment).  A newly converged system is latched by the caller's designated
-// thread.
-__device__ __forceinline__ Scal pcg_state(const PcgDev& s, int sys, int it, bool want_beta) {
-  const SysDesc& sd = s.sys[sys];
+// Convergence state and beta of system `sys` (partial sums in chunks
+// [pc_begin, pc_end)) at iteration `it`.  A newly converged system is latched
+// by a designated thread of the caller.
+__device__ __forceinline__ Scal pcg_state(const PcgDev& s, int sys, int pc_begin, int pc_end, int it,
+                                          bool want_beta) {
   const int pi = it & 1;
-  const double rr = wave_sum(s.part_rr + pi * s.n_chunks, sd.chunk_begin, sd.chunk_end);
-  Scal o;
-  o.active = (s.status[sys] == SYS_RUNNING) && !(rr <= s.tol2[sys]);
-  o.beta = 0.0;
-  if (o.active && want_beta && it > 0) {
-    const double rz_new = wave_sum(s.part_rz + pi * s.n_chunks, sd.chunk_begin, sd.chunk_end);
-    const double rz_old = wave_sum(s.part_rz + (pi ^ 1) * s.n_chunks, sd.chunk_begin, sd.chunk_end);
-    o.beta = rz_new / rz_old;
+  const int st = s.status[sys];
+  const double tol2 = s.tol2[sys];
+  const double rr = wave_sum(s.part_rr + pi * s.n_chunks, pc_begin, pc_end);
+  double rz_new = 0.0, rz_old = 1.0;
+  if (want_beta && it > 0) {
+    rz_new = wave_sum(s.part_rz + pi * s.n_chunks, pc_begin, pc_end);
+    rz_old = wave_sum(s.part_rz + (pi ^ 1) * s.n_chunks, pc_begin, pc_end);
   }
+  Scal o;
+  o.active = (st == SYS_RUNNING) && !(rr <= tol2);
+  o.beta = (want_beta && it > 0) ? rz_new / rz_old : 0.0;
   return o;
 }
 
@@ -103,29 +109,134 @@ __device__ __forceinline__ double slot_sum(const double* __restrict__ sl, int i,
 }
 
 // ---------------------------------------------------------------------------
-// Element contraction on MFMA.  One wave per tile of 16*NC element columns of
-// one system; block = 4 waves (independent tiles).
-template <int P, int NC>
-__global__ __launch_bounds__(BLOCK) void k_elem_mfma(GroupDev g, const Tile* __restrict__ tiles,
-                                                    const double* __restrict__ E,
-                                                    const double* __restrict__ xin, PcgDev s, int mode,
-                                                    int it_k) {
-  constexpr int NE = ne_of(P), NEP = nep_of(P), MB = mb_of(P), NJ = NEP / 4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tix = blockIdx.x * WAVES + wave;
-  if (tix >= g.n_tiles) return;
-  const Tile t = tiles[g.tile_begin + tix];
-  const SysDesc& sd = s.sys[t.sys];
-  double beta = 0.0;
-  if (mode == ELEM_PCG) {
-    const Scal sc = pcg_state(s, t.sys, *s.it_base + it_k, true);
-    if (!sc.active) return;
-    beta = sc.beta;
-  }
-  const int n = lane & 15, kq = lane >> 4;
-  const double* __restrict__ xs = xin + sd.dof_off;
-  const double* __restrict__ zs = s.z + sd.dof_off;
+// Double-double arithmetic for the accurate residual f - K x (error-free
+// transformations: Knuth's two-sum, FMA-based two-product).  Contraction of
+// the rounded operations into FMAs is switched off inside these helpers.
+struct dd_t {
+  double hi, lo;
+};
 
+__device__ __forceinline__ dd_t two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b;
+  const double bb = s - a;
+  const double e = (a - (s - bb)) + (b - bb);
+  return dd_t{s, e};
+}
+
+__device__ __forceinline__ dd_t dd_add(dd_t x, dd_t y) {
+#pragma clang fp contract(off)
+  const dd_t s = two_sum(x.hi, y.hi);
+  const double lo = s.lo + (x.lo + y.lo);
+  return two_sum(s.hi, lo);
+}
+
+// x + a * b for doubles a, b
+__device__ __forceinline__ dd_t dd_fma(dd_t x, double a, double b) {
+#pragma clang fp contract(off)
+  const double p = a * b;
+  const double e = fma(a, b, -p);
+  return dd_add(x, dd_t{p, e});
+}
+
+// a * y for a double a
+__device__ __forceinline__ dd_t dd_scale(double a, dd_t y) {
+#pragma clang fp contract(off)
+  const double p = a * y.hi;
+  const double e = fma(a, y.hi, -p);
+  const double lo = fma(a, y.lo, e);
+  return two_sum(p, lo);
+}
+
+// Element contraction in double-double, one thread per element column:
+// y_e = sum_s E_s (K_s x_e) with every product and sum carried to ~2^-104,
+// results to (slots, slots_lo).  Used only for the true residual.
+template <int P>
+__global__ __launch_bounds__(64) void k_elem_dd(GroupDev g, const Tile* __restrict__ tiles,
+                                               const double* __restrict__ E, const double* __restrict__ xhi,
+                                               const double* __restrict__ xlo, double* __restrict__ slots,
+                                               double* __restrict__ slots_lo) {
+  constexpr int NE = ne_of(P);
+  const Tile t = tiles[g.tile_begin + blockIdx.x];
+  const int col = threadIdx.x;
+  if (col >= t.count) return;
+  const int el = t.elem_begin + col;
+  const double* __restrict__ xh = xhi + t.dof_off;
+  const double* __restrict__ xl = xlo + t.dof_off;
+  double u[NE], ul[NE];
+#pragma unroll
+  for (int j = 0; j < NE; ++j) {
+    const int gi = g.gidx[j * g.npad + el];
+    u[j] = gi >= 0 ? xh[gi] : 0.0;
+    ul[j] = gi >= 0 ? xl[gi] : 0.0;
+  }
+  const int cb = g.cell[el];
+  for (int row = 0; row < NE; ++row) {
+    const int si = g.sidx[row * g.npad + el];
+    if (si < 0) continue;
+    dd_t y{0.0, 0.0};
+    for (int sc = 0; sc < g.S; ++sc) {
+      const double* __restrict__ kr = g.ks + ((size_t)sc * NE + row) * NE;
+      dd_t tacc{0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < NE; ++j) {
+        tacc = dd_fma(tacc, kr[j], u[j]);
+        tacc.lo = fma(kr[j], ul[j], tacc.lo);  // low part of x: one rounding at ~2^-106 relative
+      }
+      y = dd_add(y, dd_scale(E[cb + sc], two_sum(tacc.hi, tacc.lo)));
+    }
+    slots[t.slot_off + si] = y.hi;
+    slots_lo[t.slot_off + si] = y.lo;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Element contraction on MFMA.  One block per tile of 16*NC element columns
+// of one system; the block's KS waves split the density cells of the
+// reduction (wave w takes cells [w S / KS, (w+1) S / KS)) and their partial
+// products are summed through LDS.  The tile's u_e (or p_old and z in PCG
+// mode) are gathered once into LDS by the whole block, while wave 0 reduces
+// the PCG scalars.
+template <int P, int NC>
+__global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __restrict__ tiles,
+                                                  const double* __restrict__ E, const double* __restrict__ xin,
+                                                  PcgDev s, int mode, int it_k) {
+  constexpr int NE = ne_of(P), NEP = nep_of(P), MB = mb_of(P), NJ = NEP / 4, TC = 16 * NC;
+  constexpr int NACC = MB * NC * 4;
+  extern __shared__ double lds[];
+  double* ush = lds + 2;             // [NEP][TC] (u or p_old), then [NEP][TC] z in PCG mode
+  double* red = lds + 2;             // reused after the gather: [KS-1][NACC][64]
+  const int ks = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const Tile t = tiles[g.tile_begin + blockIdx.x];
+  const bool pcg = mode == ELEM_PCG;
+  if (pcg && wave == 0) {
+    const Scal sc = pcg_state(s, t.sys, t.pc_begin, t.pc_end, *s.it_base + it_k, true);
+    if (lane == 0) {
+      lds[0] = sc.beta;
+      lds[1] = sc.active ? 1.0 : 0.0;
+    }
+  }
+  {
+    const double* __restrict__ xs = xin + t.dof_off;
+    const double* __restrict__ zs = s.z + t.dof_off;
+    for (int k = threadIdx.x; k < NEP * TC; k += blockDim.x) {
+      const int row = k / TC, col = k - row * TC;
+      const int el = t.elem_begin + col;
+      const int gi = (col < t.count) ? g.gidx[row * g.npad + el] : -1;
+      double v = 0.0, zv = 0.0;
+      if (gi >= 0) {
+        v = xs[gi];
+        if (pcg) zv = zs[gi];
+      }
+      ush[k] = v;
+      if (pcg) ush[NEP * TC + k] = zv;
+    }
+  }
+  __syncthreads();
+  if (pcg && lds[1] == 0.0) return;  // system stopped: uniform over the block
+  const double beta = pcg ? lds[0] : 0.0;
+  const int n = lane & 15, kq = lane >> 4;
   double u[NC][NJ];
   int cellb[NC];
   bool valid[NC];
@@ -133,44 +244,83 @@ __global__ __launch_bounds__(BLOCK) void k_elem_mfma(GroupDev g, const Tile* __r
   for (int c = 0; c < NC; ++c) {
     const int col = c * 16 + n;
     valid[c] = col < t.count;
-    const int el = t.elem_begin + col;
-    cellb[c] = valid[c] ? g.cell[el] : 0;
+    cellb[c] = valid[c] ? g.cell[t.elem_begin + col] : 0;
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
-      const int gi = valid[c] ? g.gidx[(4 * jj + kq) * g.npad + el] : -1;
-      double v = 0.0;
-      if (gi >= 0) v = (mode == ELEM_PCG) ? fma(beta, xs[gi], zs[gi]) : xs[gi];
-      u[c][jj] = v;
+      const int k = (4 * jj + kq) * TC + col;
+      u[c][jj] = pcg ? fma(beta, ush[k], ush[NEP * TC + k]) : ush[k];
     }
   }
-
   d4 acc[MB][NC];
 #pragma unroll
   for (int b = 0; b < MB; ++b)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[b][c] = d4{0.0, 0.0, 0.0, 0.0};
 
+  const int s_begin = (wave * g.S) / ks, s_end = ((wave + 1) * g.S) / ks;
   const double* __restrict__ kf = g.kfrag + lane;
-  for (int sc = 0; sc < g.S; ++sc) {
-    double Es[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) Es[c] = valid[c] ? E[cellb[c] + sc] : 0.0;
+  // One density cell's A fragments (NJ k-steps x MB row blocks) and moduli.
+  auto load_slice = [&](int sc, double (&a)[NJ][MB], double (&e)[NC]) {
     const double* __restrict__ kfs = kf + (size_t)sc * NJ * MB * 64;
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-      double a[MB];
+    for (int jj = 0; jj < NJ; ++jj)
 #pragma unroll
-      for (int b = 0; b < MB; ++b) a[b] = kfs[(jj * MB + b) * 64];
+      for (int b = 0; b < MB; ++b) a[jj][b] = kfs[(jj * MB + b) * 64];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) e[c] = valid[c] ? E[cellb[c] + sc] : 0.0;
+  };
+  auto mma_slice = [&](const double (&a)[NJ][MB], const double (&e)[NC]) {
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj)
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const double bv = Es[c] * u[c][jj];
+        const double bv = e[c] * u[c][jj];
 #pragma unroll
-        for (int b = 0; b < MB; ++b) acc[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b], bv, acc[b][c], 0, 0, 0);
+        for (int b = 0; b < MB; ++b) acc[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[jj][b], bv, acc[b][c], 0, 0, 0);
       }
+  };
+  if constexpr (NJ * MB <= 20) {
+    // ping-pong register buffers: the next cell's fragments load during the
+    // current cell's MFMAs
+    double a0[NJ][MB], a1[NJ][MB], e0[NC], e1[NC];
+    if (s_begin < s_end) load_slice(s_begin, a0, e0);
+    for (int sc = s_begin; sc < s_end; sc += 2) {
+      if (sc + 1 < s_end) load_slice(sc + 1, a1, e1);
+      mma_slice(a0, e0);
+      if (sc + 1 >= s_end) break;
+      if (sc + 2 < s_end) load_slice(sc + 2, a0, e0);
+      mma_slice(a1, e1);
+    }
+  } else {
+    double a0[NJ][MB], e0[NC];
+    for (int sc = s_begin; sc < s_end; ++sc) {
+      load_slice(sc, a0, e0);
+      mma_slice(a0, e0);
     }
   }
 
-  double* __restrict__ sl = s.slots + sd.slot_off;
+  if (ks > 1) {
+    __syncthreads();  // the gather buffer is reused for the partial products
+    if (wave > 0) {
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[((wave - 1) * NACC + (b * NC + c) * 4 + r) * 64 + lane] = acc[b][c][r];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+    for (int w = 1; w < ks; ++w)
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[b][c][r] += red[((w - 1) * NACC + (b * NC + c) * 4 + r) * 64 + lane];
+  }
+
+  double* __restrict__ sl = s.slots + t.slot_off;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     if (!valid[c]) continue;
@@ -199,18 +349,17 @@ __global__ __launch_bounds__(64) void k_elem_plain(GroupDev g, const Tile* __res
   const int tix = blockIdx.x;
   if (tix >= g.n_tiles) return;
   const Tile t = tiles[g.tile_begin + tix];
-  const SysDesc& sd = s.sys[t.sys];
   double beta = 0.0;
   if (mode == ELEM_PCG) {
-    const Scal sc = pcg_state(s, t.sys, *s.it_base + it_k, true);
+    const Scal sc = pcg_state(s, t.sys, t.pc_begin, t.pc_end, *s.it_base + it_k, true);
     if (!sc.active) return;
     beta = sc.beta;
   }
   const int col = threadIdx.x;
   if (col >= t.count) return;
   const int el = t.elem_begin + col;
-  const double* __restrict__ xs = xin + sd.dof_off;
-  const double* __restrict__ zs = s.z + sd.dof_off;
+  const double* __restrict__ xs = xin + t.dof_off;
+  const double* __restrict__ zs = s.z + t.dof_off;
   double u[NE];
 #pragma unroll
   for (int j = 0; j < NE; ++j) {
@@ -220,7 +369,7 @@ __global__ __launch_bounds__(64) void k_elem_plain(GroupDev g, const Tile* __res
     u[j] = v;
   }
   const int cb = g.cell[el];
-  double* __restrict__ sl = s.slots + sd.slot_off;
+  double* __restrict__ sl = s.slots + t.slot_off;
   for (int row = 0; row < NE; ++row) {
     double y = 0.0;
     for (int sc = 0; sc < g.S; ++sc) {
@@ -250,7 +399,7 @@ __global__ __launch_bounds__(BLOCK) void k_sens_mfma(GroupDev g, const Tile* __r
   const Tile t = tiles[g.tile_begin + tix];
   const SysDesc& sd = sys[t.sys];
   const int n = lane & 15, kq = lane >> 4;
-  const double* __restrict__ xs = x + sd.dof_off;
+  const double* __restrict__ xs = x + t.dof_off;
   double u[NC][NJ];
   int cellb[NC];
   bool valid[NC];
@@ -350,26 +499,24 @@ __global__ void k_fill_i32(int32_t* __restrict__ a, int32_t v, int64_t n) {
   if (i < n) a[i] = v;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_dinv(PcgDev s, double* __restrict__ dinv) {
+__global__ __launch_bounds__(VBLOCK) void k_dinv(PcgDev s, double* __restrict__ dinv) {
   const Chunk ch = s.chunks[blockIdx.x];
-  const SysDesc& sd = s.sys[ch.sys];
-  if (sd.load != 0) return;
-  const double* __restrict__ sl = s.slots + sd.slot_off;
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += BLOCK)
-    dinv[sd.inst_free_off + i] = 1.0 / slot_sum(sl, i, sd.nfv, sd.nfe);
+  if (ch.load != 0) return;
+  const double* __restrict__ sl = s.slots + ch.slot_off;
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK)
+    dinv[ch.inst_free_off + i] = 1.0 / slot_sum(sl, i, ch.nfv, ch.nfe);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_init(PcgDev s, int use_slots) {
-  __shared__ double lds[WAVES];
+__global__ __launch_bounds__(VBLOCK) void k_init(PcgDev s, int use_slots) {
+  __shared__ double lds[VWAVES + 4];
   const Chunk ch = s.chunks[blockIdx.x];
-  const SysDesc& sd = s.sys[ch.sys];
-  const int64_t o = sd.dof_off;
-  const double* __restrict__ sl = s.slots + sd.slot_off;
+  const int64_t o = ch.dof_off;
+  const double* __restrict__ sl = s.slots + ch.slot_off;
   double arz = 0.0, arr = 0.0, aff = 0.0;
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += BLOCK) {
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK) {
     const double fi = s.f[o + i];
-    const double ri = use_slots ? fi - slot_sum(sl, i, sd.nfv, sd.nfe) : fi;
-    const double zi = s.dinv[sd.inst_free_off + i] * ri;
+    const double ri = use_slots == 2 ? s.r[o + i] : (use_slots ? fi - slot_sum(sl, i, ch.nfv, ch.nfe) : fi);
+    const double zi = s.dinv[ch.inst_free_off + i] * ri;
     s.r[o + i] = ri;
     s.z[o + i] = zi;
     s.p[o + i] = 0.0;
@@ -377,9 +524,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(PcgDev s, int use_slots) {
     arr = fma(ri, ri, arr);
     aff = fma(fi, fi, aff);
   }
-  arz = block_sum(arz, lds);
-  arr = block_sum(arr, lds);
-  aff = block_sum(aff, lds);
+  arz = block_sum<VWAVES>(arz, lds);
+  arr = block_sum<VWAVES>(arr, lds);
+  aff = block_sum<VWAVES>(aff, lds);
   if (threadIdx.x == 0) {
     s.part_rz[blockIdx.x] = arz;
     s.part_rz[s.n_chunks + blockIdx.x] = 1.0;  // rz of iteration -1: unused (beta_0 = 0)
@@ -403,63 +550,99 @@ __global__ __launch_bounds__(BLOCK) void k_sys_setup(PcgDev s, double rtol2) {
   if (threadIdx.x == 0) *s.it_base = 0;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_dof1(PcgDev s, int it_k) {
-  __shared__ double lds[WAVES];
+// The vector kernels run one free DOF per thread (a chunk is BLOCK DOFs of
+// one system).  Each issues its data loads before reducing the PCG scalars,
+// so the two memory round trips overlap.
+__global__ __launch_bounds__(VBLOCK) void k_dof1(PcgDev s, int it_k) {
+  __shared__ double lds[VWAVES + 4];
   const Chunk ch = s.chunks[blockIdx.x];
-  const SysDesc& sd = s.sys[ch.sys];
+  const int i = ch.begin + threadIdx.x;
+  const bool in = i < ch.end;
+  const int64_t o = ch.dof_off;
+  double qi = 0.0, po = 0.0, zi = 0.0;
+  if (in) {
+    qi = slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
+    po = s.p[o + i];
+    zi = s.z[o + i];
+  }
   const int it = *s.it_base + it_k;
-  const Scal sc = pcg_state(s, ch.sys, it, true);
+  if (threadIdx.x < 64) {
+    const Scal sc = pcg_state(s, ch.sys, ch.pc_begin, ch.pc_end, it, true);
+    if (threadIdx.x == 0) {
+      lds[VWAVES] = sc.beta;
+      lds[VWAVES + 1] = sc.active ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  Scal sc;
+  sc.beta = lds[VWAVES];
+  sc.active = lds[VWAVES + 1] != 0.0;
   if (!sc.active) {
-    if (blockIdx.x == sd.chunk_begin && threadIdx.x == 0 && s.status[ch.sys] == SYS_RUNNING)
+    if (blockIdx.x == ch.pc_begin && threadIdx.x == 0 && s.status[ch.sys] == SYS_RUNNING)
       s.status[ch.sys] = SYS_CONVERGED;
     return;
   }
-  const int64_t o = sd.dof_off;
-  const double* __restrict__ sl = s.slots + sd.slot_off;
   double acc = 0.0;
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += BLOCK) {
-    const double qi = slot_sum(sl, i, sd.nfv, sd.nfe);
-    const double pi = fma(sc.beta, s.p[o + i], s.z[o + i]);
+  if (in) {
+    const double pi = fma(sc.beta, po, zi);
     s.p[o + i] = pi;
     s.q[o + i] = qi;
-    acc = fma(pi, qi, acc);
+    acc = pi * qi;
   }
-  acc = block_sum(acc, lds);
+  acc = block_sum<VWAVES>(acc, lds);
   if (threadIdx.x == 0) s.part_pq[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_dof2(PcgDev s, int it_k) {
-  __shared__ double lds[WAVES];
+__global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
+  __shared__ double lds[VWAVES + 4];
   const Chunk ch = s.chunks[blockIdx.x];
-  const SysDesc& sd = s.sys[ch.sys];
+  const int i = ch.begin + threadIdx.x;
+  const bool in = i < ch.end;
+  const int64_t o = ch.dof_off;
+  double xi = 0.0, pi_ = 0.0, qi = 0.0, ri = 0.0, di = 0.0;
+  if (in) {
+    xi = s.x[o + i];
+    pi_ = s.p[o + i];
+    qi = s.q[o + i];
+    ri = s.r[o + i];
+    di = s.dinv[ch.inst_free_off + i];
+  }
   const int it = *s.it_base + it_k;
-  const Scal sc = pcg_state(s, ch.sys, it, false);
-  if (!sc.active) return;
-  const int pi = it & 1;
-  const double rz = wave_sum(s.part_rz + pi * s.n_chunks, sd.chunk_begin, sd.chunk_end);
-  const double pq = wave_sum(s.part_pq, sd.chunk_begin, sd.chunk_end);
+  const int par = it & 1;
+  if (threadIdx.x < 64) {
+    const Scal sc = pcg_state(s, ch.sys, ch.pc_begin, ch.pc_end, it, false);
+    const double rz = wave_sum(s.part_rz + par * s.n_chunks, ch.pc_begin, ch.pc_end);
+    const double pq = wave_sum(s.part_pq, ch.pc_begin, ch.pc_end);
+    if (threadIdx.x == 0) {
+      lds[VWAVES] = rz;
+      lds[VWAVES + 1] = pq;
+      lds[VWAVES + 2] = sc.active ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  const double rz = lds[VWAVES], pq = lds[VWAVES + 1];
+  if (lds[VWAVES + 2] == 0.0) return;
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
-    if (blockIdx.x == sd.chunk_begin && threadIdx.x == 0) s.status[ch.sys] = SYS_BREAKDOWN;
+    if (blockIdx.x == ch.pc_begin && threadIdx.x == 0) s.status[ch.sys] = SYS_BREAKDOWN;
     return;
   }
   const double alpha = rz / pq;
-  const int64_t o = sd.dof_off;
   double arz = 0.0, arr = 0.0;
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += BLOCK) {
-    s.x[o + i] = fma(alpha, s.p[o + i], s.x[o + i]);
-    const double ri = fma(-alpha, s.q[o + i], s.r[o + i]);
-    const double zi = s.dinv[sd.inst_free_off + i] * ri;
-    s.r[o + i] = ri;
-    s.z[o + i] = zi;
-    arz = fma(ri, zi, arz);
-    arr = fma(ri, ri, arr);
+  if (in) {
+    s.x[o + i] = fma(alpha, pi_, xi);
+    const double rn = fma(-alpha, qi, ri);
+    const double zn = di * rn;
+    s.r[o + i] = rn;
+    s.z[o + i] = zn;
+    arz = rn * zn;
+    arr = rn * rn;
   }
-  arz = block_sum(arz, lds);
-  arr = block_sum(arr, lds);
+  arz = block_sum<VWAVES>(arz, lds);
+  arr = block_sum<VWAVES>(arr, lds);
   if (threadIdx.x == 0) {
-    s.part_rz[(pi ^ 1) * s.n_chunks + blockIdx.x] = arz;
-    s.part_rr[(pi ^ 1) * s.n_chunks + blockIdx.x] = arr;
-    if (blockIdx.x == sd.chunk_begin) s.iters[ch.sys] = it + 1;
+    s.part_rz[(par ^ 1) * s.n_chunks + blockIdx.x] = arz;
+    s.part_rr[(par ^ 1) * s.n_chunks + blockIdx.x] = arr;
+    if (blockIdx.x == ch.pc_begin) s.iters[ch.sys] = it + 1;
   }
 }
 
@@ -490,21 +673,44 @@ __global__ __launch_bounds__(BLOCK) void k_advance(PcgDev s, int G) {
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_residual_partials(PcgDev s) {
-  __shared__ double lds[WAVES];
+// Iterative refinement: the solution is carried as xhi + xlo (double-double)
+// and each PCG cycle's correction x is added exactly, then x restarts at 0.
+__global__ __launch_bounds__(VBLOCK) void k_accumulate(PcgDev s, double* __restrict__ xhi,
+                                                       double* __restrict__ xlo) {
   const Chunk ch = s.chunks[blockIdx.x];
-  const SysDesc& sd = s.sys[ch.sys];
-  const int64_t o = sd.dof_off;
-  const double* __restrict__ sl = s.slots + sd.slot_off;
-  double afx = 0.0, ares = 0.0;
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += BLOCK) {
-    const double fi = s.f[o + i];
-    const double ri = fi - slot_sum(sl, i, sd.nfv, sd.nfe);
-    afx = fma(fi, s.x[o + i], afx);
-    ares = fma(ri, ri, ares);
+  const int64_t o = ch.dof_off;
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK) {
+    const dd_t v = dd_add(dd_t{xhi[o + i], xlo[o + i]}, dd_t{s.x[o + i], 0.0});
+    xhi[o + i] = v.hi;
+    xlo[o + i] = v.lo;
+    s.x[o + i] = 0.0;
   }
-  afx = block_sum(afx, lds);
-  ares = block_sum(ares, lds);
+}
+
+// r = f - K x from double-double slots, rounded once; also writes r into the
+// PCG residual (a restart continues from it) and the partial sums.
+__global__ __launch_bounds__(VBLOCK) void k_residual_dd(PcgDev s, const double* __restrict__ slots_lo,
+                                                        const double* __restrict__ xhi) {
+  __shared__ double lds[VWAVES + 4];
+  const Chunk ch = s.chunks[blockIdx.x];
+  const int64_t o = ch.dof_off;
+  const double* __restrict__ sh = s.slots + ch.slot_off;
+  const double* __restrict__ sl = slots_lo + ch.slot_off;
+  double afx = 0.0, ares = 0.0;
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK) {
+    int64_t base;
+    int cnt;
+    slot_range(i, ch.nfv, ch.nfe, base, cnt);
+    dd_t y{sh[base], sl[base]};
+    for (int k = 1; k < cnt; ++k) y = dd_add(y, dd_t{sh[base + k], sl[base + k]});
+    const double fi = s.f[o + i];
+    const dd_t r = dd_add(dd_t{fi, 0.0}, dd_t{-y.hi, -y.lo});
+    s.r[o + i] = r.hi;
+    afx = fma(fi, xhi[o + i], afx);
+    ares = fma(r.hi, r.hi, ares);
+  }
+  afx = block_sum<VWAVES>(afx, lds);
+  ares = block_sum<VWAVES>(ares, lds);
   if (threadIdx.x == 0) {
     s.part_aux[s.n_chunks + blockIdx.x] = afx;
     s.part_aux[2 * s.n_chunks + blockIdx.x] = ares;
@@ -531,31 +737,53 @@ __global__ __launch_bounds__(BLOCK) void k_compliance(PcgDev s, double* __restri
   if (i < s.n_sys) c[s.sys[i].c_index] = s.sys_out[4 * i + 1];
 }
 
-__global__ __launch_bounds__(BLOCK) void k_assemble_full(PcgDev s, const int32_t* __restrict__ f2f,
+__global__ __launch_bounds__(VBLOCK) void k_assemble_full(PcgDev s, const int32_t* __restrict__ f2f,
                                                         double* __restrict__ y, int diag_mode) {
   const Chunk ch = s.chunks[blockIdx.x];
   const SysDesc& sd = s.sys[ch.sys];
   if (diag_mode && sd.load != 0) return;
   const int64_t yo = diag_mode ? sd.diag_off : sd.u_off;
   const double* __restrict__ sl = s.slots + sd.slot_off;
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += BLOCK)
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK)
     y[yo + f2f[sd.inst_free_off + i]] = slot_sum(sl, i, sd.nfv, sd.nfe);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_gather_free(PcgDev s, const int32_t* __restrict__ f2f,
+__global__ __launch_bounds__(VBLOCK) void k_gather_free(PcgDev s, const int32_t* __restrict__ f2f,
                                                       const double* __restrict__ u, double* __restrict__ xf) {
   const Chunk ch = s.chunks[blockIdx.x];
   const SysDesc& sd = s.sys[ch.sys];
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += BLOCK)
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK)
     xf[sd.dof_off + i] = u[sd.u_off + f2f[sd.inst_free_off + i]];
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scatter_full(PcgDev s, const int32_t* __restrict__ f2f,
+__global__ __launch_bounds__(VBLOCK) void k_scatter_full(PcgDev s, const int32_t* __restrict__ f2f,
                                                        const double* __restrict__ xf, double* __restrict__ u) {
   const Chunk ch = s.chunks[blockIdx.x];
   const SysDesc& sd = s.sys[ch.sys];
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += BLOCK)
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK)
     u[sd.u_off + f2f[sd.inst_free_off + i]] = xf[sd.dof_off + i];
+}
+
+// out[cell] = sum over the instance's load cases l of w[c_index(l)] g[l][cell]
+// (the backward of densities -> compliances).  One thread per cell.
+__global__ __launch_bounds__(BLOCK) void k_weighted_sens(const double* __restrict__ g, const double* __restrict__ w,
+                                                        double* __restrict__ out, const int64_t* __restrict__ inst_cell_off,
+                                                        const int64_t* __restrict__ inst_g_off,
+                                                        const int32_t* __restrict__ inst_c_off,
+                                                        const int32_t* __restrict__ inst_L, int n_inst, int64_t n_cells) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= n_cells) return;
+  int lo = 0, hi = n_inst - 1;  // instance containing the cell
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst_cell_off[mid] <= cell) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t local = cell - inst_cell_off[lo];
+  const int64_t ncell = inst_cell_off[lo + 1] - inst_cell_off[lo];
+  double acc = 0.0;
+  for (int l = 0; l < inst_L[lo]; ++l) acc = fma(w[inst_c_off[lo] + l], g[inst_g_off[lo] + l * ncell + local], acc);
+  out[cell] = acc;
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -567,11 +795,12 @@ void launch_elem_p(const GroupDev& g, int path, int ncol, const Tile* tiles, con
     hipLaunchKernelGGL(k_elem_plain<P>, dim3(g.n_tiles), dim3(64), 0, st, g, tiles, E, xin, s, mode, it_k);
     return;
   }
-  const dim3 grid(nblocks(g.n_tiles, WAVES)), block(BLOCK);
+  const dim3 grid(g.n_tiles), block(64 * g.waves);
+  const size_t lds = elem_lds_bytes(P, ncol, g.waves);
   switch (ncol) {
-    case 1: hipLaunchKernelGGL((k_elem_mfma<P, 1>), grid, block, 0, st, g, tiles, E, xin, s, mode, it_k); break;
-    case 2: hipLaunchKernelGGL((k_elem_mfma<P, 2>), grid, block, 0, st, g, tiles, E, xin, s, mode, it_k); break;
-    default: hipLaunchKernelGGL((k_elem_mfma<P, 4>), grid, block, 0, st, g, tiles, E, xin, s, mode, it_k); break;
+    case 1: hipLaunchKernelGGL((k_elem_mfma<P, 1>), grid, block, lds, st, g, tiles, E, xin, s, mode, it_k); break;
+    case 2: hipLaunchKernelGGL((k_elem_mfma<P, 2>), grid, block, lds, st, g, tiles, E, xin, s, mode, it_k); break;
+    default: hipLaunchKernelGGL((k_elem_mfma<P, 4>), grid, block, lds, st, g, tiles, E, xin, s, mode, it_k); break;
   }
 }
 
@@ -639,11 +868,11 @@ void launch_fill_i32(int32_t* a, int32_t v, int64_t n, hipStream_t st) {
 }
 
 void launch_dinv(const PcgDev& s, double* dinv, hipStream_t st) {
-  hipLaunchKernelGGL(k_dinv, dim3(s.n_chunks), dim3(BLOCK), 0, st, s, dinv);
+  hipLaunchKernelGGL(k_dinv, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, dinv);
 }
 
 void launch_init(const PcgDev& s, int use_slots, hipStream_t st) {
-  hipLaunchKernelGGL(k_init, dim3(s.n_chunks), dim3(BLOCK), 0, st, s, use_slots);
+  hipLaunchKernelGGL(k_init, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, use_slots);
 }
 
 void launch_sys_setup(const PcgDev& s, double rtol, hipStream_t st) {
@@ -651,35 +880,60 @@ void launch_sys_setup(const PcgDev& s, double rtol, hipStream_t st) {
 }
 
 void launch_dof1(const PcgDev& s, int it_k, hipStream_t st) {
-  hipLaunchKernelGGL(k_dof1, dim3(s.n_chunks), dim3(BLOCK), 0, st, s, it_k);
+  hipLaunchKernelGGL(k_dof1, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, it_k);
 }
 
 void launch_dof2(const PcgDev& s, int it_k, hipStream_t st) {
-  hipLaunchKernelGGL(k_dof2, dim3(s.n_chunks), dim3(BLOCK), 0, st, s, it_k);
+  hipLaunchKernelGGL(k_dof2, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, it_k);
 }
 
 void launch_advance(const PcgDev& s, int G, hipStream_t st) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(BLOCK), 0, st, s, G);
 }
 
-void launch_residual(const PcgDev& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual_partials, dim3(s.n_chunks), dim3(BLOCK), 0, st, s);
+void launch_accumulate(const PcgDev& s, double* xhi, double* xlo, hipStream_t st) {
+  hipLaunchKernelGGL(k_accumulate, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, xhi, xlo);
+}
+
+void launch_residual_dd(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
+                        const double* xhi, const double* xlo, double* slots_lo, hipStream_t st) {
+  for (int k = 0; k < n_groups; ++k) {
+    const GroupDev& g = groups[k];
+    if (g.n_tiles == 0) continue;
+    const dim3 grid(g.n_tiles), block(64);
+    switch (g.p) {
+      case 1: hipLaunchKernelGGL(k_elem_dd<1>, grid, block, 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo); break;
+      case 2: hipLaunchKernelGGL(k_elem_dd<2>, grid, block, 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo); break;
+      case 3: hipLaunchKernelGGL(k_elem_dd<3>, grid, block, 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo); break;
+      default: hipLaunchKernelGGL(k_elem_dd<4>, grid, block, 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo); break;
+    }
+  }
+  hipLaunchKernelGGL(k_residual_dd, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, slots_lo, xhi);
   hipLaunchKernelGGL(k_residual_sums, dim3(1), dim3(BLOCK), 0, st, s);
 }
 
+
 void launch_assemble_to_full(const PcgDev& s, const int32_t* free_to_full, double* yfull, int diag_mode,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble_full, dim3(s.n_chunks), dim3(BLOCK), 0, st, s, free_to_full, yfull, diag_mode);
+  hipLaunchKernelGGL(k_assemble_full, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, free_to_full, yfull, diag_mode);
 }
 
 void launch_gather_free(const PcgDev& s, const int32_t* free_to_full, const double* ufull, double* xfree,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_gather_free, dim3(s.n_chunks), dim3(BLOCK), 0, st, s, free_to_full, ufull, xfree);
+  hipLaunchKernelGGL(k_gather_free, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, free_to_full, ufull, xfree);
 }
 
 void launch_scatter_full(const PcgDev& s, const int32_t* free_to_full, const double* xfree, double* ufull,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter_full, dim3(s.n_chunks), dim3(BLOCK), 0, st, s, free_to_full, xfree, ufull);
+  hipLaunchKernelGGL(k_scatter_full, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, free_to_full, xfree, ufull);
+}
+
+void launch_weighted_sens(const double* g, const double* w, double* out, const int64_t* inst_cell_off,
+                          const int64_t* inst_g_off, const int32_t* inst_c_off, const int32_t* inst_L, int n_inst,
+                          int64_t n_cells, hipStream_t st) {
+  if (n_cells == 0) return;
+  hipLaunchKernelGGL(k_weighted_sens, dim3(nblocks(n_cells, BLOCK)), dim3(BLOCK), 0, st, g, w, out, inst_cell_off,
+                     inst_g_off, inst_c_off, inst_L, n_inst, n_cells);
 }
 
 void launch_compliance(const PcgDev& s, double* c, hipStream_t st) {

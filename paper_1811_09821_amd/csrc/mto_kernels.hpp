@@ -13,6 +13,7 @@ struct GroupDev {
   int32_t p, d, S, npad;   // npad: stride of the DOF-major descriptor arrays
   int32_t n_elems;
   int32_t tile_begin, n_tiles, ncol;  // tiles of this group in the tile array
+  int32_t waves;           // waves per tile (density-cell split of the reduction)
   const double* kfrag;     // MFMA A fragments [S*NEP/4][MB][64]
   const double* ks;        // plain K_s [S][ne][ne]
   const double* kdiag;     // diag(K_s) [S][ne]
@@ -49,6 +50,16 @@ struct PcgDev {
 
 enum ElemMode { ELEM_APPLY = 0, ELEM_PCG = 1 };
 
+// Dynamic LDS of the MFMA element kernel: two scalars, then the larger of the
+// gathered tile ([2][NEP][16 ncol] doubles) and the partial products of
+// waves 1..ks-1 ([ks-1][MB * ncol * 4][64] doubles).
+inline size_t elem_lds_bytes(int p, int ncol, int ks) {
+  const size_t gather = 2 * (size_t)nep_of(p) * 16 * ncol;
+  const size_t red = (size_t)(ks - 1) * mb_of(p) * ncol * 4 * 64;
+  return 8 * (2 + (gather > red ? gather : red));
+}
+constexpr size_t ELEM_LDS_LIMIT = 64 * 1024;
+
 // y-slots of K applied to the vector `xin` (ELEM_APPLY) or to the PCG search
 // direction p = z + beta p formed on the fly (ELEM_PCG), for the tiles of one group.
 void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E, const double* xin,
@@ -64,14 +75,19 @@ void launch_fill(double* a, double v, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t* a, int32_t v, int64_t n, hipStream_t st);
 // dinv = 1 / (sum of slots) on the first system of each instance
 void launch_dinv(const PcgDev& s, double* dinv, hipStream_t st);
-// r = f - (assembled slots if use_slots), z = dinv r, p = 0, partials
+// r = f (use_slots 0), f - assembled slots (1) or the r already stored (2);
+// then z = dinv r, p = 0, partials
 void launch_init(const PcgDev& s, int use_slots, hipStream_t st);
 void launch_sys_setup(const PcgDev& s, double rtol, hipStream_t st);
 void launch_dof1(const PcgDev& s, int it_k, hipStream_t st);
 void launch_dof2(const PcgDev& s, int it_k, hipStream_t st);
 void launch_advance(const PcgDev& s, int G, hipStream_t st);
-// |f - assembled slots|^2 and f.x partials, then per-system sums into sys_out
-void launch_residual(const PcgDev& s, hipStream_t st);
+// accurate true residual: double-double element contraction of xhi + xlo,
+// then r = f - K x rounded once into the PCG residual, |r|^2 and f.xhi per system
+void launch_residual_dd(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
+                        const double* xhi, const double* xlo, double* slots_lo, hipStream_t st);
+// (xhi, xlo) += x exactly, then x = 0
+void launch_accumulate(const PcgDev& s, double* xhi, double* xlo, hipStream_t st);
 // assembled slots -> y in the u layout (zeros elsewhere must be pre-filled);
 // diag_mode: only load-0 systems, at their per-instance offset diag_off
 void launch_assemble_to_full(const PcgDev& s, const int32_t* free_to_full, double* yfull, int diag_mode,
@@ -82,5 +98,9 @@ void launch_gather_free(const PcgDev& s, const int32_t* free_to_full, const doub
 void launch_scatter_full(const PcgDev& s, const int32_t* free_to_full, const double* xfree, double* ufull,
                          hipStream_t st);
 void launch_compliance(const PcgDev& s, double* c, hipStream_t st);
+// out = sum_l w_l g_l per instance (inst_cell_off has n_inst + 1 entries)
+void launch_weighted_sens(const double* g, const double* w, double* out, const int64_t* inst_cell_off,
+                          const int64_t* inst_g_off, const int32_t* inst_c_off, const int32_t* inst_L, int n_inst,
+                          int64_t n_cells, hipStream_t st);
 
 }  // namespace mto

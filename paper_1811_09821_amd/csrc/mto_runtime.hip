@@ -36,7 +36,7 @@ int fail(int code, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                       \
   } while (0)
 
-constexpr int CHUNK = 2048;  // free DOFs per vector-kernel block
+constexpr int CHUNK = 1024;  // free DOFs per vector-kernel block (one per thread)
 
 struct DevBuf {
   void* ptr = nullptr;
@@ -47,7 +47,7 @@ struct DevBuf {
 
 struct GroupHost {
   int p = 0, d = 0, S = 0, ne = 0, nep = 0, mb = 0;
-  int n_elems = 0, npad = 0, ncol = 4;
+  int n_elems = 0, npad = 0, ncol = 1, waves = 1;
   // per instance: element range [inst_begin[i], inst_begin[i+1]) in the group arrays
   std::vector<int32_t> inst_begin;
   double* kfrag = nullptr;
@@ -82,10 +82,14 @@ struct mto_plan {
   double *E = nullptr, *dE = nullptr;
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *f = nullptr, *dinv = nullptr;
   double* slots = nullptr;
+  double* slots_lo = nullptr;  // low parts of the double-double residual contraction
+  double *xs_hi = nullptr, *xs_lo = nullptr;  // refined solution, double-double
   double *part_pq = nullptr, *part_rz = nullptr, *part_rr = nullptr, *part_aux = nullptr;
   int32_t *status = nullptr, *iters = nullptr, *it_base = nullptr, *n_active = nullptr;
   double *tol2 = nullptr, *sys_out = nullptr;
   int32_t* f2f = nullptr;
+  int64_t *d_inst_cell_off = nullptr, *d_inst_g_off = nullptr;  // [n_inst + 1], [n_inst]
+  int32_t *d_inst_c_off = nullptr, *d_inst_L = nullptr;
   // host pinned
   int32_t* h_active = nullptr;  // [2]
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -135,6 +139,7 @@ struct mto_plan {
     o.tile_begin = g.tile_begin;
     o.n_tiles = g.n_tiles;
     o.ncol = g.ncol;
+    o.waves = g.waves;
     o.kfrag = g.kfrag;
     o.ks = g.ks;
     o.kdiag = g.kdiag;
@@ -191,8 +196,19 @@ int rebuild_tiles(mto_plan* P) {
         int sysi = 0;
         for (int k = 0; k < i; ++k) sysi += P->L[k];
         sysi += l;
-        for (int e = a; e < b; e += tile_cols)
-          P->tiles.push_back(Tile{(int32_t)gi, sysi, e, std::min(tile_cols, b - e)});
+        const SysDesc& sd = P->sys[sysi];
+        for (int e = a; e < b; e += tile_cols) {
+          Tile t{};
+          t.dof_off = sd.dof_off;
+          t.slot_off = sd.slot_off;
+          t.group = (int32_t)gi;
+          t.sys = sysi;
+          t.elem_begin = e;
+          t.count = std::min(tile_cols, b - e);
+          t.pc_begin = sd.chunk_begin;
+          t.pc_end = sd.chunk_end;
+          P->tiles.push_back(t);
+        }
       }
     }
     g.n_tiles = (int)P->tiles.size() - g.tile_begin;
@@ -238,7 +254,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
   P->prm = *prm;
   if (P->prm.iters_per_launch <= 0) P->prm.iters_per_launch = 32;
   if (P->prm.iters_per_launch % 2) P->prm.iters_per_launch += 1;  // keeps the parity of it_base even
-  if (P->prm.max_restarts < 0) P->prm.max_restarts = 2;
+  if (P->prm.max_restarts < 0) P->prm.max_restarts = 3;
   (void)hipGetDevice(&P->device);
   P->n_inst = n;
   auto cleanup = [&](int rc) {
@@ -288,9 +304,24 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       sd.load = l;
       sd.c_index = (int32_t)(P->c_off[i] + l);
       sd.chunk_begin = (int32_t)P->chunks.size();
-      for (int b = 0; b < I[i].n_free; b += CHUNK)
-        P->chunks.push_back(Chunk{(int32_t)P->sys.size(), b, std::min(I[i].n_free, b + CHUNK), 0});
+      for (int b = 0; b < I[i].n_free; b += CHUNK) {
+        Chunk ch{};
+        ch.dof_off = sd.dof_off;
+        ch.slot_off = sd.slot_off;
+        ch.inst_free_off = sd.inst_free_off;
+        ch.sys = (int32_t)P->sys.size();
+        ch.begin = b;
+        ch.end = std::min(I[i].n_free, b + CHUNK);
+        ch.nfv = sd.nfv;
+        ch.nfe = sd.nfe;
+        ch.load = l;
+        P->chunks.push_back(ch);
+      }
       sd.chunk_end = (int32_t)P->chunks.size();
+      for (int k = sd.chunk_begin; k < sd.chunk_end; ++k) {
+        P->chunks[k].pc_begin = sd.chunk_begin;
+        P->chunks[k].pc_end = sd.chunk_end;
+      }
       P->sys.push_back(sd);
       vec_acc += I[i].n_free;
       slot_acc += I[i].n_slots;
@@ -322,7 +353,8 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     g.ne = ne_of(g.p);
     g.nep = nep_of(g.p);
     g.mb = mb_of(g.p);
-    g.ncol = g.p >= 4 ? 2 : 4;
+    g.ncol = 1;
+    g.waves = std::min(4, g.S);
   }
   // order groups by (p, d) for stable output
   for (int gi = 0; gi < (int)P->groups.size(); ++gi) {
@@ -381,6 +413,8 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_alloc(P, &P->z, P->n_vec)) || (rc = dev_alloc(P, &P->p, P->n_vec)) ||
       (rc = dev_alloc(P, &P->q, P->n_vec)) || (rc = dev_upload(P, &P->f, fh)) ||
       (rc = dev_alloc(P, &P->dinv, P->n_free_inst_tot)) || (rc = dev_alloc(P, &P->slots, P->n_slots_tot)) ||
+      (rc = dev_alloc(P, &P->slots_lo, P->n_slots_tot)) || (rc = dev_alloc(P, &P->xs_hi, P->n_vec)) ||
+      (rc = dev_alloc(P, &P->xs_lo, P->n_vec)) ||
       (rc = dev_alloc(P, &P->part_pq, nch)) || (rc = dev_alloc(P, &P->part_rz, 2 * nch)) ||
       (rc = dev_alloc(P, &P->part_rr, 2 * nch)) || (rc = dev_alloc(P, &P->part_aux, 3 * nch)) ||
       (rc = dev_alloc(P, &P->status, P->n_sys)) || (rc = dev_alloc(P, &P->iters, P->n_sys)) ||
@@ -388,8 +422,18 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_alloc(P, &P->tol2, P->n_sys)) || (rc = dev_alloc(P, &P->sys_out, 4 * (size_t)P->n_sys)) ||
       (rc = dev_upload(P, &P->f2f, f2f)))
     return cleanup(rc);
+  {
+    std::vector<int64_t> co(P->cell_off), go(P->g_off);
+    co.push_back(P->n_cells_tot);
+    std::vector<int32_t> cc(n), ll(P->L);
+    for (int i = 0; i < n; ++i) cc[i] = (int32_t)P->c_off[i];
+    if ((rc = dev_upload(P, &P->d_inst_cell_off, co)) || (rc = dev_upload(P, &P->d_inst_g_off, go)) ||
+        (rc = dev_upload(P, &P->d_inst_c_off, cc)) || (rc = dev_upload(P, &P->d_inst_L, ll)))
+      return cleanup(rc);
+  }
   // slots that no element writes (missing neighbours) must read as zero forever
   launch_fill(P->slots, 0.0, P->n_slots_tot, 0);
+  launch_fill(P->slots_lo, 0.0, P->n_slots_tot, 0);
   launch_fill(P->x, 0.0, P->n_vec, 0);
   if ((rc = check_launch("fill"))) return cleanup(rc);
   if (hipHostMalloc((void**)&P->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
@@ -412,17 +456,22 @@ void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_
   for (auto& g : P->groups) launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, xin, s, mode, it_k, st);
 }
 
+void enq_residual(mto_plan* P, hipStream_t st);
+
 void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st) {
   const PcgDev s = P->pcg();
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
   for (auto& g : P->groups) launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, st);
   launch_dinv(s, P->dinv, st);
+  // PCG iterates on the correction x (from 0); the solution is xs_hi + xs_lo
+  launch_fill(P->x, 0.0, P->n_vec, st);
+  launch_fill(P->xs_lo, 0.0, P->n_vec, st);
   if (u0) {
-    launch_gather_free(s, P->f2f, u0, P->x, st);
-    enq_elem_all(P, P->x, ELEM_APPLY, 0, st);
-    launch_init(s, 1, st);
+    launch_gather_free(s, P->f2f, u0, P->xs_hi, st);
+    enq_residual(P, st);
+    launch_init(s, 2, st);
   } else {
-    launch_fill(P->x, 0.0, P->n_vec, st);
+    launch_fill(P->xs_hi, 0.0, P->n_vec, st);
     launch_init(s, 0, st);
   }
   launch_sys_setup(s, P->prm.rtol, st);
@@ -438,14 +487,25 @@ void enq_chunk(mto_plan* P, int G, hipStream_t st) {
   launch_advance(s, G, st);
 }
 
+// True residual f - K x in double-double (then rounded): the FP64 product
+// K x cannot resolve residuals below about eps || |K| |x| ||, which for the
+// contrast E_min / E0 = 1e-9 lies above 1e-11 || f ||.
 void enq_residual(mto_plan* P, hipStream_t st) {
-  enq_elem_all(P, P->x, ELEM_APPLY, 0, st);
-  launch_residual(P->pcg(), st);
+  std::vector<GroupDev> gd;
+  for (auto& g : P->groups) gd.push_back(P->gdev(g));
+  launch_residual_dd(gd.data(), (int)gd.size(), P->d_tiles, P->E, P->pcg(), P->xs_hi, P->xs_lo, P->slots_lo, st);
 }
 
+// End of a PCG cycle: fold the correction into the refined solution, then
+// the accurate residual of the result.
+void enq_cycle_end(mto_plan* P, hipStream_t st) {
+  launch_accumulate(P->pcg(), P->xs_hi, P->xs_lo, st);
+  enq_residual(P, st);
+}
+
+// Iterative refinement: PCG continues from x with the accurate residual.
 void enq_restart(mto_plan* P, hipStream_t st) {
-  // slots hold K x from the residual step
-  launch_init(P->pcg(), 1, st);
+  launch_init(P->pcg(), 2, st);
   launch_sys_setup(P->pcg(), P->prm.rtol, st);
 }
 
@@ -453,9 +513,9 @@ void enq_outputs(mto_plan* P, double* u, double* c, double* g, hipStream_t st) {
   const PcgDev s = P->pcg();
   launch_compliance(s, c, st);
   launch_fill(u, 0.0, P->n_u, st);
-  launch_scatter_full(s, P->f2f, P->x, u, st);
+  launch_scatter_full(s, P->f2f, P->xs_hi, u, st);
   if (g)
-    for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->x, g, P->d_sys, st);
+    for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->xs_hi, g, P->d_sys, st);
 }
 
 int capture(mto_plan* P, hipGraphExec_t* exec, const std::function<void(hipStream_t)>& body) {
@@ -550,7 +610,7 @@ int run_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, c
     if (graphs) {
       HIP_TRY(hipGraphLaunch(P->resid_exec, st));
     } else {
-      enq_residual(P, st);
+      enq_cycle_end(P, st);
       if ((rc = check_launch("residual"))) return rc;
     }
     if ((rc = fetch(P, st, R))) return rc;
@@ -677,7 +737,7 @@ int mto_batch_capture(mto_plan* P, const double* rho, double* u, double* c, doub
   (void)stream;
   int rc;
   if ((rc = capture(P, &P->setup_exec, [&](hipStream_t st) { enq_setup(P, rho, nullptr, st); }))) return rc;
-  if ((rc = capture(P, &P->resid_exec, [&](hipStream_t st) { enq_residual(P, st); }))) return rc;
+  if ((rc = capture(P, &P->resid_exec, [&](hipStream_t st) { enq_cycle_end(P, st); }))) return rc;
   if ((rc = capture(P, &P->restart_exec, [&](hipStream_t st) { enq_restart(P, st); }))) return rc;
   if ((rc = capture(P, &P->out_exec, [&](hipStream_t st) { enq_outputs(P, u, c, g, st); }))) return rc;
   if ((rc = ensure_chunk_graph(P))) return rc;
@@ -734,11 +794,25 @@ int mto_jacobi_diagonal(mto_plan* P, const double* rho, double* diag, void* stre
   return check_launch("jacobi_diagonal");
 }
 
-int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol) {
+int mto_weighted_sensitivity(mto_plan* P, const double* g, const double* w, double* out, void* stream) {
   g_err.clear();
-  if (!P || (ncol != 1 && ncol != 2 && ncol != 4)) return fail(MTO_EINVAL, "ncol must be 1, 2 or 4");
+  if (!P || !g || !w || !out) return fail(MTO_EINVAL, "NULL argument");
+  launch_weighted_sens(g, w, out, P->d_inst_cell_off, P->d_inst_g_off, P->d_inst_c_off, P->d_inst_L, P->n_inst,
+                       P->n_cells_tot, (hipStream_t)stream);
+  return check_launch("weighted_sensitivity");
+}
+
+int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol, int32_t ks) {
+  g_err.clear();
+  if (!P || (ncol != 1 && ncol != 2 && ncol != 4) || ks < 1 || ks > 8)
+    return fail(MTO_EINVAL, "ncol must be 1, 2 or 4 and ks 1..8");
   for (auto& g : P->groups)
-    if (p <= 0 || (g.p == p && g.d == d)) g.ncol = ncol;
+    if (p <= 0 || (g.p == p && g.d == d)) {
+      const int k = std::min<int>(ks, g.S);
+      if (elem_lds_bytes(g.p, ncol, k) > ELEM_LDS_LIMIT) return fail(MTO_EINVAL, "tile shape exceeds the LDS limit");
+      g.ncol = ncol;
+      g.waves = k;
+    }
   return rebuild_tiles(P);
 }
 
@@ -753,35 +827,42 @@ int mto_autotune(mto_plan* P, const double* rho, void* stream, char* report, int
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   std::string rep;
-  const int cand[3] = {1, 2, 4};
+  const int cand_nc[3] = {1, 2, 4};
+  const int cand_ks[4] = {1, 2, 4, 8};
   for (auto& g : P->groups) {
     double best = 1e30;
-    int best_nc = g.ncol;
-    for (int nc : cand) {
-      g.ncol = nc;
-      int rc = rebuild_tiles(P);
-      if (rc) return rc;
-      const GroupDev gd = P->gdev(g);
-      const PcgDev s = P->pcg();
-      for (int w = 0; w < 3; ++w) launch_elem(gd, P->prm.kernel_path, P->d_tiles, P->E, P->q, s, ELEM_APPLY, 0, st);
-      const int reps = 20;
-      HIP_TRY(hipEventRecord(e0, st));
-      for (int w = 0; w < reps; ++w) launch_elem(gd, P->prm.kernel_path, P->d_tiles, P->E, P->q, s, ELEM_APPLY, 0, st);
-      HIP_TRY(hipEventRecord(e1, st));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      const double t = ms / reps;
-      char line[160];
-      snprintf(line, sizeof line, "p=%d d=%d ncol=%d: %.3f us (%.1f GF/s)\n", g.p, g.d, nc, 1e3 * t,
-               g.flops / (t * 1e6));
-      rep += line;
-      if (t < best) {
-        best = t;
-        best_nc = nc;
+    int best_nc = g.ncol, best_ks = g.waves;
+    for (int nc : cand_nc)
+      for (int ks : cand_ks) {
+        if (ks > g.S || elem_lds_bytes(g.p, nc, ks) > ELEM_LDS_LIMIT) continue;
+        if (g.p >= 3 && nc == 4) continue;  // register spills
+        g.ncol = nc;
+        g.waves = ks;
+        int rc = rebuild_tiles(P);
+        if (rc) return rc;
+        const GroupDev gd = P->gdev(g);
+        const PcgDev s = P->pcg();
+        for (int w = 0; w < 3; ++w) launch_elem(gd, P->prm.kernel_path, P->d_tiles, P->E, P->q, s, ELEM_APPLY, 0, st);
+        const int reps = 20;
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int w = 0; w < reps; ++w) launch_elem(gd, P->prm.kernel_path, P->d_tiles, P->E, P->q, s, ELEM_APPLY, 0, st);
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        const double t = ms / reps;
+        char line[160];
+        snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=%d: %.3f us (%.1f GF/s)\n", g.p, g.d, nc, ks, 1e3 * t,
+                 g.flops / (t * 1e6));
+        rep += line;
+        if (t < best) {
+          best = t;
+          best_nc = nc;
+          best_ks = ks;
+        }
       }
-    }
     g.ncol = best_nc;
+    g.waves = best_ks;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -86,8 +86,9 @@ def _load():
         "mto_apply_stiffness": ([vp, vp, vp, vp, vp], i32),
         "mto_sensitivity": ([vp, vp, vp, vp, vp], i32),
         "mto_jacobi_diagonal": ([vp, vp, vp, vp], i32),
+        "mto_weighted_sensitivity": ([vp, vp, vp, vp, vp], i32),
         "mto_autotune": ([vp, vp, vp, ctypes.c_char_p, i32], i32),
-        "mto_set_tile": ([vp, i32, i32, i32], i32),
+        "mto_set_tile": ([vp, i32, i32, i32, i32], i32),
         "mto_time_contraction": ([vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "mto_plan_destroy": ([vp], None),
     }
@@ -101,7 +102,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("mto_last_error", "mto_version", "mto_plan_create", "mto_batch_plan_create", "mto_plan_info",
             "mto_instance_info", "mto_solve", "mto_batch_capture", "mto_batch_replay", "mto_apply_stiffness",
-            "mto_sensitivity", "mto_jacobi_diagonal", "mto_autotune", "mto_set_tile", "mto_time_contraction",
+            "mto_sensitivity", "mto_jacobi_diagonal", "mto_weighted_sensitivity", "mto_autotune", "mto_set_tile", "mto_time_contraction",
             "mto_plan_destroy")
 
 
@@ -149,7 +150,7 @@ def _f64_cuda(t, n, name):
 
 def default_params(**kw):
     prm = dict(E0=1.0, Emin=1e-9, nu=0.3, q=3.0, rtol=1e-11, max_iter=0, kernel_path=PATH_MFMA,
-               iters_per_launch=32, max_restarts=2)
+               iters_per_launch=32, max_restarts=3)
     prm.update(kw)
     return prm
 
@@ -279,6 +280,14 @@ class Plan:
         _check(_lib.mto_sensitivity(self.handle, _ptr(rho), _ptr(u), _ptr(g), _stream(stream)))
         return g
 
+    def weighted_sensitivity(self, g, w, stream=None):
+        """sum_l w_l dc_l/drho per instance (backward of rho -> c)."""
+        _f64_cuda(g, self.info["n_g"], "g")
+        _f64_cuda(w, self.n_c, "w")
+        out = self._empty(self.info["n_cells"], g)
+        _check(_lib.mto_weighted_sensitivity(self.handle, _ptr(g), _ptr(w), _ptr(out), _stream(stream)))
+        return out
+
     def jacobi_diagonal(self, rho, stream=None):
         _f64_cuda(rho, self.info["n_cells"], "rho")
         n = sum(r["n_dof"] for r in self.instances)
@@ -300,8 +309,8 @@ class Plan:
         _check(_lib.mto_time_contraction(self.handle, _ptr(rho), int(reps), _stream(stream), ctypes.byref(ms)))
         return ms.value
 
-    def set_tile(self, ncol, p=0, d=0):
-        _check(_lib.mto_set_tile(self.handle, int(p), int(d), int(ncol)))
+    def set_tile(self, ncol, ks=1, p=0, d=0):
+        _check(_lib.mto_set_tile(self.handle, int(p), int(d), int(ncol), int(ks)))
         self._bound = None
 
     # -- layout helpers --

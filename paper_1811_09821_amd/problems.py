@@ -17,10 +17,13 @@ cell centres, so it does not depend on d.
 
 Density map: rho = clip(0.5 + 0.5 z - t, rho_min, 1) with the shift t found
 by bisection so that the area-weighted mean density equals the volume
-fraction.
+fraction; cells on the load paths are solid (rho = 1): a pad of radius
+LOAD_PAD around each point load and a beam of half-width BEAM_HALF_WIDTH from
+the clamped edge to it, as the paper's optimised designs carry every load
+through material to the supports.
 
 dp rule for mixed meshes (an element is 'solid' when z at its centre >= 0,
-i.e. the [0, 1]-mapped field is >= 0.5): elements whose centre lies within 3
+i.e. the [0, 1]-mapped field is >= 0.5, or it lies on a load path): elements whose centre lies within 3
 element widths of an element on the solid/void contour (one with a
 4-neighbour of the other class) get p = 4, d = 5; other solid elements get
 p = 2, d = 2 and other void elements p = 1, d = 1.  Then neighbouring orders
@@ -38,6 +41,10 @@ SUP_VERTEX, SUP_EDGE_LEFT, SUP_EDGE_RIGHT, SUP_EDGE_BOTTOM, SUP_EDGE_TOP = 0, 1,
 # Gaussian smoothing length (element widths) of the mixed-mesh configs; fixed
 # once so that about a fifth of a 200 x 100 mesh is refined.
 MIXED_SIGMA = 12.0
+# Radius (element widths) of the solid pad around each point load, and the
+# half-width of the solid beam that joins each load to the clamped edge.
+LOAD_PAD = 2.0
+BEAM_HALF_WIDTH = 2.0
 
 
 @dataclass
@@ -126,23 +133,39 @@ def cell_centres(nelx, nely, d):
     return xs, ys, ws
 
 
-def map_density(z, weights, volfrac, rho_min=1e-3):
-    """rho = clip(0.5 + 0.5 z - t, rho_min, 1), t by bisection on the mean."""
+def map_density(z, weights, volfrac, rho_min=1e-3, solid=None):
+    """rho = clip(0.5 + 0.5 z - t, rho_min, 1) (1 on the `solid` mask), with
+    t by bisection so that the area-weighted mean is volfrac."""
     wsum = weights.sum()
+    if solid is None:
+        solid = np.zeros(z.shape, dtype=bool)
 
-    def mean(t):
-        return float(np.dot(np.clip(0.5 + 0.5 * z - t, rho_min, 1.0), weights) / wsum)
+    def field(t):
+        return np.where(solid, 1.0, np.clip(0.5 + 0.5 * z - t, rho_min, 1.0))
 
     lo, hi = -10.0, 10.0
     for _ in range(200):
         mid = 0.5 * (lo + hi)
-        if mean(mid) > volfrac:
+        if float(np.dot(field(mid), weights) / wsum) > volfrac:
             lo = mid
         else:
             hi = mid
         if hi - lo < 1e-13:
             break
-    return np.clip(0.5 + 0.5 * z - 0.5 * (lo + hi), rho_min, 1.0)
+    return field(0.5 * (lo + hi))
+
+
+def load_paths(x, y, loads, pad=LOAD_PAD, half_width=BEAM_HALF_WIDTH):
+    """Solid mask at points (x, y): a pad of radius `pad` around each loaded
+    vertex and a horizontal beam of half-width `half_width` from the clamped
+    edge x = 0 to it.  The paper's optimised designs carry every load through
+    material to the supports; a random field alone at a low volume fraction
+    leaves the loads on void (E = Emin) with compliances of order 1e9."""
+    solid = np.zeros(np.shape(x), dtype=bool)
+    for vx, vy, *_ in loads:
+        solid |= (x - vx) ** 2 + (y - vy) ** 2 <= pad * pad
+        solid |= (np.abs(y - vy) <= half_width) & (x <= vx)
+    return solid
 
 
 def smooth_orders(p, nelx, nely, max_jump=2):
@@ -163,12 +186,14 @@ def smooth_orders(p, nelx, nely, max_jump=2):
             return p.ravel()
 
 
-def dp_rule(nelx, nely, fieldfn, band=3.0):
-    """Per-element (p, d) of the mixed-mesh configs (see the module docstring)."""
+def dp_rule(nelx, nely, fieldfn, band=3.0, loads=()):
+    """Per-element (p, d) of the mixed-mesh configs (see the module docstring);
+    elements on the load paths count as solid."""
     from scipy import ndimage
 
     ex, ey = np.meshgrid(np.arange(nelx) + 0.5, np.arange(nely) + 0.5)
-    solid = (fieldfn(ex.ravel(), ey.ravel()) >= 0.0).reshape(nely, nelx)
+    solid = (fieldfn(ex.ravel(), ey.ravel()) >= 0.0) | load_paths(ex.ravel(), ey.ravel(), loads)
+    solid = solid.reshape(nely, nelx)
     contour = np.zeros_like(solid)
     contour[:, :-1] |= solid[:, :-1] != solid[:, 1:]
     contour[:, 1:] |= solid[:, :-1] != solid[:, 1:]
@@ -211,8 +236,8 @@ def cantilever_uniform(nelx=160, nely=80, p=3, d=4, sigma=8.0, volfrac=0.4, seed
     da = np.full(nelx * nely, d, np.int8)
     fld = RandomField(seed, sigma, nelx, nely)
     x, y, w = cell_centres(nelx, nely, da)
-    rho = map_density(fld(x, y), w, volfrac)
     loads = [(nelx, nely // 2, 0.0, -1.0, 0)]
+    rho = map_density(fld(x, y), w, volfrac, solid=load_paths(x, y, loads))
     return Problem(f"cantilever{nelx}x{nely}_p{p}d{d}", nelx, nely, pa, da, rho,
                    cantilever_supports(), loads, 1)
 
@@ -221,12 +246,12 @@ def mixed_cantilever(nelx=200, nely=100, volfrac=0.5, seed=3, load_vy=None, sigm
     """Clamped-left cantilever on a dp-mixed mesh from the dp rule; point loads
     f_y = -1 at the given right-edge vertices (one load case each)."""
     fld = RandomField(seed, sigma, nelx, nely)
-    p, d = dp_rule(nelx, nely, fld)
-    x, y, w = cell_centres(nelx, nely, d)
-    rho = map_density(fld(x, y), w, volfrac)
     if load_vy is None:
         load_vy = [nely // 2]
     loads = [(nelx, int(vy), 0.0, -1.0, lc) for lc, vy in enumerate(load_vy)]
+    p, d = dp_rule(nelx, nely, fld, loads=loads)
+    x, y, w = cell_centres(nelx, nely, d)
+    rho = map_density(fld(x, y), w, volfrac, solid=load_paths(x, y, loads))
     return Problem(f"mixed{nelx}x{nely}", nelx, nely, p, d, rho, cantilever_supports(), loads,
                    len(load_vy))
 

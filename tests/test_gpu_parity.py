@@ -79,7 +79,7 @@ GROUPS = [(p, d) for p in (1, 2, 3, 4) for d in (1, 2, 3, 4, 5)]
 def test_matvec_every_group(cuda, p, d):
     """y = K x (element contraction + slot assembly) for all 20 (p, d) groups,
     on a 7 x 5 mesh (35 elements: several 16-column tiles and a ragged tail)
-    with each tile width."""
+    with several tile widths and density-cell splits across waves."""
     pr = P.uniform_random(7, 5, p, d, seed=100 + 10 * p + d)
     K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
     free = free_mask(space, pr.supports)
@@ -90,10 +90,10 @@ def test_matvec_every_group(cuda, p, d):
     plan = mto().Plan(pr)
     rho = torch.tensor(pr.rho, device=cuda)
     xt = torch.tensor(x, device=cuda)
-    for ncol in (1, 2, 4):
-        plan.set_tile(ncol)
+    for ncol, ks in ((1, 1), (2, 2), (1, 4), (4, 1), (1, 8)):
+        plan.set_tile(ncol, ks)
         y = plan.apply_stiffness(rho, xt).cpu().numpy()
-        assert rel(y, yref) < 1e-13, (p, d, ncol, rel(y, yref))
+        assert rel(y, yref) < 1e-13, (p, d, ncol, ks, rel(y, yref))
 
 
 @pytest.mark.parametrize("path", [0, 1])
