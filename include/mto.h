@@ -82,6 +82,13 @@ enum { /* element contraction kernels */
   MTO_PATH_PLAIN = 1  /* one thread per element column, FP64 VALU (comparison path) */
 };
 
+enum { /* PCG preconditioners */
+  MTO_PRECOND_JACOBI = 0, /* diagonal of K (default) */
+  MTO_PRECOND_MG = 1      /* one multigrid V-cycle: hierarchic-order injection to the bilinear
+                             vertex grid, then geometric coarsening with Galerkin operators,
+                             l1-Jacobi smoothing, dense coarsest solve */
+};
+
 typedef struct {
   int32_t nelx, nely;
   const int8_t* p; /* host [nelx*nely], order per element */
@@ -110,6 +117,9 @@ typedef struct {
   int32_t kernel_path;      /* MTO_PATH_* */
   int32_t iters_per_launch; /* PCG iterations per captured graph launch (<= 0: 32) */
   int32_t max_restarts;     /* refinement restarts from the true residual when it misses rtol (< 0: 3) */
+  int32_t precond;          /* MTO_PRECOND_* */
+  double mg_omega;          /* multigrid level-0 smoother: damped Jacobi with this factor if > 0,
+                               else l1-Jacobi */
 } mto_params;
 
 typedef struct {

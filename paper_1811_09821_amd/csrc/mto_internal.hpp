@@ -98,4 +98,39 @@ struct SysDesc {
   int32_t c_index;     // index into c
 };
 
+// ---- geometric multigrid preconditioner (levels >= 1: vertex grids) ----
+
+constexpr int MG_CHUNK = 256;      // nodes per level-kernel block
+constexpr int MG_COARSE_MAX = 256; // DOFs of the coarsest grid (dense inverse)
+
+// Work unit of the level kernels: nodes [node_begin, node_end) of the level
+// grid of one system (vector kernels) or one instance (operator kernels; sys
+// is then -1).  Offsets are in nodes (vectors hold 2 DOFs per node, operators
+// 36 doubles per node: nine 2 x 2 blocks).
+struct MgChunk {
+  int64_t vec, op;      // this level: system vector / instance operator node offsets
+  int64_t fvec, fop;    // finer level (level >= 2)
+  int64_t cvec, cop;    // coarser level (absent at the coarsest: -1)
+  int64_t dense_off;    // coarsest level: offset of the instance's dense inverse
+  int64_t dof_off;      // level 1 only: the system's level-0 offsets
+  int64_t slot_off;
+  int64_t elem_off;     // level 1 only: the instance's first element in the MgElem table
+  int32_t sys, inst;
+  int32_t node_begin, node_end;
+  int32_t nx, ny;       // this grid (elements per side)
+  int32_t fnx, fny;     // finer grid (level >= 2)
+  int32_t cnx, cny;     // coarser grid
+  int32_t nfv, nfe;     // level 1 only: level-0 slot layout
+  int32_t level;
+  int32_t pad;
+};
+
+// Per instance element data for the level-1 (vertex-grid) assembly.
+struct MgElem {
+  int32_t cell_off;     // first density cell (global)
+  int32_t kv_off;       // offset of its group's vertex-block table [S][4][4][2][2]
+  int32_t S;
+  int32_t pad;
+};
+
 }  // namespace mto

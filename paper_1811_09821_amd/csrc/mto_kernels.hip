@@ -209,6 +209,7 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
   const int ks = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Tile t = tiles[g.tile_begin + blockIdx.x];
+  if (mode == ELEM_APPLY_RUNNING && s.status[t.sys] != SYS_RUNNING) return;
   const bool pcg = mode == ELEM_PCG;
   if (pcg && wave == 0) {
     const Scal sc = pcg_state(s, t.sys, t.pc_begin, t.pc_end, *s.it_base + it_k, true);
@@ -349,6 +350,7 @@ __global__ __launch_bounds__(64) void k_elem_plain(GroupDev g, const Tile* __res
   const int tix = blockIdx.x;
   if (tix >= g.n_tiles) return;
   const Tile t = tiles[g.tile_begin + tix];
+  if (mode == ELEM_APPLY_RUNNING && s.status[t.sys] != SYS_RUNNING) return;
   double beta = 0.0;
   if (mode == ELEM_PCG) {
     const Scal sc = pcg_state(s, t.sys, t.pc_begin, t.pc_end, *s.it_base + it_k, true);
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_sens_mfma(GroupDev g, const Tile* __r
 template <int P>
 __global__ __launch_bounds__(64) void k_diag_elem(GroupDev g, const Tile* __restrict__ tiles,
                                                  const double* __restrict__ E, double* __restrict__ slots,
-                                                 const SysDesc* __restrict__ sys) {
+                                                 const SysDesc* __restrict__ sys, const double* __restrict__ table) {
   constexpr int NE = ne_of(P);
   const int tix = blockIdx.x;
   if (tix >= g.n_tiles) return;
@@ -472,7 +474,7 @@ __global__ __launch_bounds__(64) void k_diag_elem(GroupDev g, const Tile* __rest
   double* __restrict__ sl = slots + sd.slot_off;
   for (int row = 0; row < NE; ++row) {
     double dsum = 0.0;
-    for (int sc = 0; sc < g.S; ++sc) dsum = fma(E[cb + sc], g.kdiag[sc * NE + row], dsum);
+    for (int sc = 0; sc < g.S; ++sc) dsum = fma(E[cb + sc], table[sc * NE + row], dsum);
     const int si = g.sidx[row * g.npad + el];
     if (si >= 0) sl[si] = dsum;
   }
@@ -499,12 +501,12 @@ __global__ void k_fill_i32(int32_t* __restrict__ a, int32_t v, int64_t n) {
   if (i < n) a[i] = v;
 }
 
-__global__ __launch_bounds__(VBLOCK) void k_dinv(PcgDev s, double* __restrict__ dinv) {
+__global__ __launch_bounds__(VBLOCK) void k_dinv(PcgDev s, double* __restrict__ dinv, double scale) {
   const Chunk ch = s.chunks[blockIdx.x];
   if (ch.load != 0) return;
   const double* __restrict__ sl = s.slots + ch.slot_off;
   for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK)
-    dinv[ch.inst_free_off + i] = 1.0 / slot_sum(sl, i, ch.nfv, ch.nfe);
+    dinv[ch.inst_free_off + i] = scale / slot_sum(sl, i, ch.nfv, ch.nfe);
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_init(PcgDev s, int use_slots) {
@@ -840,14 +842,14 @@ void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const d
 }
 
 void launch_diag_elem(const GroupDev& g, const Tile* tiles, const double* E, double* slots, const SysDesc* sys,
-                      hipStream_t st) {
+                      const double* table, hipStream_t st) {
   if (g.n_tiles == 0) return;
   const dim3 grid(g.n_tiles), block(64);
   switch (g.p) {
-    case 1: hipLaunchKernelGGL(k_diag_elem<1>, grid, block, 0, st, g, tiles, E, slots, sys); break;
-    case 2: hipLaunchKernelGGL(k_diag_elem<2>, grid, block, 0, st, g, tiles, E, slots, sys); break;
-    case 3: hipLaunchKernelGGL(k_diag_elem<3>, grid, block, 0, st, g, tiles, E, slots, sys); break;
-    default: hipLaunchKernelGGL(k_diag_elem<4>, grid, block, 0, st, g, tiles, E, slots, sys); break;
+    case 1: hipLaunchKernelGGL(k_diag_elem<1>, grid, block, 0, st, g, tiles, E, slots, sys, table); break;
+    case 2: hipLaunchKernelGGL(k_diag_elem<2>, grid, block, 0, st, g, tiles, E, slots, sys, table); break;
+    case 3: hipLaunchKernelGGL(k_diag_elem<3>, grid, block, 0, st, g, tiles, E, slots, sys, table); break;
+    default: hipLaunchKernelGGL(k_diag_elem<4>, grid, block, 0, st, g, tiles, E, slots, sys, table); break;
   }
 }
 
@@ -867,8 +869,8 @@ void launch_fill_i32(int32_t* a, int32_t v, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(n, BLOCK)), dim3(BLOCK), 0, st, a, v, n);
 }
 
-void launch_dinv(const PcgDev& s, double* dinv, hipStream_t st) {
-  hipLaunchKernelGGL(k_dinv, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, dinv);
+void launch_dinv(const PcgDev& s, double* dinv, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_dinv, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, dinv, scale);
 }
 
 void launch_init(const PcgDev& s, int use_slots, hipStream_t st) {

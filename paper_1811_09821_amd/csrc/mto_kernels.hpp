@@ -17,6 +17,7 @@ struct GroupDev {
   const double* kfrag;     // MFMA A fragments [S*NEP/4][MB][64]
   const double* ks;        // plain K_s [S][ne][ne]
   const double* kdiag;     // diag(K_s) [S][ne]
+  const double* kabs;      // row sums of |K_s| [S][ne] (l1 smoother)
   const int32_t* gidx;     // [NEP][npad] free DOF (instance-local) of local DOF, -1 absent
   const int32_t* sidx;     // [MB*16][npad] slot (instance-local), -1 absent
   const int32_t* cell;     // [npad] first density cell (global)
@@ -48,7 +49,8 @@ struct PcgDev {
   int32_t* n_active;       // [1]
 };
 
-enum ElemMode { ELEM_APPLY = 0, ELEM_PCG = 1 };
+// ELEM_APPLY_RUNNING: as ELEM_APPLY, skipping systems whose PCG has stopped.
+enum ElemMode { ELEM_APPLY = 0, ELEM_PCG = 1, ELEM_APPLY_RUNNING = 2 };
 
 // Dynamic LDS of the MFMA element kernel: two scalars, then the larger of the
 // gathered tile ([2][NEP][16 ncol] doubles) and the partial products of
@@ -66,15 +68,17 @@ void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E
                  const PcgDev& s, int mode, int it_k, hipStream_t st);
 void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const double* x, double* gout,
                  const SysDesc* sys, hipStream_t st);
+// per element, sum_s E_s table[s][row] into the slots of load-0 systems
+// (table = diag(K_s) for Jacobi, row sums of |K_s| for the l1 smoother)
 void launch_diag_elem(const GroupDev& g, const Tile* tiles, const double* E, double* slots, const SysDesc* sys,
-                      hipStream_t st);
+                      const double* table, hipStream_t st);
 
 void launch_simp(const double* rho, double* E, double* dE, int64_t n, double E0, double Emin, double q,
                  hipStream_t st);
 void launch_fill(double* a, double v, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t* a, int32_t v, int64_t n, hipStream_t st);
-// dinv = 1 / (sum of slots) on the first system of each instance
-void launch_dinv(const PcgDev& s, double* dinv, hipStream_t st);
+// dinv = scale / (sum of slots) on the first system of each instance
+void launch_dinv(const PcgDev& s, double* dinv, double scale, hipStream_t st);
 // r = f (use_slots 0), f - assembled slots (1) or the r already stored (2);
 // then z = dinv r, p = 0, partials
 void launch_init(const PcgDev& s, int use_slots, hipStream_t st);
@@ -102,5 +106,23 @@ void launch_compliance(const PcgDev& s, double* c, hipStream_t st);
 void launch_weighted_sens(const double* g, const double* w, double* out, const int64_t* inst_cell_off,
                           const int64_t* inst_g_off, const int32_t* inst_c_off, const int32_t* inst_L, int n_inst,
                           int64_t n_cells, hipStream_t st);
+
+// ---- multigrid (mto_mg.hip) ----
+void launch_mg_assemble1(const MgChunk* ch, int n, const MgElem* elems, const double* kv, const double* E,
+                         const int32_t* vfree, double* A, double* mask, hipStream_t st);
+void launch_mg_l1(const MgChunk* ch, int n, const double* A, double* dinv, hipStream_t st);
+void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_t st);
+void launch_mg_coarse_setup(const MgChunk* ch, int n, const double* A, double* dense, hipStream_t st);
+void launch_mg_restrict0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* dinv,
+                         double* r1, double* e1, hipStream_t st);
+void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
+                        const double* dinv, double* r, double* e, hipStream_t st);
+void launch_mg_coarse_solve(const MgChunk* ch, int n, const PcgDev& s, const double* dense, const double* r,
+                            double* e2, hipStream_t st);
+void launch_mg_prolong_smooth(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
+                              const double* dinv, const double* r, const double* e, double* e2, hipStream_t st);
+void launch_mg_prolong0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* e2,
+                        hipStream_t st);
+void launch_mg_post0(const PcgDev& s, int it_k, int init, hipStream_t st);
 
 }  // namespace mto

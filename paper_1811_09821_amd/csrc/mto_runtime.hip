@@ -53,11 +53,31 @@ struct GroupHost {
   double* kfrag = nullptr;
   double* ks = nullptr;
   double* kdiag = nullptr;
+  double* kabs = nullptr;
   int32_t* gidx = nullptr;
   int32_t* sidx = nullptr;
   int32_t* cell = nullptr;
   int tile_begin = 0, n_tiles = 0;
   double flops = 0.0;  // 2 S ne^2 per element column
+  std::vector<double> kv;  // host copy of the vertex-block table
+  int kv_off = 0;
+};
+
+// Geometric hierarchy of the multigrid preconditioner (levels 1..L).
+struct MgHost {
+  int L = 0;
+  // per level l (index l-1): chunk ranges in the device chunk arrays
+  std::vector<int> sys_begin, sys_count, inst_begin, inst_count;
+  std::vector<MgChunk> chunks;  // all levels: system chunks then instance chunks, per level
+  MgChunk* d_chunks = nullptr;
+  double *A = nullptr, *dinv = nullptr, *mask = nullptr;  // operators [op nodes]
+  double *r = nullptr, *e = nullptr, *e2 = nullptr;       // vectors [vec nodes]
+  double* dense = nullptr;                                // coarsest inverses
+  int32_t* vfree = nullptr;                               // level 1: free index of vertex DOFs
+  MgElem* elems = nullptr;
+  double* kv = nullptr;
+  const MgChunk* sysc(int l) const { return d_chunks + sys_begin[l - 1]; }
+  const MgChunk* instc(int l) const { return d_chunks + inst_begin[l - 1]; }
 };
 
 struct mto_plan {
@@ -102,6 +122,7 @@ struct mto_plan {
   const double* b_rho = nullptr;
   double *b_u = nullptr, *b_c = nullptr, *b_g = nullptr;
   hipGraphExec_t setup_exec = nullptr, resid_exec = nullptr, restart_exec = nullptr, out_exec = nullptr;
+  MgHost mg;
 
   PcgDev pcg() const {
     PcgDev s{};
@@ -143,6 +164,7 @@ struct mto_plan {
     o.kfrag = g.kfrag;
     o.ks = g.ks;
     o.kdiag = g.kdiag;
+    o.kabs = g.kabs;
     o.gidx = g.gidx;
     o.sidx = g.sidx;
     o.cell = g.cell;
@@ -235,6 +257,154 @@ int check_launch(const char* what) {
   return MTO_OK;
 }
 
+// Builds the multigrid hierarchy: per instance the vertex grid of the mesh
+// (level 1) and its coarsenings by two, until the largest instance's grid
+// has at most MG_COARSE_MAX DOFs (smaller instances continue to coarsen,
+// down to one element, so every instance has the same number of levels).
+int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
+  MgHost& M = P->mg;
+  const int n = P->n_inst;
+  std::vector<std::vector<std::pair<int, int>>> dims(n);
+  int L = 1;
+  for (int i = 0; i < n; ++i) {
+    int nx = I[i].nelx, ny = I[i].nely, l = 1;
+    while (2LL * (nx + 1) * (ny + 1) > MG_COARSE_MAX && (nx > 1 || ny > 1)) {
+      nx = (nx + 1) / 2;
+      ny = (ny + 1) / 2;
+      ++l;
+    }
+    L = std::max(L, l);
+  }
+  for (int i = 0; i < n; ++i) {
+    int nx = I[i].nelx, ny = I[i].nely;
+    for (int l = 1; l <= L; ++l) {
+      dims[i].emplace_back(nx, ny);
+      nx = (nx + 1) / 2;
+      ny = (ny + 1) / 2;
+    }
+  }
+  M.L = L;
+  // operator node offsets [l][instance], vector node offsets [l][system]
+  std::vector<std::vector<int64_t>> op(L, std::vector<int64_t>(n)), vec(L, std::vector<int64_t>(P->n_sys));
+  int64_t op_tot = 0, vec_tot = 0, dense_tot = 0;
+  std::vector<int64_t> dense_off(n);
+  for (int l = 0; l < L; ++l)
+    for (int i = 0; i < n; ++i) {
+      op[l][i] = op_tot;
+      op_tot += (int64_t)(dims[i][l].first + 1) * (dims[i][l].second + 1);
+    }
+  for (int l = 0; l < L; ++l)
+    for (int s = 0; s < P->n_sys; ++s) {
+      const int i = P->sys[s].inst;
+      vec[l][s] = vec_tot;
+      vec_tot += (int64_t)(dims[i][l].first + 1) * (dims[i][l].second + 1);
+    }
+  for (int i = 0; i < n; ++i) {
+    const int64_t N = (int64_t)(dims[i][L - 1].first + 1) * (dims[i][L - 1].second + 1);
+    if (2 * N > MG_COARSE_MAX) return fail(MTO_EINVAL, "multigrid: coarsest grid too large");
+    dense_off[i] = dense_tot;
+    dense_tot += 4 * N * N;
+  }
+  // element table per instance for the level-1 assembly
+  std::vector<int64_t> elem_off(n);
+  std::vector<MgElem> elems;
+  std::map<std::pair<int, int>, int> gidx;
+  std::vector<double> kvpool;
+  for (size_t g = 0; g < P->groups.size(); ++g) {
+    gidx[{P->groups[g].p, P->groups[g].d}] = (int)g;
+    P->groups[g].kv_off = (int)kvpool.size();
+    kvpool.insert(kvpool.end(), P->groups[g].kv.begin(), P->groups[g].kv.end());
+  }
+  for (int i = 0; i < n; ++i) {
+    elem_off[i] = (int64_t)elems.size();
+    for (size_t e = 0; e < I[i].p.size(); ++e) {
+      const GroupHost& G = P->groups[gidx[{(int)I[i].p[e], (int)I[i].d[e]}]];
+      elems.push_back(MgElem{(int32_t)(P->cell_off[i] + I[i].cell_off[e]), G.kv_off, G.S, 0});
+    }
+  }
+  // level-1 free index of each vertex DOF (vertex DOFs are the first 2 N1 of the numbering)
+  std::vector<int32_t> vfree;
+  int64_t n1_tot = 0;
+  for (int i = 0; i < n; ++i) n1_tot += (int64_t)(I[i].nelx + 1) * (I[i].nely + 1);
+  vfree.assign(2 * (size_t)n1_tot, -1);
+  for (int i = 0; i < n; ++i) {
+    const int64_t N1 = (int64_t)(I[i].nelx + 1) * (I[i].nely + 1);
+    for (int64_t k = 0; k < 2 * N1; ++k) vfree[2 * op[0][i] + k] = I[i].full_to_free[k];
+  }
+  // chunks: per level the system chunks, then the instance chunks
+  M.sys_begin.assign(L, 0);
+  M.sys_count.assign(L, 0);
+  M.inst_begin.assign(L, 0);
+  M.inst_count.assign(L, 0);
+  auto make = [&](int l, int i, int sys, int nb, int ne) {
+    MgChunk c{};
+    c.sys = sys;
+    c.inst = i;
+    c.level = l + 1;
+    c.node_begin = nb;
+    c.node_end = ne;
+    c.nx = dims[i][l].first;
+    c.ny = dims[i][l].second;
+    c.op = op[l][i];
+    c.vec = sys >= 0 ? vec[l][sys] : -1;
+    if (l > 0) {
+      c.fnx = dims[i][l - 1].first;
+      c.fny = dims[i][l - 1].second;
+      c.fop = op[l - 1][i];
+      c.fvec = sys >= 0 ? vec[l - 1][sys] : -1;
+    } else {
+      c.fop = c.fvec = -1;
+    }
+    if (l + 1 < L) {
+      c.cnx = dims[i][l + 1].first;
+      c.cny = dims[i][l + 1].second;
+      c.cop = op[l + 1][i];
+      c.cvec = sys >= 0 ? vec[l + 1][sys] : -1;
+    } else {
+      c.cop = c.cvec = -1;
+    }
+    c.dense_off = dense_off[i];
+    c.elem_off = elem_off[i];
+    if (sys >= 0) {
+      c.dof_off = P->sys[sys].dof_off;
+      c.slot_off = P->sys[sys].slot_off;
+      c.nfv = P->sys[sys].nfv;
+      c.nfe = P->sys[sys].nfe;
+    }
+    return c;
+  };
+  for (int l = 0; l < L; ++l) {
+    const bool coarsest = l == L - 1;
+    M.sys_begin[l] = (int)M.chunks.size();
+    for (int s = 0; s < P->n_sys; ++s) {
+      const int i = P->sys[s].inst;
+      const int N = (dims[i][l].first + 1) * (dims[i][l].second + 1);
+      const int step = coarsest ? N : MG_CHUNK;
+      for (int b = 0; b < N; b += step) M.chunks.push_back(make(l, i, s, b, std::min(N, b + step)));
+    }
+    M.sys_count[l] = (int)M.chunks.size() - M.sys_begin[l];
+    M.inst_begin[l] = (int)M.chunks.size();
+    for (int i = 0; i < n; ++i) {
+      const int N = (dims[i][l].first + 1) * (dims[i][l].second + 1);
+      const int step = coarsest ? N : MG_CHUNK;
+      for (int b = 0; b < N; b += step) M.chunks.push_back(make(l, i, -1, b, std::min(N, b + step)));
+    }
+    M.inst_count[l] = (int)M.chunks.size() - M.inst_begin[l];
+  }
+  int rc;
+  if ((rc = dev_upload(P, &M.d_chunks, M.chunks)) || (rc = dev_alloc(P, &M.A, 36 * (size_t)op_tot)) ||
+      (rc = dev_alloc(P, &M.dinv, 2 * (size_t)op_tot)) || (rc = dev_alloc(P, &M.mask, 2 * (size_t)op_tot)) ||
+      (rc = dev_alloc(P, &M.r, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.e, 2 * (size_t)vec_tot)) ||
+      (rc = dev_alloc(P, &M.e2, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.dense, (size_t)dense_tot)) ||
+      (rc = dev_upload(P, &M.vfree, vfree)) || (rc = dev_upload(P, &M.elems, elems)) ||
+      (rc = dev_upload(P, &M.kv, kvpool)))
+    return rc;
+  launch_fill(M.e, 0.0, 2 * vec_tot, 0);
+  launch_fill(M.e2, 0.0, 2 * vec_tot, 0);
+  launch_fill(M.r, 0.0, 2 * vec_tot, 0);
+  return check_launch("multigrid setup");
+}
+
 int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan** out) {
   if (!out) return fail(MTO_EINVAL, "out is NULL");
   *out = nullptr;
@@ -244,6 +414,8 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     return fail(MTO_EINVAL, "params out of range (rtol > 0, 0 <= Emin <= E0, -1 < nu < 0.5, q >= 1)");
   if (prm->kernel_path != MTO_PATH_MFMA && prm->kernel_path != MTO_PATH_PLAIN)
     return fail(MTO_EINVAL, "unknown kernel_path");
+  if (prm->precond != MTO_PRECOND_JACOBI && prm->precond != MTO_PRECOND_MG)
+    return fail(MTO_EINVAL, "unknown precond");
   std::vector<InstanceHost> I(n);
   for (int i = 0; i < n; ++i) {
     std::string err;
@@ -381,13 +553,27 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     }
     std::vector<double> ks = subcell_tables(g.p, g.d, P->prm.nu);
     std::vector<double> kfr = mfma_fragments(ks, g.p, g.d);
-    std::vector<double> kdiag((size_t)g.S * g.ne);
+    std::vector<double> kdiag((size_t)g.S * g.ne), kabs((size_t)g.S * g.ne, 0.0);
     for (int s = 0; s < g.S; ++s)
-      for (int j = 0; j < g.ne; ++j) kdiag[(size_t)s * g.ne + j] = ks[(size_t)s * g.ne * g.ne + j * g.ne + j];
+      for (int j = 0; j < g.ne; ++j) {
+        kdiag[(size_t)s * g.ne + j] = ks[(size_t)s * g.ne * g.ne + j * g.ne + j];
+        for (int k = 0; k < g.ne; ++k) kabs[(size_t)s * g.ne + j] += std::fabs(ks[(size_t)s * g.ne * g.ne + j * g.ne + k]);
+      }
+    // vertex-vertex blocks [S][corner a0][corner a1][c0][c1] for the level-1 operator
+    g.kv.assign((size_t)g.S * 64, 0.0);
+    for (int s = 0; s < g.S; ++s)
+      for (int a0 = 0; a0 < 4; ++a0)
+        for (int a1 = 0; a1 < 4; ++a1)
+          for (int c0 = 0; c0 < 2; ++c0)
+            for (int c1 = 0; c1 < 2; ++c1) {
+              const int l0 = (a0 >> 1) * (g.p + 1) + (a0 & 1), l1 = (a1 >> 1) * (g.p + 1) + (a1 & 1);
+              g.kv[(((size_t)s * 4 + a0) * 4 + a1) * 4 + c0 * 2 + c1] =
+                  ks[(size_t)s * g.ne * g.ne + (2 * l0 + c0) * g.ne + 2 * l1 + c1];
+            }
     int rc;
     if ((rc = dev_upload(P, &g.gidx, gidx)) || (rc = dev_upload(P, &g.sidx, sidx)) ||
         (rc = dev_upload(P, &g.cell, cell)) || (rc = dev_upload(P, &g.ks, ks)) || (rc = dev_upload(P, &g.kfrag, kfr)) ||
-        (rc = dev_upload(P, &g.kdiag, kdiag)))
+        (rc = dev_upload(P, &g.kdiag, kdiag)) || (rc = dev_upload(P, &g.kabs, kabs)))
       return cleanup(rc);
     double per_col = 2.0 * g.S * g.ne * g.ne;
     int64_t cols = 0;
@@ -443,6 +629,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       return cleanup(fail(MTO_EHIP, "hipEventCreate failed"));
   if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(fail(MTO_EHIP, "hipStreamCreate failed"));
+  if (P->prm.precond == MTO_PRECOND_MG && (rc = build_mg(P, I))) return cleanup(rc);
   if ((rc = rebuild_tiles(P))) return cleanup(rc);
   HIP_TRY(hipDeviceSynchronize());
   *out = P;
@@ -458,11 +645,47 @@ void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_
 
 void enq_residual(mto_plan* P, hipStream_t st);
 
+// Per design: level-1 operator, Galerkin coarse operators, l1 diagonals and
+// the dense inverse of the coarsest grid.
+void enq_mg_setup(mto_plan* P, hipStream_t st) {
+  const MgHost& M = P->mg;
+  launch_mg_assemble1(M.instc(1), M.inst_count[0], M.elems, M.kv, P->E, M.vfree, M.A, M.mask, st);
+  launch_mg_l1(M.instc(1), M.inst_count[0], M.A, M.dinv, st);
+  for (int l = 2; l <= M.L; ++l) {
+    launch_mg_rap(M.instc(l), M.inst_count[l - 1], M.A, M.mask, st);
+    launch_mg_l1(M.instc(l), M.inst_count[l - 1], M.A, M.dinv, st);
+  }
+  launch_mg_coarse_setup(M.instc(M.L), M.inst_count[M.L - 1], M.A, M.dense, st);
+}
+
+// z = M r: one V-cycle from z = D0^-1 r (already in z), l1-Jacobi pre- and
+// post-smoothing on every level, dense solve on the coarsest; the last kernel
+// also forms the partial sums of r.z.
+void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_t st);
+void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
+  const MgHost& M = P->mg;
+  const PcgDev s = P->pcg();
+  enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
+  launch_mg_restrict0(M.sysc(1), M.sys_count[0], s, M.vfree, M.dinv, M.r, M.e, st);
+  for (int l = 2; l <= M.L; ++l)
+    launch_mg_restrict(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, st);
+  launch_mg_coarse_solve(M.sysc(M.L), M.sys_count[M.L - 1], s, M.dense, M.r, M.e2, st);
+  for (int l = M.L - 1; l >= 1; --l)
+    launch_mg_prolong_smooth(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, M.e2, st);
+  launch_mg_prolong0(M.sysc(1), M.sys_count[0], s, M.vfree, M.e2, st);
+  enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
+  launch_mg_post0(s, it_k, init, st);
+}
+
 void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st) {
   const PcgDev s = P->pcg();
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
-  for (auto& g : P->groups) launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, st);
-  launch_dinv(s, P->dinv, st);
+  const bool mg = P->prm.precond == MTO_PRECOND_MG;
+  const bool l1 = mg && !(P->prm.mg_omega > 0.0);  // l1-Jacobi level-0 smoother
+  for (auto& g : P->groups)
+    launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, l1 ? g.kabs : g.kdiag, st);
+  launch_dinv(s, P->dinv, (mg && !l1) ? P->prm.mg_omega : 1.0, st);
+  if (mg) enq_mg_setup(P, st);
   // PCG iterates on the correction x (from 0); the solution is xs_hi + xs_lo
   launch_fill(P->x, 0.0, P->n_vec, st);
   launch_fill(P->xs_lo, 0.0, P->n_vec, st);
@@ -475,6 +698,7 @@ void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st)
     launch_init(s, 0, st);
   }
   launch_sys_setup(s, P->prm.rtol, st);
+  if (mg) enq_vcycle(P, 0, 1, st);
 }
 
 void enq_chunk(mto_plan* P, int G, hipStream_t st) {
@@ -483,6 +707,7 @@ void enq_chunk(mto_plan* P, int G, hipStream_t st) {
     enq_elem_all(P, P->p, ELEM_PCG, k, st);
     launch_dof1(s, k, st);
     launch_dof2(s, k, st);
+    if (P->prm.precond == MTO_PRECOND_MG) enq_vcycle(P, k, 0, st);
   }
   launch_advance(s, G, st);
 }
@@ -507,6 +732,7 @@ void enq_cycle_end(mto_plan* P, hipStream_t st) {
 void enq_restart(mto_plan* P, hipStream_t st) {
   launch_init(P->pcg(), 2, st);
   launch_sys_setup(P->pcg(), P->prm.rtol, st);
+  if (P->prm.precond == MTO_PRECOND_MG) enq_vcycle(P, 0, 1, st);
 }
 
 void enq_outputs(mto_plan* P, double* u, double* c, double* g, hipStream_t st) {
@@ -786,7 +1012,7 @@ int mto_jacobi_diagonal(mto_plan* P, const double* rho, double* diag, void* stre
   hipStream_t st = (hipStream_t)stream;
   const PcgDev s = P->pcg();
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
-  for (auto& g : P->groups) launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, st);
+  for (auto& g : P->groups) launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, g.kdiag, st);
   int64_t acc = 0;
   for (int i = 0; i < P->n_inst; ++i) acc += P->n_dof[i];
   launch_fill(diag, 0.0, acc, st);

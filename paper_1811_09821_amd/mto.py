@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmto.so")
 
 MTO_OK, MTO_EINVAL, MTO_ESINGULAR, MTO_ENOCONV, MTO_EBREAKDOWN, MTO_EHIP, MTO_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 PATH_MFMA, PATH_PLAIN = 0, 1
+PRECOND_JACOBI, PRECOND_MG = 0, 1
 ERROR_NAMES = {MTO_EINVAL: "MTO_EINVAL", MTO_ESINGULAR: "MTO_ESINGULAR", MTO_ENOCONV: "MTO_ENOCONV",
                MTO_EBREAKDOWN: "MTO_EBREAKDOWN", MTO_EHIP: "MTO_EHIP", MTO_ENOMEM: "MTO_ENOMEM"}
 
@@ -45,7 +46,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("E0", ctypes.c_double), ("Emin", ctypes.c_double), ("nu", ctypes.c_double),
                 ("q", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("kernel_path", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32),
-                ("max_restarts", ctypes.c_int32)]
+                ("max_restarts", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("mg_omega", ctypes.c_double)]
 
 
 class _Problem(ctypes.Structure):
@@ -150,7 +152,8 @@ def _f64_cuda(t, n, name):
 
 def default_params(**kw):
     prm = dict(E0=1.0, Emin=1e-9, nu=0.3, q=3.0, rtol=1e-11, max_iter=0, kernel_path=PATH_MFMA,
-               iters_per_launch=32, max_restarts=3)
+               iters_per_launch=32, max_restarts=3, precond=PRECOND_JACOBI,
+               mg_omega=0.0)
     prm.update(kw)
     return prm
 
@@ -183,7 +186,8 @@ class Plan:
             arr[k].n_loads = len(pr.loads)
             arr[k].n_load_cases = int(pr.n_load_cases)
         cp = _Params(prm["E0"], prm["Emin"], prm["nu"], prm["q"], prm["rtol"], prm["max_iter"],
-                     prm["kernel_path"], prm["iters_per_launch"], prm["max_restarts"])
+                     prm["kernel_path"], prm["iters_per_launch"], prm["max_restarts"], prm["precond"],
+                     prm["mg_omega"])
         h = ctypes.c_void_p()
         _check(_lib.mto_batch_plan_create(arr, len(problems), ctypes.byref(cp), ctypes.byref(h)))
         self._keep = []

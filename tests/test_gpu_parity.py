@@ -157,6 +157,16 @@ def test_solve_parity(cuda, name):
     check_solution(plan, prs, u, c, g, st)
 
 
+@pytest.mark.parametrize("name", ["mbb20x10", "mixed_3loads", "uniform_p4d5"])
+def test_solve_parity_multigrid(cuda, name):
+    """The multigrid-preconditioned PCG reaches the same solution."""
+    prs = CASES[name]()
+    plan = mto().Plan(prs, precond=1)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
+
+
 def test_solve_parity_plain_path(cuda):
     prs = [P.small_mixed(12, 6, seed=6, n_loads=2)]
     plan = mto().Plan(prs, kernel_path=1)
