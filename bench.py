@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--compare-plain", action="store_true", help="also time the plain per-element path")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="after timing, run one device-to-device copy of this many MiB (a known-size kernel "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus must be 1)",
@@ -162,6 +165,15 @@ def main():
         out["plain_path"] = {"s_per_design": (time.perf_counter() - t1) / n_designs,
                              "contraction_ms": plain.time_contraction(rho, reps=20),
                              "iterations": st_p["iterations"]}
+
+    if args.calibrate_copy_mb > 0:
+        n = args.calibrate_copy_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 2 * n * 8
 
     if not args.no_cpu_baseline:
         t_cpu, n_s = cpu_baseline(prs)

@@ -211,6 +211,43 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
   const Tile t = tiles[g.tile_begin + blockIdx.x];
   if (mode == ELEM_APPLY_RUNNING && s.status[t.sys] != SYS_RUNNING) return;
   const bool pcg = mode == ELEM_PCG;
+  const int n = lane & 15, kq = lane >> 4;
+  // Everything that depends only on the tile is requested before the gather
+  // barrier, so these loads overlap the gather: cell offsets, the scatter
+  // slots (wave 0 stores), the first density cell's A fragments and moduli.
+  int cellb[NC];
+  bool valid[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int col = c * 16 + n;
+    valid[c] = col < t.count;
+    cellb[c] = valid[c] ? g.cell[t.elem_begin + col] : 0;
+  }
+  int sidx[NC][MB][4];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = b * 16 + kq + 4 * r;
+        sidx[c][b][r] = (wave == 0 && valid[c] && row < NE) ? g.sidx[row * g.npad + t.elem_begin + c * 16 + n] : -1;
+      }
+  const int s_begin = (wave * g.S) / ks, s_end = ((wave + 1) * g.S) / ks;
+  const double* __restrict__ kf = g.kfrag + lane;
+  // One density cell's A fragments (NJ k-steps x MB row blocks) and moduli.
+  auto load_slice = [&](int sc, double (&a)[NJ][MB], double (&e)[NC]) {
+    const double* __restrict__ kfs = kf + (size_t)sc * NJ * MB * 64;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+      for (int b = 0; b < MB; ++b) a[jj][b] = kfs[(jj * MB + b) * 64];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) e[c] = valid[c] ? E[cellb[c] + sc] : 0.0;
+  };
+  double a0[NJ][MB], e0[NC];
+  if (s_begin < s_end) load_slice(s_begin, a0, e0);
+
   if (pcg && wave == 0) {
     const Scal sc = pcg_state(s, t.sys, t.pc_begin, t.pc_end, *s.it_base + it_k, true);
     if (lane == 0) {
@@ -237,15 +274,10 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
   __syncthreads();
   if (pcg && lds[1] == 0.0) return;  // system stopped: uniform over the block
   const double beta = pcg ? lds[0] : 0.0;
-  const int n = lane & 15, kq = lane >> 4;
   double u[NC][NJ];
-  int cellb[NC];
-  bool valid[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int col = c * 16 + n;
-    valid[c] = col < t.count;
-    cellb[c] = valid[c] ? g.cell[t.elem_begin + col] : 0;
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
       const int k = (4 * jj + kq) * TC + col;
@@ -258,18 +290,6 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[b][c] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int s_begin = (wave * g.S) / ks, s_end = ((wave + 1) * g.S) / ks;
-  const double* __restrict__ kf = g.kfrag + lane;
-  // One density cell's A fragments (NJ k-steps x MB row blocks) and moduli.
-  auto load_slice = [&](int sc, double (&a)[NJ][MB], double (&e)[NC]) {
-    const double* __restrict__ kfs = kf + (size_t)sc * NJ * MB * 64;
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj)
-#pragma unroll
-      for (int b = 0; b < MB; ++b) a[jj][b] = kfs[(jj * MB + b) * 64];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) e[c] = valid[c] ? E[cellb[c] + sc] : 0.0;
-  };
   auto mma_slice = [&](const double (&a)[NJ][MB], const double (&e)[NC]) {
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj)
@@ -283,8 +303,7 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
   if constexpr (NJ * MB <= 20) {
     // ping-pong register buffers: the next cell's fragments load during the
     // current cell's MFMAs
-    double a0[NJ][MB], a1[NJ][MB], e0[NC], e1[NC];
-    if (s_begin < s_end) load_slice(s_begin, a0, e0);
+    double a1[NJ][MB], e1[NC];
     for (int sc = s_begin; sc < s_end; sc += 2) {
       if (sc + 1 < s_end) load_slice(sc + 1, a1, e1);
       mma_slice(a0, e0);
@@ -293,9 +312,8 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
       mma_slice(a1, e1);
     }
   } else {
-    double a0[NJ][MB], e0[NC];
     for (int sc = s_begin; sc < s_end; ++sc) {
-      load_slice(sc, a0, e0);
+      if (sc > s_begin) load_slice(sc, a0, e0);
       mma_slice(a0, e0);
     }
   }
@@ -323,20 +341,12 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
 
   double* __restrict__ sl = s.slots + t.slot_off;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    if (!valid[c]) continue;
-    const int el = t.elem_begin + c * 16 + n;
+  for (int c = 0; c < NC; ++c)
 #pragma unroll
     for (int b = 0; b < MB; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = b * 16 + kq + 4 * r;
-        if (row < NE) {
-          const int si = g.sidx[row * g.npad + el];
-          if (si >= 0) sl[si] = acc[b][c][r];
-        }
-      }
-  }
+      for (int r = 0; r < 4; ++r)
+        if (sidx[c][b][r] >= 0) sl[sidx[c][b][r]] = acc[b][c][r];
 }
 
 // ---------------------------------------------------------------------------

@@ -1061,7 +1061,7 @@ int mto_autotune(mto_plan* P, const double* rho, void* stream, char* report, int
     for (int nc : cand_nc)
       for (int ks : cand_ks) {
         if (ks > g.S || elem_lds_bytes(g.p, nc, ks) > ELEM_LDS_LIMIT) continue;
-        if (g.p >= 3 && nc == 4) continue;  // register spills
+        if ((nc == 4 && g.p >= 2) || (nc == 2 && g.p == 4)) continue;  // register spills
         g.ncol = nc;
         g.waves = ks;
         int rc = rebuild_tiles(P);
