@@ -237,11 +237,19 @@ int mto_autotune(mto_plan* plan, const double* rho, void* stream, char* report, 
  * LDS.  Invalidates captured graphs. */
 int mto_set_tile(mto_plan* plan, int32_t p, int32_t d, int32_t ncol, int32_t ks);
 
-/* Average time (ms, host float from HIP events on `stream`) of one PCG
- * search-direction product K p, i.e. the element contraction kernels of all
- * (p, d) groups, over `reps` launches after 3 warm-ups.  Runs the solve setup
- * for rho first (overwrites the plan's PCG state). */
-int mto_time_contraction(mto_plan* plan, const double* rho, int32_t reps, void* stream, double* ms_per_matvec);
+/* Average time (ms, from HIP events on `stream`) of one PCG search-direction
+ * product K p, i.e. the element contraction kernels of all (p, d) groups.
+ * in_loop = 0: `reps` back-to-back launches of the first iteration's product
+ * after 3 warm-ups, between two stream events.  in_loop = 1: `reps` PCG
+ * iterations run eagerly from x = 0 (the kernels of a captured chunk, in
+ * order), each product kernel launched with start/end events on its own
+ * dispatch (hipExtLaunchKernel), summed over groups and averaged over
+ * iterations; reps should not exceed the iteration count of a solve,
+ * since the products of a converged system return at once.  Both run the
+ * solve setup for rho first and overwrite the plan's PCG state.  MTO_EINVAL
+ * for reps < 1 or in_loop outside {0, 1}. */
+int mto_time_contraction(mto_plan* plan, const double* rho, int32_t reps, int32_t in_loop, void* stream,
+                         double* ms_per_matvec);
 
 /* Frees the plan and its device buffers (NULL is a no-op). */
 void mto_plan_destroy(mto_plan* plan);

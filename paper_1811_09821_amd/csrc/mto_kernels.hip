@@ -21,6 +21,7 @@
 // see bit-identical alpha, beta and convergence decisions.
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "mto_kernels.hpp"
 
@@ -800,19 +801,30 @@ __global__ __launch_bounds__(BLOCK) void k_weighted_sens(const double* __restric
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Launches kernel k; with events the launch carries them on its own dispatch
+// packet, so they time exactly this kernel (no separate marker packets).
+template <typename K, typename... Args>
+void launch_timed(K k, dim3 grid, dim3 block, uint32_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                  Args... args) {
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL(k, grid, block, lds, st, ev0, ev1, 0u, args...);
+  else
+    hipLaunchKernelGGL(k, grid, block, lds, st, args...);
+}
+
 template <int P>
 void launch_elem_p(const GroupDev& g, int path, int ncol, const Tile* tiles, const double* E, const double* xin,
-                   const PcgDev& s, int mode, int it_k, hipStream_t st) {
+                   const PcgDev& s, int mode, int it_k, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (path == MTO_PATH_PLAIN) {
-    hipLaunchKernelGGL(k_elem_plain<P>, dim3(g.n_tiles), dim3(64), 0, st, g, tiles, E, xin, s, mode, it_k);
+    launch_timed(k_elem_plain<P>, dim3(g.n_tiles), dim3(64), 0u, st, ev0, ev1, g, tiles, E, xin, s, mode, it_k);
     return;
   }
   const dim3 grid(g.n_tiles), block(64 * g.waves);
-  const size_t lds = elem_lds_bytes(P, ncol, g.waves);
+  const uint32_t lds = (uint32_t)elem_lds_bytes(P, ncol, g.waves);
   switch (ncol) {
-    case 1: hipLaunchKernelGGL((k_elem_mfma<P, 1>), grid, block, lds, st, g, tiles, E, xin, s, mode, it_k); break;
-    case 2: hipLaunchKernelGGL((k_elem_mfma<P, 2>), grid, block, lds, st, g, tiles, E, xin, s, mode, it_k); break;
-    default: hipLaunchKernelGGL((k_elem_mfma<P, 4>), grid, block, lds, st, g, tiles, E, xin, s, mode, it_k); break;
+    case 1: launch_timed(k_elem_mfma<P, 1>, grid, block, lds, st, ev0, ev1, g, tiles, E, xin, s, mode, it_k); break;
+    case 2: launch_timed(k_elem_mfma<P, 2>, grid, block, lds, st, ev0, ev1, g, tiles, E, xin, s, mode, it_k); break;
+    default: launch_timed(k_elem_mfma<P, 4>, grid, block, lds, st, ev0, ev1, g, tiles, E, xin, s, mode, it_k); break;
   }
 }
 
@@ -830,13 +842,13 @@ void launch_sens_p(const GroupDev& g, int ncol, const Tile* tiles, const double*
 }  // namespace
 
 void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E, const double* xin,
-                 const PcgDev& s, int mode, int it_k, hipStream_t st) {
+                 const PcgDev& s, int mode, int it_k, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.n_tiles == 0) return;
   switch (g.p) {
-    case 1: launch_elem_p<1>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st); break;
-    case 2: launch_elem_p<2>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st); break;
-    case 3: launch_elem_p<3>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st); break;
-    default: launch_elem_p<4>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st); break;
+    case 1: launch_elem_p<1>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
+    case 2: launch_elem_p<2>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
+    case 3: launch_elem_p<3>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
+    default: launch_elem_p<4>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
   }
 }
 

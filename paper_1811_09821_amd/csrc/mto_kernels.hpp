@@ -64,8 +64,10 @@ constexpr size_t ELEM_LDS_LIMIT = 64 * 1024;
 
 // y-slots of K applied to the vector `xin` (ELEM_APPLY) or to the PCG search
 // direction p = z + beta p formed on the fly (ELEM_PCG), for the tiles of one group.
+// Optional events ev0/ev1 record the start and end of this kernel itself.
 void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E, const double* xin,
-                 const PcgDev& s, int mode, int it_k, hipStream_t st);
+                 const PcgDev& s, int mode, int it_k, hipStream_t st, hipEvent_t ev0 = nullptr,
+                 hipEvent_t ev1 = nullptr);
 void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const double* x, double* gout,
                  const SysDesc* sys, hipStream_t st);
 // per element, sum_s E_s table[s][row] into the slots of load-0 systems

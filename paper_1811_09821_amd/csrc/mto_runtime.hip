@@ -1100,28 +1100,64 @@ int mto_autotune(mto_plan* P, const double* rho, void* stream, char* report, int
   return check_launch("autotune");
 }
 
-int mto_time_contraction(mto_plan* P, const double* rho, int32_t reps, void* stream, double* ms_per_matvec) {
+int mto_time_contraction(mto_plan* P, const double* rho, int32_t reps, int32_t in_loop, void* stream,
+                         double* ms_per_matvec) {
   g_err.clear();
-  if (!P || !rho || !ms_per_matvec || reps < 1) return fail(MTO_EINVAL, "bad argument");
+  if (!P || !rho || !ms_per_matvec || reps < 1 || (in_loop != 0 && in_loop != 1))
+    return fail(MTO_EINVAL, "bad argument");
   hipStream_t st = (hipStream_t)stream;
-  // PCG state of iteration 0 (x = 0, p = 0, beta = 0): each launch is the
-  // search-direction product of the first iteration, identical every time.
   enq_setup(P, rho, nullptr, st);
   int rc = check_launch("time_contraction setup");
   if (rc) return rc;
-  for (int w = 0; w < 3; ++w) enq_elem_all(P, P->p, ELEM_PCG, 0, st);
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  HIP_TRY(hipEventRecord(e0, st));
-  for (int w = 0; w < reps; ++w) enq_elem_all(P, P->p, ELEM_PCG, 0, st);
-  HIP_TRY(hipEventRecord(e1, st));
-  HIP_TRY(hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  *ms_per_matvec = (double)ms / reps;
+  if (!in_loop) {
+    // PCG state of iteration 0 (x = 0, p = 0, beta = 0): each launch is the
+    // search-direction product of the first iteration, identical every time.
+    for (int w = 0; w < 3; ++w) enq_elem_all(P, P->p, ELEM_PCG, 0, st);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    for (int w = 0; w < reps; ++w) enq_elem_all(P, P->p, ELEM_PCG, 0, st);
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_matvec = (double)ms / reps;
+    return check_launch("time_contraction");
+  }
+  // Inside the iteration: `reps` PCG iterations run eagerly from x = 0, the
+  // same kernels in the same order as a captured chunk, so the products see
+  // the caches the vector kernels leave behind.  Each product kernel carries
+  // its own start/end events on its dispatch packet.
+  const PcgDev s = P->pcg();
+  const int G = P->prm.iters_per_launch;
+  const size_t ng = P->groups.size();
+  std::vector<hipEvent_t> ev(2 * ng * (size_t)reps, nullptr);
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  for (int i = 0; i < reps; ++i) {
+    const int k = i % G;
+    for (size_t gi = 0; gi < ng; ++gi) {
+      auto& g = P->groups[gi];
+      hipEvent_t* e = &ev[2 * (ng * i + gi)];
+      launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, P->p, s, ELEM_PCG, k, st, e[0], e[1]);
+    }
+    launch_dof1(s, k, st);
+    launch_dof2(s, k, st);
+    if (P->prm.precond == MTO_PRECOND_MG) enq_vcycle(P, k, 0, st);
+    if (k == G - 1 || i == reps - 1) launch_advance(s, k + 1, st);
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  double total = 0.0;
+  for (size_t j = 0; j < ng * (size_t)reps; ++j) {
+    if (P->groups[j % ng].n_tiles == 0) continue;  // nothing launched, events never recorded
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
+    total += ms;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  *ms_per_matvec = total / reps;
   return check_launch("time_contraction");
 }
 

@@ -91,7 +91,7 @@ def _load():
         "mto_weighted_sensitivity": ([vp, vp, vp, vp, vp], i32),
         "mto_autotune": ([vp, vp, vp, ctypes.c_char_p, i32], i32),
         "mto_set_tile": ([vp, i32, i32, i32, i32], i32),
-        "mto_time_contraction": ([vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
+        "mto_time_contraction": ([vp, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "mto_plan_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
@@ -306,11 +306,13 @@ class Plan:
         self._bound = None
         return buf.value.decode()
 
-    def time_contraction(self, rho, reps=50, stream=None):
-        """Average ms of one PCG product K p (all groups), HIP events."""
+    def time_contraction(self, rho, reps=50, in_loop=False, stream=None):
+        """Average ms of one PCG product K p (all groups), HIP events:
+        back-to-back launches, or (in_loop) inside eagerly run PCG iterations."""
         _f64_cuda(rho, self.info["n_cells"], "rho")
         ms = ctypes.c_double()
-        _check(_lib.mto_time_contraction(self.handle, _ptr(rho), int(reps), _stream(stream), ctypes.byref(ms)))
+        _check(_lib.mto_time_contraction(self.handle, _ptr(rho), int(reps), int(bool(in_loop)), _stream(stream),
+                                         ctypes.byref(ms)))
         return ms.value
 
     def set_tile(self, ncol, ks=1, p=0, d=0):

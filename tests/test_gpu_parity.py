@@ -243,3 +243,21 @@ def test_repeat_solve_is_deterministic(cuda):
     b = plan.solve(rho)
     for x, y in zip(a[:3], b[:3]):
         assert torch.equal(x, y)
+
+
+def test_time_contraction_modes_leave_solve_exact(cuda):
+    """Both timing modes of the contraction report a positive duration, reject
+    bad arguments, and a later solve of the same plan is bit-identical to one
+    made before them (timing only overwrites the PCG state)."""
+    m = mto()
+    pr = P.small_mixed(16, 8, seed=52, n_loads=2)
+    plan = m.Plan(pr)
+    rho = torch.tensor(pr.rho, device=cuda)
+    a = plan.solve(rho)
+    assert plan.time_contraction(rho, reps=5) > 0.0
+    assert plan.time_contraction(rho, reps=40, in_loop=True) > 0.0
+    with pytest.raises(m.MtoError):
+        plan.time_contraction(rho, reps=0)
+    b = plan.solve(rho)
+    for x, y in zip(a[:3], b[:3]):
+        assert torch.equal(x, y)
