@@ -84,9 +84,12 @@ enum { /* element contraction kernels */
 
 enum { /* PCG preconditioners */
   MTO_PRECOND_JACOBI = 0, /* diagonal of K (default) */
-  MTO_PRECOND_MG = 1      /* one multigrid V-cycle: hierarchic-order injection to the bilinear
+  MTO_PRECOND_MG = 1,     /* one multigrid V-cycle: hierarchic-order injection to the bilinear
                              vertex grid, then geometric coarsening with Galerkin operators,
                              l1-Jacobi smoothing, dense coarsest solve */
+  MTO_PRECOND_MG_ASM = 2  /* the same V-cycle with an element-block additive Schwarz smoother on
+                             the hierarchic level: exact inverses of the assembled operator
+                             restricted to each element's DOFs, formed once per design */
 };
 
 typedef struct {
@@ -118,8 +121,10 @@ typedef struct {
   int32_t iters_per_launch; /* PCG iterations per captured graph launch (<= 0: 32) */
   int32_t max_restarts;     /* refinement restarts from the true residual when it misses rtol (< 0: 3) */
   int32_t precond;          /* MTO_PRECOND_* */
-  double mg_omega;          /* multigrid level-0 smoother: damped Jacobi with this factor if > 0,
-                               else l1-Jacobi */
+  double mg_omega;          /* level-0 smoother weight.  MTO_PRECOND_MG: damped Jacobi with this
+                               factor if > 0, else l1-Jacobi.  MTO_PRECOND_MG_ASM: Schwarz
+                               damping if > 0, else 2 / (9 * 1.05), below the bound 2 / 9 that
+                               the nine-colouring of element blocks guarantees */
 } mto_params;
 
 typedef struct {

@@ -87,28 +87,6 @@ __device__ __forceinline__ Scal pcg_state(const PcgDev& s, int sys, int pc_begin
   return o;
 }
 
-__device__ __forceinline__ void slot_range(int i, int nfv, int nfe, int64_t& base, int& cnt) {
-  if (i < nfv) {
-    base = 4 * (int64_t)i;
-    cnt = 4;
-  } else if (i < nfv + nfe) {
-    base = 4 * (int64_t)nfv + 2 * (int64_t)(i - nfv);
-    cnt = 2;
-  } else {
-    base = 4 * (int64_t)nfv + 2 * (int64_t)nfe + (i - nfv - nfe);
-    cnt = 1;
-  }
-}
-
-__device__ __forceinline__ double slot_sum(const double* __restrict__ sl, int i, int nfv, int nfe) {
-  int64_t base;
-  int cnt;
-  slot_range(i, nfv, nfe, base, cnt);
-  double q = sl[base];
-  for (int k = 1; k < cnt; ++k) q += sl[base + k];
-  return q;
-}
-
 // ---------------------------------------------------------------------------
 // Double-double arithmetic for the accurate residual f - K x (error-free
 // transformations: Knuth's two-sum, FMA-based two-product).  Contraction of

@@ -23,6 +23,31 @@ struct GroupDev {
   const int32_t* cell;     // [npad] first density cell (global)
 };
 
+// Slots of free DOF i of a system: 4 per vertex DOF, 2 per edge DOF, 1 per
+// interior DOF, in that order.
+__device__ __forceinline__ void slot_range(int i, int nfv, int nfe, int64_t& base, int& cnt) {
+  if (i < nfv) {
+    base = 4 * (int64_t)i;
+    cnt = 4;
+  } else if (i < nfv + nfe) {
+    base = 4 * (int64_t)nfv + 2 * (int64_t)(i - nfv);
+    cnt = 2;
+  } else {
+    base = 4 * (int64_t)nfv + 2 * (int64_t)nfe + (i - nfv - nfe);
+    cnt = 1;
+  }
+}
+
+// Assembled value of DOF i: its slots summed in a fixed order.
+__device__ __forceinline__ double slot_sum(const double* __restrict__ sl, int i, int nfv, int nfe) {
+  int64_t base;
+  int cnt;
+  slot_range(i, nfv, nfe, base, cnt);
+  double q = sl[base];
+  for (int k = 1; k < cnt; ++k) q += sl[base + k];
+  return q;
+}
+
 // Iteration state shared by the PCG kernels.
 struct PcgDev {
   const SysDesc* sys;
@@ -126,5 +151,24 @@ void launch_mg_prolong_smooth(const MgChunk* ch, int n, const PcgDev& s, const d
 void launch_mg_prolong0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* e2,
                         hipStream_t st);
 void launch_mg_post0(const PcgDev& s, int it_k, int init, hipStream_t st);
+
+// ---- element-block additive Schwarz smoother (mto_mg.hip) ----
+// Per element column of group `gi`: the assembled operator restricted to the
+// element's free DOFs (own sum_s E_s K_s plus the shared-DOF entries of the
+// eight neighbours), inverted; binv [ne][ne][npad], zero rows/columns at
+// absent or supported DOFs.  groups: device array of all group views;
+// nbr [8][npad]: global element index of each neighbour (-1: none);
+// el_group / el_col: group and column of every global element.
+void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const int32_t* nbr, const int32_t* el_group,
+                      const int32_t* el_col, const double* E, double* binv, hipStream_t st);
+// slots = omega * B_e v_e for the running systems of the group's tiles
+void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, const PcgDev& s,
+                      double omega, hipStream_t st);
+// z = assembled slots (running systems)
+void launch_asm_z(const PcgDev& s, hipStream_t st);
+// q = r - assembled slots (running systems)
+void launch_asm_resid(const PcgDev& s, hipStream_t st);
+// z += assembled slots, partial sums of r.z (parity slot as k_mg_post0)
+void launch_asm_post(const PcgDev& s, int it_k, int init, hipStream_t st);
 
 }  // namespace mto

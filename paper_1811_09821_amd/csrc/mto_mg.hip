@@ -449,6 +449,196 @@ __global__ __launch_bounds__(1024) void k_mg_post0(PcgDev s, int it_k, int init)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Element-block additive Schwarz smoother for the hierarchic level.
+//
+// Point smoothers fail on this level once p >= 2 meets density contrast
+// inside an element: the near-null modes of a partly void element are
+// combinations of many of its edge and interior modes, which neither a
+// diagonal nor the vertex grid below captures.  Each block here is the
+// assembled operator restricted to all DOFs of one element, i.e. the
+// element's own sum_s E_s K_s plus, on the DOFs it shares, the entries of
+// its neighbours, inverted exactly once per design.  The smoother applies
+// omega * sum_e P_e^T B_e P_e.  Two elements whose blocks couple through K
+// lie within two elements of each other in both directions, so nine colours
+// separate the blocks and lambda_max(B K) <= 9: any omega < 2/9 gives a
+// convergent, symmetric smoother and keeps the V-cycle SPD.
+
+namespace {
+constexpr int ASM_BLOCK = 256;
+}
+
+template <int P>
+__global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restrict__ groups, int gi,
+                                                         const int32_t* __restrict__ nbr,
+                                                         const int32_t* __restrict__ el_group,
+                                                         const int32_t* __restrict__ el_col,
+                                                         const double* __restrict__ E, double* __restrict__ binv) {
+  constexpr int NE = ne_of(P);
+  constexpr int NEMAX = ne_of(MTO_MAX_P);
+  __shared__ double A[NE][NE + 1];
+  __shared__ double fcol[NE];
+  __shared__ double sc[NE];
+  __shared__ int gid[NE];
+  __shared__ int pos[NEMAX];
+  const GroupDev g = groups[gi];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < NE; a += ASM_BLOCK) gid[a] = g.gidx[a * g.npad + k];
+  const int cell = g.cell[k];
+  for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
+    const int a = idx / NE, b = idx - a * NE;
+    double v = 0.0;
+    for (int sc_ = 0; sc_ < g.S; ++sc_) v = fma(E[cell + sc_], g.ks[((int64_t)sc_ * NE + a) * NE + b], v);
+    A[a][b] = v;
+  }
+  __syncthreads();
+  // neighbours: add their entries on pairs of shared DOFs (matched by free index)
+  for (int m = 0; m < 8; ++m) {
+    const int ge = nbr[m * g.npad + k];
+    if (ge < 0) continue;  // uniform over the block
+    const GroupDev& gn = groups[el_group[ge]];
+    const int kn = el_col[ge];
+    const int nen = ne_of(gn.p);
+    for (int b = tid; b < nen; b += ASM_BLOCK) {
+      const int id = gn.gidx[b * gn.npad + kn];
+      int ps = -1;
+      if (id >= 0)
+        for (int a = 0; a < NE; ++a)
+          if (gid[a] == id) {
+            ps = a;
+            break;
+          }
+      pos[b] = ps;
+    }
+    __syncthreads();
+    const int celln = gn.cell[kn];
+    for (int idx = tid; idx < nen * nen; idx += ASM_BLOCK) {
+      const int a = idx / nen, b = idx - a * nen;
+      const int pa = pos[a], pb = pos[b];
+      if (pa < 0 || pb < 0) continue;
+      double v = 0.0;
+      for (int sc_ = 0; sc_ < gn.S; ++sc_) v = fma(E[celln + sc_], gn.ks[((int64_t)sc_ * nen + a) * nen + b], v);
+      A[pa][pb] += v;  // (a, b) -> (pa, pb) is one-to-one within a neighbour
+    }
+    __syncthreads();
+  }
+  // absent or supported DOFs, and DOFs with no stiffness at all (E_min = 0
+  // around them): identity rows, zero in the result; then symmetric scaling
+  for (int a = tid; a < NE; a += ASM_BLOCK)
+    if (!(A[a][a] > 0.0)) gid[a] = -1;
+  __syncthreads();
+  for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
+    const int a = idx / NE, b = idx - a * NE;
+    if (gid[a] < 0 || gid[b] < 0) A[a][b] = a == b ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int a = tid; a < NE; a += ASM_BLOCK) sc[a] = 1.0 / sqrt(A[a][a]);
+  __syncthreads();
+  for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
+    const int a = idx / NE, b = idx - a * NE;
+    A[a][b] *= sc[a] * sc[b];
+  }
+  __syncthreads();
+  // Gauss-Jordan inverse in place, no pivoting (the block is SPD)
+  for (int kk = 0; kk < NE; ++kk) {
+    const double piv = A[kk][kk];
+    __syncthreads();
+    for (int j = tid; j < NE; j += ASM_BLOCK) A[kk][j] = (j == kk ? 1.0 : A[kk][j]) / piv;
+    __syncthreads();
+    for (int i = tid; i < NE; i += ASM_BLOCK) fcol[i] = i == kk ? 0.0 : A[i][kk];
+    __syncthreads();
+    for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
+      const int i = idx / NE, j = idx - i * NE;
+      if (i != kk) A[i][j] = (j == kk ? 0.0 : A[i][j]) - fcol[i] * A[kk][j];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
+    const int a = idx / NE, b = idx - a * NE;
+    double v = 0.5 * (A[a][b] + A[b][a]) * sc[a] * sc[b];
+    if (gid[a] < 0 || gid[b] < 0) v = 0.0;
+    binv[(int64_t)idx * g.npad + k] = v;
+  }
+}
+
+// slots = omega * B_e v_e: one wave per tile, 16 element columns at a time;
+// lane = (row quarter, column).
+template <int P>
+__global__ __launch_bounds__(64) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
+                                                  const double* __restrict__ binv, const double* __restrict__ v,
+                                                  PcgDev s, double omega) {
+  constexpr int NE = ne_of(P);
+  __shared__ double vs[NE][17];
+  const Tile t = tiles[g.tile_begin + blockIdx.x];
+  if (s.status[t.sys] != SYS_RUNNING) return;
+  const int lane = threadIdx.x, c = lane & 15, qd = lane >> 4;
+  const double* __restrict__ vsys = v + t.dof_off;
+  double* __restrict__ sl = s.slots + t.slot_off;
+  for (int c0 = 0; c0 < t.count; c0 += 16) {
+    const bool valid = c0 + c < t.count;
+    const int col = t.elem_begin + c0 + (valid ? c : 0);
+    for (int r = qd; r < NE; r += 4) {
+      const int id = valid ? g.gidx[r * g.npad + col] : -1;
+      vs[r][c] = id >= 0 ? vsys[id] : 0.0;
+    }
+    __syncthreads();
+    for (int a = qd; a < NE; a += 4) {
+      const double* __restrict__ bp = binv + (int64_t)a * NE * g.npad + col;
+      double acc = 0.0;
+#pragma unroll 10
+      for (int b = 0; b < NE; ++b) acc = fma(bp[(int64_t)b * g.npad], vs[b][c], acc);
+      const int si = valid ? g.sidx[a * g.npad + col] : -1;
+      if (si >= 0) sl[si] = omega * acc;
+    }
+    __syncthreads();
+  }
+}
+
+// z = assembled slots
+__global__ __launch_bounds__(1024) void k_asm_z(PcgDev s) {
+  const Chunk ch = s.chunks[blockIdx.x];
+  if (!sys_running(s, ch.sys)) return;
+  const int i = ch.begin + threadIdx.x;
+  if (i >= ch.end) return;
+  s.z[ch.dof_off + i] = slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
+}
+
+// q = r - assembled slots
+__global__ __launch_bounds__(1024) void k_asm_resid(PcgDev s) {
+  const Chunk ch = s.chunks[blockIdx.x];
+  if (!sys_running(s, ch.sys)) return;
+  const int i = ch.begin + threadIdx.x;
+  if (i >= ch.end) return;
+  const int64_t o = ch.dof_off + i;
+  s.q[o] = s.r[o] - slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
+}
+
+// z += assembled slots; partial sums of r.z for the next PCG iteration
+__global__ __launch_bounds__(1024) void k_asm_post(PcgDev s, int it_k, int init) {
+  __shared__ double lds[20];
+  const Chunk ch = s.chunks[blockIdx.x];
+  if (!sys_running(s, ch.sys)) return;
+  const int par = init ? 0 : ((*s.it_base + it_k + 1) & 1);
+  const int i = ch.begin + threadIdx.x;
+  double arz = 0.0;
+  if (i < ch.end) {
+    const int64_t o = ch.dof_off + i;
+    const double zi = s.z[o] + slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
+    s.z[o] = zi;
+    arz = s.r[o] * zi;
+  }
+  for (int m = 32; m >= 1; m >>= 1) arz += __shfl_xor(arz, m);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) lds[wave] = arz;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
+    s.part_rz[par * s.n_chunks + blockIdx.x] = t;
+  }
+}
+
 // ---- launchers ----
 void launch_mg_assemble1(const MgChunk* ch, int n, const MgElem* elems, const double* kv, const double* E,
                          const int32_t* vfree, double* A, double* mask, hipStream_t st) {
@@ -486,5 +676,38 @@ void launch_mg_prolong0(const MgChunk* ch, int n, const PcgDev& s, const int32_t
 void launch_mg_post0(const PcgDev& s, int it_k, int init, hipStream_t st) {
   hipLaunchKernelGGL(k_mg_post0, dim3(s.n_chunks), dim3(1024), 0, st, s, it_k, init);
 }
+
+void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const int32_t* nbr, const int32_t* el_group,
+                      const int32_t* el_col, const double* E, double* binv, hipStream_t st) {
+  if (g.n_elems == 0) return;
+  const dim3 grid(g.n_elems), block(ASM_BLOCK);
+  switch (g.p) {
+    case 1: hipLaunchKernelGGL(k_asm_block<1>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+    case 2: hipLaunchKernelGGL(k_asm_block<2>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+    case 3: hipLaunchKernelGGL(k_asm_block<3>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+    default: hipLaunchKernelGGL(k_asm_block<4>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+  }
+}
+void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, const PcgDev& s,
+                      double omega, hipStream_t st) {
+  if (g.n_tiles == 0) return;
+  const dim3 grid(g.n_tiles), block(64);
+  switch (g.p) {
+    case 1: hipLaunchKernelGGL(k_asm_apply<1>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
+    case 2: hipLaunchKernelGGL(k_asm_apply<2>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
+    case 3: hipLaunchKernelGGL(k_asm_apply<3>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
+    default: hipLaunchKernelGGL(k_asm_apply<4>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
+  }
+}
+void launch_asm_z(const PcgDev& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_asm_z, dim3(s.n_chunks), dim3(1024), 0, st, s);
+}
+void launch_asm_resid(const PcgDev& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_asm_resid, dim3(s.n_chunks), dim3(1024), 0, st, s);
+}
+void launch_asm_post(const PcgDev& s, int it_k, int init, hipStream_t st) {
+  hipLaunchKernelGGL(k_asm_post, dim3(s.n_chunks), dim3(1024), 0, st, s, it_k, init);
+}
+
 
 }  // namespace mto

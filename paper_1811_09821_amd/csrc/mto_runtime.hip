@@ -61,6 +61,9 @@ struct GroupHost {
   double flops = 0.0;  // 2 S ne^2 per element column
   std::vector<double> kv;  // host copy of the vertex-block table
   int kv_off = 0;
+  // element-block Schwarz smoother: inverses [ne][ne][npad], neighbours [8][npad]
+  double* binv = nullptr;
+  int32_t* nbr = nullptr;
 };
 
 // Geometric hierarchy of the multigrid preconditioner (levels 1..L).
@@ -123,6 +126,10 @@ struct mto_plan {
   double *b_u = nullptr, *b_c = nullptr, *b_g = nullptr;
   hipGraphExec_t setup_exec = nullptr, resid_exec = nullptr, restart_exec = nullptr, out_exec = nullptr;
   MgHost mg;
+  // element-block Schwarz smoother (MTO_PRECOND_MG_ASM)
+  GroupDev* d_groups = nullptr;
+  int32_t *d_el_group = nullptr, *d_el_col = nullptr;
+  double asm_omega = 0.0;
 
   PcgDev pcg() const {
     PcgDev s{};
@@ -405,6 +412,53 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
   return check_launch("multigrid setup");
 }
 
+// Tables of the element-block Schwarz smoother: the group and column of every
+// element of every instance, each column's eight neighbours, and the block
+// inverses (filled per design by the setup).
+int build_asm(mto_plan* P, const std::vector<InstanceHost>& I) {
+  const int n = P->n_inst;
+  std::vector<int64_t> base(n + 1, 0);
+  for (int i = 0; i < n; ++i) base[i + 1] = base[i] + (int64_t)I[i].nelx * I[i].nely;
+  std::vector<int32_t> el_group(base[n], -1), el_col(base[n], -1);
+  std::map<std::pair<int, int>, int> gid;
+  for (size_t g = 0; g < P->groups.size(); ++g) gid[{P->groups[g].p, P->groups[g].d}] = (int)g;
+  std::vector<int> next(P->groups.size(), 0);
+  for (int i = 0; i < n; ++i)
+    for (size_t e = 0; e < I[i].p.size(); ++e) {
+      const int g = gid[{(int)I[i].p[e], (int)I[i].d[e]}];
+      el_group[base[i] + e] = g;
+      el_col[base[i] + e] = next[g]++;  // group columns: instance order, then element order
+    }
+  std::vector<GroupDev> gd;
+  int rc;
+  for (size_t g = 0; g < P->groups.size(); ++g) {
+    GroupHost& G = P->groups[g];
+    std::vector<int32_t> nbr(8 * (size_t)G.npad, -1);
+    for (int i = 0; i < n; ++i) {
+      const int nx = I[i].nelx, ny = I[i].nely;
+      for (int e = 0; e < nx * ny; ++e) {
+        if (el_group[base[i] + e] != (int)g) continue;
+        const int k = el_col[base[i] + e], ex = e % nx, ey = e / nx;
+        int m = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (!dx && !dy) continue;
+            const int x = ex + dx, y = ey + dy;
+            if (x >= 0 && x < nx && y >= 0 && y < ny) nbr[(size_t)m * G.npad + k] = (int32_t)(base[i] + y * nx + x);
+            ++m;
+          }
+      }
+    }
+    if ((rc = dev_upload(P, &G.nbr, nbr)) || (rc = dev_alloc(P, &G.binv, (size_t)G.ne * G.ne * G.npad))) return rc;
+    gd.push_back(P->gdev(G));
+  }
+  if ((rc = dev_upload(P, &P->d_groups, gd)) || (rc = dev_upload(P, &P->d_el_group, el_group)) ||
+      (rc = dev_upload(P, &P->d_el_col, el_col)))
+    return rc;
+  P->asm_omega = P->prm.mg_omega > 0.0 ? P->prm.mg_omega : 2.0 / (9.0 * 1.05);
+  return MTO_OK;
+}
+
 int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan** out) {
   if (!out) return fail(MTO_EINVAL, "out is NULL");
   *out = nullptr;
@@ -414,8 +468,10 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     return fail(MTO_EINVAL, "params out of range (rtol > 0, 0 <= Emin <= E0, -1 < nu < 0.5, q >= 1)");
   if (prm->kernel_path != MTO_PATH_MFMA && prm->kernel_path != MTO_PATH_PLAIN)
     return fail(MTO_EINVAL, "unknown kernel_path");
-  if (prm->precond != MTO_PRECOND_JACOBI && prm->precond != MTO_PRECOND_MG)
+  if (prm->precond != MTO_PRECOND_JACOBI && prm->precond != MTO_PRECOND_MG && prm->precond != MTO_PRECOND_MG_ASM)
     return fail(MTO_EINVAL, "unknown precond");
+  if (prm->precond == MTO_PRECOND_MG_ASM && !(prm->mg_omega < 2.0 / 9.0))
+    return fail(MTO_EINVAL, "Schwarz smoother weight must be below 2/9 (<= 0 selects the default)");
   std::vector<InstanceHost> I(n);
   for (int i = 0; i < n; ++i) {
     std::string err;
@@ -629,7 +685,8 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       return cleanup(fail(MTO_EHIP, "hipEventCreate failed"));
   if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(fail(MTO_EHIP, "hipStreamCreate failed"));
-  if (P->prm.precond == MTO_PRECOND_MG && (rc = build_mg(P, I))) return cleanup(rc);
+  if (P->prm.precond != MTO_PRECOND_JACOBI && (rc = build_mg(P, I))) return cleanup(rc);
+  if (P->prm.precond == MTO_PRECOND_MG_ASM && (rc = build_asm(P, I))) return cleanup(rc);
   if ((rc = rebuild_tiles(P))) return cleanup(rc);
   HIP_TRY(hipDeviceSynchronize());
   *out = P;
@@ -662,10 +719,13 @@ void enq_mg_setup(mto_plan* P, hipStream_t st) {
 // post-smoothing on every level, dense solve on the coarsest; the last kernel
 // also forms the partial sums of r.z.
 void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_t st);
-void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
+
+// The coarse-grid correction shared by both smoothers: restrict r - A0 z
+// (A0 z in the slots) to the vertex grid, one V-cycle over levels 1..L,
+// prolongate and add to z.
+void enq_coarse_correction(mto_plan* P, hipStream_t st) {
   const MgHost& M = P->mg;
   const PcgDev s = P->pcg();
-  enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
   launch_mg_restrict0(M.sysc(1), M.sys_count[0], s, M.vfree, M.dinv, M.r, M.e, st);
   for (int l = 2; l <= M.L; ++l)
     launch_mg_restrict(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, st);
@@ -673,6 +733,27 @@ void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
   for (int l = M.L - 1; l >= 1; --l)
     launch_mg_prolong_smooth(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, M.e2, st);
   launch_mg_prolong0(M.sysc(1), M.sys_count[0], s, M.vfree, M.e2, st);
+}
+
+// z = M r: one V-cycle.  Level-0 smoothing is Jacobi-type (z = D0^-1 r is
+// already in z; l1 or damped post-sweep) or the element-block Schwarz
+// smoother (pre: z = w B r; post: z += w B (r - A0 z)).  The last kernel also
+// forms the partial sums of r.z.
+void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
+  const PcgDev s = P->pcg();
+  if (P->prm.precond == MTO_PRECOND_MG_ASM) {
+    for (auto& g : P->groups) launch_asm_apply(P->gdev(g), P->d_tiles, g.binv, P->r, s, P->asm_omega, st);
+    launch_asm_z(s, st);
+    enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
+    enq_coarse_correction(P, st);
+    enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
+    launch_asm_resid(s, st);
+    for (auto& g : P->groups) launch_asm_apply(P->gdev(g), P->d_tiles, g.binv, P->q, s, P->asm_omega, st);
+    launch_asm_post(s, it_k, init, st);
+    return;
+  }
+  enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
+  enq_coarse_correction(P, st);
   enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
   launch_mg_post0(s, it_k, init, st);
 }
@@ -680,11 +761,18 @@ void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
 void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st) {
   const PcgDev s = P->pcg();
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
-  const bool mg = P->prm.precond == MTO_PRECOND_MG;
-  const bool l1 = mg && !(P->prm.mg_omega > 0.0);  // l1-Jacobi level-0 smoother
+  const bool mg = P->prm.precond != MTO_PRECOND_JACOBI;
+  // l1-Jacobi level-0 smoother of MTO_PRECOND_MG unless a damping factor is set
+  const bool l1 = P->prm.precond == MTO_PRECOND_MG && !(P->prm.mg_omega > 0.0);
+  const bool damped = P->prm.precond == MTO_PRECOND_MG && !l1;
   for (auto& g : P->groups)
     launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, l1 ? g.kabs : g.kdiag, st);
-  launch_dinv(s, P->dinv, (mg && !l1) ? P->prm.mg_omega : 1.0, st);
+  launch_dinv(s, P->dinv, damped ? P->prm.mg_omega : 1.0, st);
+  if (P->prm.precond == MTO_PRECOND_MG_ASM)
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+      const GroupHost& g = P->groups[gi];
+      launch_asm_block(P->gdev(g), (int)gi, P->d_groups, g.nbr, P->d_el_group, P->d_el_col, P->E, g.binv, st);
+    }
   if (mg) enq_mg_setup(P, st);
   // PCG iterates on the correction x (from 0); the solution is xs_hi + xs_lo
   launch_fill(P->x, 0.0, P->n_vec, st);
@@ -707,7 +795,7 @@ void enq_chunk(mto_plan* P, int G, hipStream_t st) {
     enq_elem_all(P, P->p, ELEM_PCG, k, st);
     launch_dof1(s, k, st);
     launch_dof2(s, k, st);
-    if (P->prm.precond == MTO_PRECOND_MG) enq_vcycle(P, k, 0, st);
+    if (P->prm.precond != MTO_PRECOND_JACOBI) enq_vcycle(P, k, 0, st);
   }
   launch_advance(s, G, st);
 }
@@ -732,7 +820,7 @@ void enq_cycle_end(mto_plan* P, hipStream_t st) {
 void enq_restart(mto_plan* P, hipStream_t st) {
   launch_init(P->pcg(), 2, st);
   launch_sys_setup(P->pcg(), P->prm.rtol, st);
-  if (P->prm.precond == MTO_PRECOND_MG) enq_vcycle(P, 0, 1, st);
+  if (P->prm.precond != MTO_PRECOND_JACOBI) enq_vcycle(P, 0, 1, st);
 }
 
 void enq_outputs(mto_plan* P, double* u, double* c, double* g, hipStream_t st) {
@@ -1145,7 +1233,7 @@ int mto_time_contraction(mto_plan* P, const double* rho, int32_t reps, int32_t i
     }
     launch_dof1(s, k, st);
     launch_dof2(s, k, st);
-    if (P->prm.precond == MTO_PRECOND_MG) enq_vcycle(P, k, 0, st);
+    if (P->prm.precond != MTO_PRECOND_JACOBI) enq_vcycle(P, k, 0, st);
     if (k == G - 1 || i == reps - 1) launch_advance(s, k + 1, st);
   }
   HIP_TRY(hipStreamSynchronize(st));

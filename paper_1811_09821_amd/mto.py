@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmto.so")
 
 MTO_OK, MTO_EINVAL, MTO_ESINGULAR, MTO_ENOCONV, MTO_EBREAKDOWN, MTO_EHIP, MTO_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 PATH_MFMA, PATH_PLAIN = 0, 1
-PRECOND_JACOBI, PRECOND_MG = 0, 1
+PRECOND_JACOBI, PRECOND_MG, PRECOND_MG_ASM = 0, 1, 2
 ERROR_NAMES = {MTO_EINVAL: "MTO_EINVAL", MTO_ESINGULAR: "MTO_ESINGULAR", MTO_ENOCONV: "MTO_ENOCONV",
                MTO_EBREAKDOWN: "MTO_EBREAKDOWN", MTO_EHIP: "MTO_EHIP", MTO_ENOMEM: "MTO_ENOMEM"}
 

@@ -157,14 +157,31 @@ def test_solve_parity(cuda, name):
     check_solution(plan, prs, u, c, g, st)
 
 
-@pytest.mark.parametrize("name", ["mbb20x10", "mixed_3loads", "uniform_p4d5"])
-def test_solve_parity_multigrid(cuda, name):
-    """The multigrid-preconditioned PCG reaches the same solution."""
+@pytest.mark.parametrize("precond", [1, 2])
+@pytest.mark.parametrize("name", ["mbb20x10", "mixed_3loads", "uniform_p4d5", "cantilever_field"])
+def test_solve_parity_multigrid(cuda, name, precond):
+    """The multigrid-preconditioned PCG (l1-Jacobi or element-block Schwarz
+    smoothing on the hierarchic level) reaches the same solution."""
     prs = CASES[name]()
-    plan = mto().Plan(prs, precond=1)
+    plan = mto().Plan(prs, precond=precond)
     rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
     u, c, g, st = plan.solve(rho)
     check_solution(plan, prs, u, c, g, st)
+
+
+def test_schwarz_multigrid_cuts_iterations(cuda):
+    """On a p = 3, d = 4 cantilever with a smoothed density field the
+    element-block Schwarz V-cycle needs a small fraction of the Jacobi
+    iterations, and both reach the same solution."""
+    m = mto()
+    pr = P.cantilever_uniform(40, 20, 3, 4, sigma=2.0, volfrac=0.4, seed=7)
+    rho = torch.tensor(pr.rho, device=cuda)
+    uj, cj, gj, sj = m.Plan(pr).solve(rho)
+    us, cs, gs, ss = m.Plan(pr, precond=m.PRECOND_MG_ASM).solve(rho)
+    print(f"\niterations: Jacobi {sj['iterations']}, Schwarz multigrid {ss['iterations']}", flush=True)
+    assert max(ss["iterations"]) * 8 < max(sj["iterations"])
+    assert rel(us.cpu().numpy(), uj.cpu().numpy()) < 1e-9
+    assert abs(cs.item() - cj.item()) <= 1e-9 * abs(cj.item())
 
 
 def test_solve_parity_plain_path(cuda):
