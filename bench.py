@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, help="workload 1..5 (default 2)")
     ap.add_argument("--path", choices=["mfma", "plain"], default="mfma")
+    ap.add_argument("--precond", choices=["schwarz-mg", "jacobi", "l1-mg"], default="schwarz-mg",
+                    help="PCG preconditioner (default: multigrid with element-block Schwarz smoothing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--compare-plain", action="store_true", help="also time the plain per-element path")
@@ -96,7 +98,8 @@ def main():
     dev = torch.device("cuda:0")
     prs, desc = workload(args.config)
     path = mto.PATH_MFMA if args.path == "mfma" else mto.PATH_PLAIN
-    plan = mto.Plan(prs, kernel_path=path)
+    precond = {"jacobi": mto.PRECOND_JACOBI, "l1-mg": mto.PRECOND_MG, "schwarz-mg": mto.PRECOND_MG_ASM}[args.precond]
+    plan = mto.Plan(prs, kernel_path=path, precond=precond)
     rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=dev)
     tune = ""
     if path == mto.PATH_MFMA and not args.no_autotune:
@@ -153,6 +156,7 @@ def main():
         "data": "synthetic (seeded Gaussian-smoothed density field; the paper's designs exist only as figures)",
         "config": {"workload": desc, "designs_per_step": n_designs, "n_free_dofs": plan.info["n_free_total"],
                    "n_cells": plan.info["n_cells"], "rtol": 1e-11, "kernel_path": args.path,
+                   "preconditioner": args.precond,
                    "parallelism": "single GPU"},
         "pcg_iterations": stats["iterations"] if stats else None,
         "true_rel_residual": stats["true_rel_residual"] if stats else None,
@@ -163,7 +167,7 @@ def main():
         out["autotune"] = tune.strip().splitlines()
 
     if args.compare_plain and path == mto.PATH_MFMA:
-        plain = mto.Plan(prs, kernel_path=mto.PATH_PLAIN)
+        plain = mto.Plan(prs, kernel_path=mto.PATH_PLAIN, precond=precond)
         plain.capture(rho)
         plain.replay()
         torch.cuda.synchronize()

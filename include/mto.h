@@ -118,7 +118,8 @@ typedef struct {
   double rtol;    /* PCG stop: ||r||_2 <= rtol ||f||_2 */
   int32_t max_iter;         /* PCG iteration cap per system (<= 0: 20 * n_free) */
   int32_t kernel_path;      /* MTO_PATH_* */
-  int32_t iters_per_launch; /* PCG iterations per captured graph launch (<= 0: 32) */
+  int32_t iters_per_launch; /* PCG iterations per captured graph launch (<= 0: 32 with Jacobi,
+                               8 with a multigrid preconditioner) */
   int32_t max_restarts;     /* refinement restarts from the true residual when it misses rtol (< 0: 3) */
   int32_t precond;          /* MTO_PRECOND_* */
   double mg_omega;          /* level-0 smoother weight.  MTO_PRECOND_MG: damped Jacobi with this

@@ -101,7 +101,8 @@ struct SysDesc {
 // ---- geometric multigrid preconditioner (levels >= 1: vertex grids) ----
 
 constexpr int MG_CHUNK = 256;      // nodes per level-kernel block
-constexpr int MG_COARSE_MAX = 256; // DOFs of the coarsest grid (dense inverse)
+constexpr int MG_COARSE_MAX = 3000;  // DOFs of the coarsest grid (dense inverse from a band Cholesky)
+constexpr int MG_BAND_MAX = 88;      // its band width: the Cholesky window of (b+1)^2 doubles fits 64 KB of LDS
 
 // Work unit of the level kernels: nodes [node_begin, node_end) of the level
 // grid of one system (vector kernels) or one instance (operator kernels; sys
@@ -112,6 +113,7 @@ struct MgChunk {
   int64_t fvec, fop;    // finer level (level >= 2)
   int64_t cvec, cop;    // coarser level (absent at the coarsest: -1)
   int64_t dense_off;    // coarsest level: offset of the instance's dense inverse
+  int64_t band_off;     // coarsest level: offset of the instance's band Cholesky factor
   int64_t dof_off;      // level 1 only: the system's level-0 offsets
   int64_t slot_off;
   int64_t elem_off;     // level 1 only: the instance's first element in the MgElem table

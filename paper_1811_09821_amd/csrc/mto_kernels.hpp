@@ -139,12 +139,18 @@ void launch_mg_assemble1(const MgChunk* ch, int n, const MgElem* elems, const do
                          const int32_t* vfree, double* A, double* mask, hipStream_t st);
 void launch_mg_l1(const MgChunk* ch, int n, const double* A, double* dinv, hipStream_t st);
 void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_t st);
-void launch_mg_coarse_setup(const MgChunk* ch, int n, const double* A, double* dense, hipStream_t st);
+// coarsest level of each instance: band Cholesky (LDS window), dense inverse, symmetrised;
+// nmax / bmax: largest DOF count and band width over the instances
+void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* dense,
+                            hipStream_t st);
 void launch_mg_restrict0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* dinv,
                          double* r1, double* e1, hipStream_t st);
-void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
-                        const double* dinv, double* r, double* e, hipStream_t st);
-void launch_mg_coarse_solve(const MgChunk* ch, int n, const PcgDev& s, const double* dense, const double* r,
+// t = r - A e on a level (l >= 1); then r_{l+1} = P~^T t, e_{l+1} = D^-1 r_{l+1}
+void launch_mg_resid(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* r, const double* e,
+                     double* t, hipStream_t st);
+void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* mask, const double* dinv,
+                        const double* t, double* r, double* e, hipStream_t st);
+void launch_mg_coarse_solve(const MgChunk* ch, int n, int nmax, const PcgDev& s, const double* dense, const double* r,
                             double* e2, hipStream_t st);
 void launch_mg_prolong_smooth(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
                               const double* dinv, const double* r, const double* e, double* e2, hipStream_t st);

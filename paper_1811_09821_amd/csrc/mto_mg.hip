@@ -209,51 +209,138 @@ __global__ __launch_bounds__(MGB) void k_mg_rap(const MgChunk* __restrict__ chun
     for (int c = 0; c < 4; ++c) A[node * 36 + k * 4 + c] = acc[k][c];
 }
 
-// Dense inverse of the coarsest operator of one instance (one block; the
-// grid fits in one chunk): Gauss-Jordan without pivoting (the operator is
-// SPD), then symmetrised.
-__global__ __launch_bounds__(MGB) void k_mg_coarse_setup(const MgChunk* __restrict__ chunks,
-                                                         const double* __restrict__ A, double* __restrict__ dense) {
+// ---- the coarsest level: dense inverse from a banded Cholesky factor ----
+//
+// The coarsest grid (up to MG_COARSE_MAX DOFs) is solved exactly by a dense
+// inverse, formed once per design: its DOFs are renumbered with the shorter
+// side of the grid running fastest, which makes the operator banded with
+// lower bandwidth b = 2 m + 5 (m elements along the short side); a
+// right-looking band Cholesky runs in one block with a sliding window of
+// b + 1 rows in LDS; then every column of the inverse is one forward and one
+// backward band substitution, one thread per column; finally symmetrised.
+
+// node q couples to q +- (m + 2) at most (m = elements along the short side),
+// so DOF 2 q + c couples to DOFs at most 2 (m + 2) + 1 away
+__device__ __forceinline__ int band_width(const MgChunk& ch) { return 2 * min(ch.nx, ch.ny) + 5; }
+
+// node of band position q (the shorter side runs fastest)
+__device__ __forceinline__ void band_node(const MgChunk& ch, int q, int& ix, int& iy) {
+  if (ch.ny <= ch.nx) {
+    ix = q / (ch.ny + 1);
+    iy = q - ix * (ch.ny + 1);
+  } else {
+    iy = q / (ch.nx + 1);
+    ix = q - iy * (ch.nx + 1);
+  }
+}
+
+// entry (d1, d2) of the coarsest operator in band numbering (DOF 2 q + c)
+__device__ __forceinline__ double band_entry(const MgChunk& ch, const double* __restrict__ A, int d1, int d2) {
+  int x1, y1, x2, y2;
+  band_node(ch, d1 >> 1, x1, y1);
+  band_node(ch, d2 >> 1, x2, y2);
+  const int dx = x2 - x1, dy = y2 - y1;
+  if (dx < -1 || dx > 1 || dy < -1 || dy > 1) return 0.0;
+  const int64_t node = ch.op + (int64_t)y1 * (ch.nx + 1) + x1;
+  return A[node * 36 + ((dy + 1) * 3 + (dx + 1)) * 4 + (d1 & 1) * 2 + (d2 & 1)];
+}
+
+// Band Cholesky of one instance's coarsest operator: band[j][k] = L[j][j - k].
+// Two barriers per column: (1) scale column j below the diagonal and retire
+// row j to global memory; (2) the rank-1 update of the window and the load of
+// row j + b + 1 into the slot row j has left.
+__global__ __launch_bounds__(1024) void k_mg_coarse_chol(const MgChunk* __restrict__ chunks,
+                                                        const double* __restrict__ A, double* __restrict__ band) {
+  extern __shared__ double W[];  // window [(b + 1)][(b + 1)], row i in slot i % (b + 1)
   const MgChunk ch = chunks[blockIdx.x];
-  const int N = ch.node_end - ch.node_begin;  // the whole grid
-  const int nx = ch.nx;
-  const int n = 2 * N;
-  double* W = dense + ch.dense_off;
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) W[idx] = 0.0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const int ix = i % (nx + 1), iy = i / (nx + 1);
-    for (int k = 0; k < 9; ++k) {
-      const int jx = ix + k % 3 - 1, jy = iy + k / 3 - 1;
-      if (jx < 0 || jx > nx || jy < 0 || jy > ch.ny) continue;
-      const int j = jy * (nx + 1) + jx;
-      for (int c = 0; c < 2; ++c)
-        for (int cc = 0; cc < 2; ++cc) W[(2 * i + c) * n + 2 * j + cc] = A[(ch.op + i) * 36 + k * 4 + c * 2 + cc];
-    }
-  }
-  __shared__ double piv;
-  for (int k = 0; k < n; ++k) {
-    __syncthreads();
-    if (threadIdx.x == 0) piv = W[k * n + k];
-    __syncthreads();
-    const double p = piv;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) W[k * n + j] = (j == k ? 1.0 : W[k * n + j]) / p;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      if (i == k) continue;
-      const double f = W[i * n + k];
-      for (int j = 0; j < n; ++j) W[i * n + j] = (j == k ? 0.0 : W[i * n + j]) - f * W[k * n + j];
-    }
+  const int n = 2 * (ch.node_end - ch.node_begin);
+  const int b = band_width(ch), w = b + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* __restrict__ out = band + ch.band_off;
+  for (int idx = tid; idx < w * w; idx += nt) {
+    const int r = idx / w, k = idx - r * w;
+    W[idx] = (r < n && r - k >= 0) ? band_entry(ch, A, r, r - k) : 0.0;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-    const int i = idx / n, j = idx % n;
-    if (i < j) {
-      const double v = 0.5 * (W[i * n + j] + W[j * n + i]);
-      W[i * n + j] = v;
-      W[j * n + i] = v;
+  for (int j = 0; j < n; ++j) {
+    const int sj = j % w;
+    const double d = sqrt(W[sj * w]);
+    const int m = min(b, n - 1 - j);
+    for (int ii = tid; ii < m; ii += nt) {
+      const int i = j + 1 + ii;
+      W[(i % w) * w + (i - j)] /= d;
     }
+    for (int k = tid; k < w; k += nt) out[(int64_t)j * w + k] = k == 0 ? d : W[sj * w + k];
+    __syncthreads();
+    for (int idx = tid; idx < m * m; idx += nt) {
+      const int ii = idx / m, kk = idx - ii * m;
+      if (kk > ii) continue;
+      const int i = j + 1 + ii, k = j + 1 + kk;
+      W[(i % w) * w + (i - k)] -= W[(i % w) * w + (i - j)] * W[(k % w) * w + (k - j)];
+    }
+    const int r = j + w;  // first touched by step j + 1
+    for (int k = tid; k < w; k += nt) W[sj * w + k] = (r < n && r - k >= 0) ? band_entry(ch, A, r, r - k) : 0.0;
+    __syncthreads();
   }
+}
+
+// Column c of the inverse (band numbering) per wave: y = L^-1 e_c, then
+// x = L^-T y, held in LDS; each substitution step is a band dot product
+// spread over the 64 lanes.  Stored as row c (the inverse is symmetric, and
+// rows are contiguous).
+constexpr int MG_INV_WAVES = 2;
+
+__global__ __launch_bounds__(64 * MG_INV_WAVES) void k_mg_coarse_inv(const MgChunk* __restrict__ chunks,
+                                                                     const double* __restrict__ band,
+                                                                     double* __restrict__ dense, int nmax) {
+  extern __shared__ double xs_all[];  // [MG_INV_WAVES][nmax]
+  const MgChunk ch = chunks[blockIdx.y];
+  const int n = 2 * (ch.node_end - ch.node_begin);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * MG_INV_WAVES + wave;
+  if (c >= n) return;  // whole wave
+  const int b = band_width(ch), w = b + 1;
+  const double* __restrict__ L = band + ch.band_off;
+  double* xs = xs_all + wave * nmax;
+  for (int i = lane; i < n; i += 64) xs[i] = 0.0;
+  // forward: rows c .. n-1 (y_i = 0 above c)
+  for (int i = c; i < n; ++i) {
+    double acc = 0.0;
+    for (int k = i - 1 - lane; k >= max(c, i - b); k -= 64) acc = fma(L[(int64_t)i * w + (i - k)], xs[k], acc);
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+    const double yi = ((i == c ? 1.0 : 0.0) - acc) / L[(int64_t)i * w];
+    if (lane == 0) xs[i] = yi;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+  // backward: rows n-1 .. 0
+  for (int i = n - 1; i >= 0; --i) {
+    double acc = 0.0;
+    const int kend = min(n - 1, i + b);
+    for (int k = i + 1 + lane; k <= kend; k += 64) acc = fma(L[(int64_t)k * w + (k - i)], xs[k], acc);
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+    const double xi = (xs[i] - acc) / L[(int64_t)i * w];
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) xs[i] = xi;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+  double* __restrict__ X = dense + ch.dense_off + (int64_t)c * n;
+  for (int i = lane; i < n; i += 64) X[i] = xs[i];
+}
+
+// X = (X + X^T) / 2
+__global__ __launch_bounds__(256) void k_mg_coarse_sym(const MgChunk* __restrict__ chunks, double* __restrict__ dense) {
+  const MgChunk ch = chunks[blockIdx.y];
+  const int n = 2 * (ch.node_end - ch.node_begin);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+  if (j <= i) return;
+  double* __restrict__ X = dense + ch.dense_off;
+  const double v = 0.5 * (X[(int64_t)i * n + j] + X[(int64_t)j * n + i]);
+  X[(int64_t)i * n + j] = v;
+  X[(int64_t)j * n + i] = v;
 }
 
 // Level 0 -> 1: t = r - A0 z at the vertex DOFs (A0 z in the slots), injected;
@@ -278,15 +365,35 @@ __global__ __launch_bounds__(MGB) void k_mg_restrict0(const MgChunk* __restrict_
   }
 }
 
-// Level l-1 -> l (l >= 2): r_l = P~^T (r - A e) of the finer level; e_l = D^-1 r_l.
-__global__ __launch_bounds__(MGB) void k_mg_restrict(const MgChunk* __restrict__ chunks, PcgDev s,
-                                                     const double* __restrict__ A, const double* __restrict__ mask,
-                                                     const double* __restrict__ dinv, double* __restrict__ r,
-                                                     double* __restrict__ e) {
-  const MgChunk ch = chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;
-  const int n = ch.node_begin + threadIdx.x;
-  if (n >= ch.node_end) return;
+// ---- per-node steps of levels >= 1 (shared by the one-level kernels and
+// the fused coarse cycle) ----
+
+// Residual of a level after its pre-smoothing: t = r - A e.
+__device__ __forceinline__ void mg_resid_node(const MgChunk& ch, int n, const double* __restrict__ A,
+                                              const double* __restrict__ r, const double* __restrict__ e,
+                                              double* __restrict__ t) {
+  const int nx = ch.nx, ny = ch.ny;
+  const int ix = n % (nx + 1), iy = n / (nx + 1);
+  const int64_t node = ch.op + n, v = ch.vec + n;
+  double t0 = r[v * 2], t1 = r[v * 2 + 1];
+  for (int k = 0; k < 9; ++k) {
+    const int jx = ix + k % 3 - 1, jy = iy + k / 3 - 1;
+    if (jx < 0 || jx > nx || jy < 0 || jy > ny) continue;
+    const int64_t jv = ch.vec + (int64_t)jy * (nx + 1) + jx;
+    const double* a = A + node * 36 + k * 4;
+    const double ej0 = e[jv * 2], ej1 = e[jv * 2 + 1];
+    t0 -= a[0] * ej0 + a[1] * ej1;
+    t1 -= a[2] * ej0 + a[3] * ej1;
+  }
+  t[v * 2] = t0;
+  t[v * 2 + 1] = t1;
+}
+
+// Restriction to this level: r = P~^T t of the finer level's residual, and
+// the pre-smoothing from zero e = D^-1 r.
+__device__ __forceinline__ void mg_restrict_node(const MgChunk& ch, int n, const double* __restrict__ mask,
+                                                 const double* __restrict__ dinv, const double* __restrict__ t,
+                                                 double* __restrict__ r, double* __restrict__ e) {
   const int nx = ch.nx, fnx = ch.fnx, fny = ch.fny;
   const int cx = n % (nx + 1), cy = n / (nx + 1);
   double acc0 = 0.0, acc1 = 0.0;
@@ -303,19 +410,9 @@ __global__ __launch_bounds__(MGB) void k_mg_restrict(const MgChunk* __restrict__
       if (wx == 0.0) continue;
       const int64_t fo = (int64_t)fy * (fnx + 1) + fx;
       const int64_t fi = ch.fop + fo, fv = ch.fvec + fo;
-      double t0 = r[fv * 2], t1 = r[fv * 2 + 1];
-      for (int k = 0; k < 9; ++k) {
-        const int jx = fx + k % 3 - 1, jy = fy + k / 3 - 1;
-        if (jx < 0 || jx > fnx || jy < 0 || jy > fny) continue;
-        const int64_t jv = ch.fvec + (int64_t)jy * (fnx + 1) + jx;
-        const double* a = A + fi * 36 + k * 4;
-        const double ej0 = e[jv * 2], ej1 = e[jv * 2 + 1];
-        t0 -= a[0] * ej0 + a[1] * ej1;
-        t1 -= a[2] * ej0 + a[3] * ej1;
-      }
       const double w = wx * wy;
-      acc0 += w * mask[fi * 2] * t0;
-      acc1 += w * mask[fi * 2 + 1] * t1;
+      acc0 += w * mask[fi * 2] * t[fv * 2];
+      acc1 += w * mask[fi * 2 + 1] * t[fv * 2 + 1];
     }
   }
   const int64_t node = ch.op + n, v = ch.vec + n;
@@ -325,34 +422,13 @@ __global__ __launch_bounds__(MGB) void k_mg_restrict(const MgChunk* __restrict__
   e[v * 2 + 1] = dinv[node * 2 + 1] * acc1;
 }
 
-// Coarsest level: e2 = A^-1 r (one block per system).
-__global__ __launch_bounds__(MGB) void k_mg_coarse_solve(const MgChunk* __restrict__ chunks, PcgDev s,
-                                                         const double* __restrict__ dense,
-                                                         const double* __restrict__ r, double* __restrict__ e2) {
-  const MgChunk ch = chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;
-  const int n = 2 * (ch.node_end - ch.node_begin);
-  const double* W = dense + ch.dense_off;
-  const double* rv = r + ch.vec * 2;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc = fma(W[i * n + j], rv[j], acc);
-    e2[ch.vec * 2 + i] = acc;
-  }
-}
-
-// Level l (>= 1) going up: e~ = e + P~ e2_coarse, then one l1-Jacobi sweep
+// Going up: e~ = e + P~ e2_coarse, then one l1-Jacobi sweep
 // e2 = e~ + D^-1 (r - A e~).
-__global__ __launch_bounds__(MGB) void k_mg_prolong_smooth(const MgChunk* __restrict__ chunks, PcgDev s,
-                                                           const double* __restrict__ A,
-                                                           const double* __restrict__ mask,
-                                                           const double* __restrict__ dinv,
-                                                           const double* __restrict__ r, const double* __restrict__ e,
-                                                           double* __restrict__ e2) {
-  const MgChunk ch = chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;
-  const int n = ch.node_begin + threadIdx.x;
-  if (n >= ch.node_end) return;
+__device__ __forceinline__ void mg_prolong_smooth_node(const MgChunk& ch, int n, const double* __restrict__ A,
+                                                       const double* __restrict__ mask,
+                                                       const double* __restrict__ dinv,
+                                                       const double* __restrict__ r, const double* __restrict__ e,
+                                                       double* __restrict__ e2) {
   const int nx = ch.nx, ny = ch.ny, cnx = ch.cnx;
   const int ix = n % (nx + 1), iy = n / (nx + 1);
   double et[9][2];
@@ -392,6 +468,64 @@ __global__ __launch_bounds__(MGB) void k_mg_prolong_smooth(const MgChunk* __rest
   }
   e2[v * 2] = et[4][0] + dinv[node * 2] * t0;
   e2[v * 2 + 1] = et[4][1] + dinv[node * 2 + 1] * t1;
+}
+
+__global__ __launch_bounds__(MGB) void k_mg_resid(const MgChunk* __restrict__ chunks, PcgDev s,
+                                                  const double* __restrict__ A, const double* __restrict__ r,
+                                                  const double* __restrict__ e, double* __restrict__ t) {
+  const MgChunk ch = chunks[blockIdx.x];
+  if (!sys_running(s, ch.sys)) return;
+  const int n = ch.node_begin + threadIdx.x;
+  if (n < ch.node_end) mg_resid_node(ch, n, A, r, e, t);
+}
+
+__global__ __launch_bounds__(MGB) void k_mg_restrict(const MgChunk* __restrict__ chunks, PcgDev s,
+                                                     const double* __restrict__ mask, const double* __restrict__ dinv,
+                                                     const double* __restrict__ t, double* __restrict__ r,
+                                                     double* __restrict__ e) {
+  const MgChunk ch = chunks[blockIdx.x];
+  if (!sys_running(s, ch.sys)) return;
+  const int n = ch.node_begin + threadIdx.x;
+  if (n < ch.node_end) mg_restrict_node(ch, n, mask, dinv, t, r, e);
+}
+
+// Coarsest level: e2 = X r with the dense inverse X (band numbering, so r
+// and e2 are permuted on the way).  Grid (row blocks of 16, systems); 16
+// lanes per row read contiguous stretches of the row.
+__global__ __launch_bounds__(256) void k_mg_coarse_solve(const MgChunk* __restrict__ chunks, PcgDev s,
+                                                         const double* __restrict__ dense,
+                                                         const double* __restrict__ r, double* __restrict__ e2) {
+  const MgChunk ch = chunks[blockIdx.y];
+  if (!sys_running(s, ch.sys)) return;
+  const int n = 2 * (ch.node_end - ch.node_begin);
+  const int i = blockIdx.x * 16 + (threadIdx.x >> 4), l16 = threadIdx.x & 15;
+  const bool row_ok = i < n;
+  const double* __restrict__ X = dense + ch.dense_off + (int64_t)(row_ok ? i : 0) * n;
+  double acc = 0.0;
+  if (row_ok)
+    for (int j = l16; j < n; j += 16) {
+      int x, y;
+      band_node(ch, j >> 1, x, y);
+      acc = fma(X[j], r[(ch.vec + (int64_t)y * (ch.nx + 1) + x) * 2 + (j & 1)], acc);
+    }
+  for (int m = 8; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+  if (row_ok && l16 == 0) {
+    int x, y;
+    band_node(ch, i >> 1, x, y);
+    e2[(ch.vec + (int64_t)y * (ch.nx + 1) + x) * 2 + (i & 1)] = acc;
+  }
+}
+
+__global__ __launch_bounds__(MGB) void k_mg_prolong_smooth(const MgChunk* __restrict__ chunks, PcgDev s,
+                                                           const double* __restrict__ A,
+                                                           const double* __restrict__ mask,
+                                                           const double* __restrict__ dinv,
+                                                           const double* __restrict__ r, const double* __restrict__ e,
+                                                           double* __restrict__ e2) {
+  const MgChunk ch = chunks[blockIdx.x];
+  if (!sys_running(s, ch.sys)) return;
+  const int n = ch.node_begin + threadIdx.x;
+  if (n < ch.node_end) mg_prolong_smooth_node(ch, n, A, mask, dinv, r, e, e2);
 }
 
 // Level 1 -> 0: z += injection^T e2_1 at the free vertex DOFs.
@@ -466,6 +600,13 @@ __global__ __launch_bounds__(1024) void k_mg_post0(PcgDev s, int it_k, int init)
 
 namespace {
 constexpr int ASM_BLOCK = 256;
+constexpr int ASM_APPLY_BLOCK = 256;
+
+// Position of (a, b), a <= b, in the row-packed upper triangle of an NE x NE matrix.
+template <int NE>
+__device__ __forceinline__ int packed_index(int a, int b) {
+  return a * NE - (a * (a - 1)) / 2 + (b - a);
+}
 }
 
 template <int P>
@@ -554,41 +695,48 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
     }
     __syncthreads();
   }
+  // upper triangle, packed by rows (the inverse is symmetric)
   for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
     const int a = idx / NE, b = idx - a * NE;
+    if (b < a) continue;
     double v = 0.5 * (A[a][b] + A[b][a]) * sc[a] * sc[b];
     if (gid[a] < 0 || gid[b] < 0) v = 0.0;
-    binv[(int64_t)idx * g.npad + k] = v;
+    binv[(int64_t)packed_index<NE>(a, b) * g.npad + k] = v;
   }
 }
 
-// slots = omega * B_e v_e: one wave per tile, 16 element columns at a time;
-// lane = (row quarter, column).
+// slots = omega * B_e v_e: one block per tile, 16 element columns at a time;
+// thread = (row group, column), rows rg, rg + 16, ...  B_e is read from the
+// packed upper triangle (row a takes entry (min(a, b), max(a, b))).
 template <int P>
-__global__ __launch_bounds__(64) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
-                                                  const double* __restrict__ binv, const double* __restrict__ v,
-                                                  PcgDev s, double omega) {
+__global__ __launch_bounds__(ASM_APPLY_BLOCK) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
+                                                               const double* __restrict__ binv,
+                                                               const double* __restrict__ v, PcgDev s,
+                                                               double omega) {
   constexpr int NE = ne_of(P);
   __shared__ double vs[NE][17];
   const Tile t = tiles[g.tile_begin + blockIdx.x];
   if (s.status[t.sys] != SYS_RUNNING) return;
-  const int lane = threadIdx.x, c = lane & 15, qd = lane >> 4;
+  const int c = threadIdx.x & 15, rg = threadIdx.x >> 4;
   const double* __restrict__ vsys = v + t.dof_off;
   double* __restrict__ sl = s.slots + t.slot_off;
+  const int64_t np = g.npad;
   for (int c0 = 0; c0 < t.count; c0 += 16) {
     const bool valid = c0 + c < t.count;
     const int col = t.elem_begin + c0 + (valid ? c : 0);
-    for (int r = qd; r < NE; r += 4) {
-      const int id = valid ? g.gidx[r * g.npad + col] : -1;
+    for (int r = rg; r < NE; r += 16) {
+      const int id = valid ? g.gidx[r * np + col] : -1;
       vs[r][c] = id >= 0 ? vsys[id] : 0.0;
     }
     __syncthreads();
-    for (int a = qd; a < NE; a += 4) {
-      const double* __restrict__ bp = binv + (int64_t)a * NE * g.npad + col;
+    for (int a = rg; a < NE; a += 16) {
+      const double* __restrict__ bp = binv + col;
       double acc = 0.0;
-#pragma unroll 10
-      for (int b = 0; b < NE; ++b) acc = fma(bp[(int64_t)b * g.npad], vs[b][c], acc);
-      const int si = valid ? g.sidx[a * g.npad + col] : -1;
+      for (int b = 0; b < a; ++b) acc = fma(bp[packed_index<NE>(b, a) * np], vs[b][c], acc);
+      const double* __restrict__ row = bp + (int64_t)packed_index<NE>(a, a) * np;
+#pragma unroll 8
+      for (int b = a; b < NE; ++b) acc = fma(row[(b - a) * np], vs[b][c], acc);
+      const int si = valid ? g.sidx[a * np + col] : -1;
       if (si >= 0) sl[si] = omega * acc;
     }
     __syncthreads();
@@ -650,20 +798,31 @@ void launch_mg_l1(const MgChunk* ch, int n, const double* A, double* dinv, hipSt
 void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_mg_rap, dim3(n), dim3(MGB), 0, st, ch, A, mask);
 }
-void launch_mg_coarse_setup(const MgChunk* ch, int n, const double* A, double* dense, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_mg_coarse_setup, dim3(n), dim3(MGB), 0, st, ch, A, dense);
+void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* dense,
+                            hipStream_t st) {
+  if (!n) return;
+  const size_t lds = (size_t)(bmax + 1) * (bmax + 1) * 8;
+  hipLaunchKernelGGL(k_mg_coarse_chol, dim3(n), dim3(1024), lds, st, ch, A, band);
+  hipLaunchKernelGGL(k_mg_coarse_inv, dim3((nmax + MG_INV_WAVES - 1) / MG_INV_WAVES, n), dim3(64 * MG_INV_WAVES),
+                     (size_t)MG_INV_WAVES * nmax * 8, st, ch, band, dense, nmax);
+  const int64_t nn = (int64_t)nmax * nmax;
+  hipLaunchKernelGGL(k_mg_coarse_sym, dim3((unsigned)((nn + 255) / 256), n), dim3(256), 0, st, ch, dense);
 }
 void launch_mg_restrict0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* dinv,
                          double* r1, double* e1, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_mg_restrict0, dim3(n), dim3(MGB), 0, st, ch, s, vfree, dinv, r1, e1);
 }
-void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
-                        const double* dinv, double* r, double* e, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_mg_restrict, dim3(n), dim3(MGB), 0, st, ch, s, A, mask, dinv, r, e);
+void launch_mg_resid(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* r, const double* e,
+                     double* t, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_mg_resid, dim3(n), dim3(MGB), 0, st, ch, s, A, r, e, t);
 }
-void launch_mg_coarse_solve(const MgChunk* ch, int n, const PcgDev& s, const double* dense, const double* r,
+void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* mask, const double* dinv,
+                        const double* t, double* r, double* e, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_mg_restrict, dim3(n), dim3(MGB), 0, st, ch, s, mask, dinv, t, r, e);
+}
+void launch_mg_coarse_solve(const MgChunk* ch, int n, int nmax, const PcgDev& s, const double* dense, const double* r,
                             double* e2, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_mg_coarse_solve, dim3(n), dim3(MGB), 0, st, ch, s, dense, r, e2);
+  if (n) hipLaunchKernelGGL(k_mg_coarse_solve, dim3((nmax + 15) / 16, n), dim3(256), 0, st, ch, s, dense, r, e2);
 }
 void launch_mg_prolong_smooth(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
                               const double* dinv, const double* r, const double* e, double* e2, hipStream_t st) {
@@ -691,7 +850,7 @@ void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const i
 void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, const PcgDev& s,
                       double omega, hipStream_t st) {
   if (g.n_tiles == 0) return;
-  const dim3 grid(g.n_tiles), block(64);
+  const dim3 grid(g.n_tiles), block(ASM_APPLY_BLOCK);
   switch (g.p) {
     case 1: hipLaunchKernelGGL(k_asm_apply<1>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
     case 2: hipLaunchKernelGGL(k_asm_apply<2>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;

@@ -61,7 +61,7 @@ struct GroupHost {
   double flops = 0.0;  // 2 S ne^2 per element column
   std::vector<double> kv;  // host copy of the vertex-block table
   int kv_off = 0;
-  // element-block Schwarz smoother: inverses [ne][ne][npad], neighbours [8][npad]
+  // element-block Schwarz smoother: packed inverses [ne (ne+1)/2][npad], neighbours [8][npad]
   double* binv = nullptr;
   int32_t* nbr = nullptr;
 };
@@ -71,16 +71,25 @@ struct MgHost {
   int L = 0;
   // per level l (index l-1): chunk ranges in the device chunk arrays
   std::vector<int> sys_begin, sys_count, inst_begin, inst_count;
+  // whole-grid chunks of the coarsest level (one per system, one per
+  // instance) for the dense coarse kernels; the node-parallel kernels use the
+  // MG_CHUNK-node chunks above on every level
+  int coarse_sys_begin = 0, coarse_inst_begin = 0;
   std::vector<MgChunk> chunks;  // all levels: system chunks then instance chunks, per level
   MgChunk* d_chunks = nullptr;
   double *A = nullptr, *dinv = nullptr, *mask = nullptr;  // operators [op nodes]
   double *r = nullptr, *e = nullptr, *e2 = nullptr;       // vectors [vec nodes]
+  double* t = nullptr;                                    // residual after pre-smoothing [vec nodes]
   double* dense = nullptr;                                // coarsest inverses
   int32_t* vfree = nullptr;                               // level 1: free index of vertex DOFs
   MgElem* elems = nullptr;
   double* kv = nullptr;
+  double* band = nullptr;  // coarsest: band Cholesky factors
+  int coarse_nmax = 0, coarse_bmax = 0;
   const MgChunk* sysc(int l) const { return d_chunks + sys_begin[l - 1]; }
   const MgChunk* instc(int l) const { return d_chunks + inst_begin[l - 1]; }
+  const MgChunk* coarse_sysc() const { return d_chunks + coarse_sys_begin; }
+  const MgChunk* coarse_instc() const { return d_chunks + coarse_inst_begin; }
 };
 
 struct mto_plan {
@@ -275,7 +284,8 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
   int L = 1;
   for (int i = 0; i < n; ++i) {
     int nx = I[i].nelx, ny = I[i].nely, l = 1;
-    while (2LL * (nx + 1) * (ny + 1) > MG_COARSE_MAX && (nx > 1 || ny > 1)) {
+    while ((2LL * (nx + 1) * (ny + 1) > MG_COARSE_MAX || 2 * std::min(nx, ny) + 5 > MG_BAND_MAX) &&
+           (nx > 1 || ny > 1)) {
       nx = (nx + 1) / 2;
       ny = (ny + 1) / 2;
       ++l;
@@ -293,8 +303,8 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
   M.L = L;
   // operator node offsets [l][instance], vector node offsets [l][system]
   std::vector<std::vector<int64_t>> op(L, std::vector<int64_t>(n)), vec(L, std::vector<int64_t>(P->n_sys));
-  int64_t op_tot = 0, vec_tot = 0, dense_tot = 0;
-  std::vector<int64_t> dense_off(n);
+  int64_t op_tot = 0, vec_tot = 0, dense_tot = 0, band_tot = 0;
+  std::vector<int64_t> dense_off(n), band_off(n);
   for (int l = 0; l < L; ++l)
     for (int i = 0; i < n; ++i) {
       op[l][i] = op_tot;
@@ -308,9 +318,14 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
     }
   for (int i = 0; i < n; ++i) {
     const int64_t N = (int64_t)(dims[i][L - 1].first + 1) * (dims[i][L - 1].second + 1);
-    if (2 * N > MG_COARSE_MAX) return fail(MTO_EINVAL, "multigrid: coarsest grid too large");
+    const int bw = 2 * std::min(dims[i][L - 1].first, dims[i][L - 1].second) + 5;  // band width, as in the kernels
+    if (2 * N > MG_COARSE_MAX || bw > MG_BAND_MAX) return fail(MTO_EINVAL, "multigrid: coarsest grid too large");
     dense_off[i] = dense_tot;
     dense_tot += 4 * N * N;
+    band_off[i] = band_tot;
+    band_tot += 2 * N * (bw + 1);
+    M.coarse_nmax = std::max<int>(M.coarse_nmax, (int)(2 * N));
+    M.coarse_bmax = std::max(M.coarse_bmax, bw);
   }
   // element table per instance for the level-1 assembly
   std::vector<int64_t> elem_off(n);
@@ -371,6 +386,7 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
       c.cop = c.cvec = -1;
     }
     c.dense_off = dense_off[i];
+    c.band_off = band_off[i];
     c.elem_off = elem_off[i];
     if (sys >= 0) {
       c.dof_off = P->sys[sys].dof_off;
@@ -381,34 +397,41 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
     return c;
   };
   for (int l = 0; l < L; ++l) {
-    const bool coarsest = l == L - 1;
     M.sys_begin[l] = (int)M.chunks.size();
     for (int s = 0; s < P->n_sys; ++s) {
       const int i = P->sys[s].inst;
       const int N = (dims[i][l].first + 1) * (dims[i][l].second + 1);
-      const int step = coarsest ? N : MG_CHUNK;
-      for (int b = 0; b < N; b += step) M.chunks.push_back(make(l, i, s, b, std::min(N, b + step)));
+      for (int b = 0; b < N; b += MG_CHUNK) M.chunks.push_back(make(l, i, s, b, std::min(N, b + MG_CHUNK)));
     }
     M.sys_count[l] = (int)M.chunks.size() - M.sys_begin[l];
     M.inst_begin[l] = (int)M.chunks.size();
     for (int i = 0; i < n; ++i) {
       const int N = (dims[i][l].first + 1) * (dims[i][l].second + 1);
-      const int step = coarsest ? N : MG_CHUNK;
-      for (int b = 0; b < N; b += step) M.chunks.push_back(make(l, i, -1, b, std::min(N, b + step)));
+      for (int b = 0; b < N; b += MG_CHUNK) M.chunks.push_back(make(l, i, -1, b, std::min(N, b + MG_CHUNK)));
     }
     M.inst_count[l] = (int)M.chunks.size() - M.inst_begin[l];
   }
+  M.coarse_sys_begin = (int)M.chunks.size();
+  for (int s = 0; s < P->n_sys; ++s) {
+    const int i = P->sys[s].inst;
+    M.chunks.push_back(make(L - 1, i, s, 0, (dims[i][L - 1].first + 1) * (dims[i][L - 1].second + 1)));
+  }
+  M.coarse_inst_begin = (int)M.chunks.size();
+  for (int i = 0; i < n; ++i)
+    M.chunks.push_back(make(L - 1, i, -1, 0, (dims[i][L - 1].first + 1) * (dims[i][L - 1].second + 1)));
   int rc;
   if ((rc = dev_upload(P, &M.d_chunks, M.chunks)) || (rc = dev_alloc(P, &M.A, 36 * (size_t)op_tot)) ||
       (rc = dev_alloc(P, &M.dinv, 2 * (size_t)op_tot)) || (rc = dev_alloc(P, &M.mask, 2 * (size_t)op_tot)) ||
       (rc = dev_alloc(P, &M.r, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.e, 2 * (size_t)vec_tot)) ||
-      (rc = dev_alloc(P, &M.e2, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.dense, (size_t)dense_tot)) ||
+      (rc = dev_alloc(P, &M.e2, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.t, 2 * (size_t)vec_tot)) ||
+      (rc = dev_alloc(P, &M.dense, (size_t)dense_tot)) || (rc = dev_alloc(P, &M.band, (size_t)band_tot)) ||
       (rc = dev_upload(P, &M.vfree, vfree)) || (rc = dev_upload(P, &M.elems, elems)) ||
       (rc = dev_upload(P, &M.kv, kvpool)))
     return rc;
   launch_fill(M.e, 0.0, 2 * vec_tot, 0);
   launch_fill(M.e2, 0.0, 2 * vec_tot, 0);
   launch_fill(M.r, 0.0, 2 * vec_tot, 0);
+  launch_fill(M.t, 0.0, 2 * vec_tot, 0);
   return check_launch("multigrid setup");
 }
 
@@ -449,7 +472,7 @@ int build_asm(mto_plan* P, const std::vector<InstanceHost>& I) {
           }
       }
     }
-    if ((rc = dev_upload(P, &G.nbr, nbr)) || (rc = dev_alloc(P, &G.binv, (size_t)G.ne * G.ne * G.npad))) return rc;
+    if ((rc = dev_upload(P, &G.nbr, nbr)) || (rc = dev_alloc(P, &G.binv, (size_t)G.ne * (G.ne + 1) / 2 * G.npad))) return rc;
     gd.push_back(P->gdev(G));
   }
   if ((rc = dev_upload(P, &P->d_groups, gd)) || (rc = dev_upload(P, &P->d_el_group, el_group)) ||
@@ -480,7 +503,10 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
   }
   mto_plan* P = new mto_plan();
   P->prm = *prm;
-  if (P->prm.iters_per_launch <= 0) P->prm.iters_per_launch = 32;
+  // Default chunk of captured iterations: Jacobi runs thousands of short
+  // iterations, the multigrid tens of long ones (a stopped system still
+  // launches the rest of its chunk, which then returns at once).
+  if (P->prm.iters_per_launch <= 0) P->prm.iters_per_launch = P->prm.precond == MTO_PRECOND_JACOBI ? 32 : 8;
   if (P->prm.iters_per_launch % 2) P->prm.iters_per_launch += 1;  // keeps the parity of it_base even
   if (P->prm.max_restarts < 0) P->prm.max_restarts = 3;
   (void)hipGetDevice(&P->device);
@@ -712,7 +738,7 @@ void enq_mg_setup(mto_plan* P, hipStream_t st) {
     launch_mg_rap(M.instc(l), M.inst_count[l - 1], M.A, M.mask, st);
     launch_mg_l1(M.instc(l), M.inst_count[l - 1], M.A, M.dinv, st);
   }
-  launch_mg_coarse_setup(M.instc(M.L), M.inst_count[M.L - 1], M.A, M.dense, st);
+  launch_mg_coarse_setup(M.coarse_instc(), P->n_inst, M.coarse_nmax, M.coarse_bmax, M.A, M.band, M.dense, st);
 }
 
 // z = M r: one V-cycle from z = D0^-1 r (already in z), l1-Jacobi pre- and
@@ -727,9 +753,11 @@ void enq_coarse_correction(mto_plan* P, hipStream_t st) {
   const MgHost& M = P->mg;
   const PcgDev s = P->pcg();
   launch_mg_restrict0(M.sysc(1), M.sys_count[0], s, M.vfree, M.dinv, M.r, M.e, st);
-  for (int l = 2; l <= M.L; ++l)
-    launch_mg_restrict(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, st);
-  launch_mg_coarse_solve(M.sysc(M.L), M.sys_count[M.L - 1], s, M.dense, M.r, M.e2, st);
+  for (int l = 2; l <= M.L; ++l) {
+    launch_mg_resid(M.sysc(l - 1), M.sys_count[l - 2], s, M.A, M.r, M.e, M.t, st);
+    launch_mg_restrict(M.sysc(l), M.sys_count[l - 1], s, M.mask, M.dinv, M.t, M.r, M.e, st);
+  }
+  launch_mg_coarse_solve(M.coarse_sysc(), P->n_sys, M.coarse_nmax, s, M.dense, M.r, M.e2, st);
   for (int l = M.L - 1; l >= 1; --l)
     launch_mg_prolong_smooth(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, M.e2, st);
   launch_mg_prolong0(M.sysc(1), M.sys_count[0], s, M.vfree, M.e2, st);

@@ -152,7 +152,7 @@ def _f64_cuda(t, n, name):
 
 def default_params(**kw):
     prm = dict(E0=1.0, Emin=1e-9, nu=0.3, q=3.0, rtol=1e-11, max_iter=0, kernel_path=PATH_MFMA,
-               iters_per_launch=32, max_restarts=3, precond=PRECOND_JACOBI,
+               iters_per_launch=0, max_restarts=3, precond=PRECOND_MG_ASM,
                mg_omega=0.0)
     prm.update(kw)
     return prm
@@ -211,7 +211,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:  # _lib is None during interpreter shutdown
             _lib.mto_plan_destroy(h)
             self.handle = None
 

@@ -147,11 +147,13 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("precond", [0, 2])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_solve_parity(cuda, name):
-    """u, c and dc/drho against the oracle (direct solve)."""
+def test_solve_parity(cuda, name, precond):
+    """u, c and dc/drho against the oracle (direct solve), Jacobi (0) and
+    Schwarz-multigrid (2) preconditioned."""
     prs = CASES[name]()
-    plan = mto().Plan(prs)
+    plan = mto().Plan(prs, precond=precond)
     rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
     u, c, g, st = plan.solve(rho)
     check_solution(plan, prs, u, c, g, st)
@@ -176,7 +178,7 @@ def test_schwarz_multigrid_cuts_iterations(cuda):
     m = mto()
     pr = P.cantilever_uniform(40, 20, 3, 4, sigma=2.0, volfrac=0.4, seed=7)
     rho = torch.tensor(pr.rho, device=cuda)
-    uj, cj, gj, sj = m.Plan(pr).solve(rho)
+    uj, cj, gj, sj = m.Plan(pr, precond=m.PRECOND_JACOBI).solve(rho)
     us, cs, gs, ss = m.Plan(pr, precond=m.PRECOND_MG_ASM).solve(rho)
     print(f"\niterations: Jacobi {sj['iterations']}, Schwarz multigrid {ss['iterations']}", flush=True)
     assert max(ss["iterations"]) * 8 < max(sj["iterations"])
@@ -242,7 +244,7 @@ def test_noconv_reported(cuda):
     """max_iter too small: MTO_ENOCONV, outputs still written."""
     m = mto()
     pr = P.small_mixed(12, 6, seed=42)
-    plan = m.Plan(pr, max_iter=4, iters_per_launch=2, max_restarts=0)
+    plan = m.Plan(pr, max_iter=4, iters_per_launch=2, max_restarts=0, precond=m.PRECOND_JACOBI)
     rho = torch.tensor(pr.rho, device=cuda)
     with pytest.raises(m.MtoError) as ei:
         plan.solve(rho)
