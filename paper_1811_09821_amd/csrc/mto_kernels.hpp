@@ -139,10 +139,11 @@ void launch_mg_assemble1(const MgChunk* ch, int n, const MgElem* elems, const do
                          const int32_t* vfree, double* A, double* mask, hipStream_t st);
 void launch_mg_l1(const MgChunk* ch, int n, const double* A, double* dinv, hipStream_t st);
 void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_t st);
-// coarsest level of each instance: band Cholesky (LDS window), dense inverse, symmetrised;
+// coarsest level of each instance: band Cholesky (LDS window), dense inverse
+// (band-order rows in scr), symmetrised into natural order in dense;
 // nmax / bmax: largest DOF count and band width over the instances
-void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* dense,
-                            hipStream_t st);
+void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* scr,
+                            double* dense, hipStream_t st);
 void launch_mg_restrict0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* dinv,
                          double* r1, double* e1, hipStream_t st);
 // t = r - A e on a level (l >= 1); then r_{l+1} = P~^T t, e_{l+1} = D^-1 r_{l+1}
@@ -152,8 +153,10 @@ void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double*
                         const double* t, double* r, double* e, hipStream_t st);
 void launch_mg_coarse_solve(const MgChunk* ch, int n, int nmax, const PcgDev& s, const double* dense, const double* r,
                             double* e2, hipStream_t st);
+// vfree != NULL (level 1): also z += e2 at the free vertex DOFs
 void launch_mg_prolong_smooth(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
-                              const double* dinv, const double* r, const double* e, double* e2, hipStream_t st);
+                              const double* dinv, const double* r, const double* e, double* e2, const int32_t* vfree,
+                              hipStream_t st);
 void launch_mg_prolong0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* e2,
                         hipStream_t st);
 void launch_mg_post0(const PcgDev& s, int it_k, int init, hipStream_t st);
@@ -167,14 +170,13 @@ void launch_mg_post0(const PcgDev& s, int it_k, int init, hipStream_t st);
 // el_group / el_col: group and column of every global element.
 void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const int32_t* nbr, const int32_t* el_group,
                       const int32_t* el_col, const double* E, double* binv, hipStream_t st);
-// slots = omega * B_e v_e for the running systems of the group's tiles
-void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, const PcgDev& s,
-                      double omega, hipStream_t st);
-// z = assembled slots (running systems)
-void launch_asm_z(const PcgDev& s, hipStream_t st);
-// q = r - assembled slots (running systems)
-void launch_asm_resid(const PcgDev& s, hipStream_t st);
-// z += assembled slots, partial sums of r.z (parity slot as k_mg_post0)
-void launch_asm_post(const PcgDev& s, int it_k, int init, hipStream_t st);
+// slots2 = omega * B_e v_e for the running systems of the group's tiles,
+// with v_e gathered from v, or (resid) from v - assembled slots
+void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, int resid,
+                      const PcgDev& s, double* slots2, double omega, hipStream_t st);
+// z = assembled slots2 (running systems)
+void launch_asm_z(const PcgDev& s, const double* slots2, hipStream_t st);
+// z += assembled slots2, partial sums of r.z (parity slot as k_mg_post0)
+void launch_asm_post(const PcgDev& s, const double* slots2, int it_k, int init, hipStream_t st);
 
 }  // namespace mto

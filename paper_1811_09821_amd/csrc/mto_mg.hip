@@ -249,9 +249,13 @@ __device__ __forceinline__ double band_entry(const MgChunk& ch, const double* __
 // Two barriers per column: (1) scale column j below the diagonal and retire
 // row j to global memory; (2) the rank-1 update of the window and the load of
 // row j + b + 1 into the slot row j has left.
-__global__ __launch_bounds__(1024) void k_mg_coarse_chol(const MgChunk* __restrict__ chunks,
-                                                        const double* __restrict__ A, double* __restrict__ band) {
+constexpr int MG_CHOL_BLOCK = 1024;
+
+__global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk* __restrict__ chunks,
+                                                                 const double* __restrict__ A,
+                                                                 double* __restrict__ band) {
   extern __shared__ double W[];  // window [(b + 1)][(b + 1)], row i in slot i % (b + 1)
+  constexpr int D = 4;           // rows of A requested ahead (thread k < b + 1 holds entry k)
   const MgChunk ch = chunks[blockIdx.x];
   const int n = 2 * (ch.node_end - ch.node_begin);
   const int b = band_width(ch), w = b + 1;
@@ -261,39 +265,66 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_chol(const MgChunk* __restri
     const int r = idx / w, k = idx - r * w;
     W[idx] = (r < n && r - k >= 0) ? band_entry(ch, A, r, r - k) : 0.0;
   }
+  auto row_entry = [&](int r) { return (tid < w && r < n && r - tid >= 0) ? band_entry(ch, A, r, r - tid) : 0.0; };
+  double pre[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) pre[d] = row_entry(w + d);
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const int sj = j % w;
-    const double d = sqrt(W[sj * w]);
-    const int m = min(b, n - 1 - j);
-    for (int ii = tid; ii < m; ii += nt) {
-      const int i = j + 1 + ii;
-      W[(i % w) * w + (i - j)] /= d;
+  int sj = 0;  // slot of row j
+  for (int j0 = 0; j0 < n; j0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int j = j0 + d;
+      if (j >= n) break;  // uniform
+      // slot of row j + e (0 <= e <= b)
+      auto slot = [&](int e) { return sj + e >= w ? sj + e - w : sj + e; };
+      const double dj = sqrt(W[sj * w]);
+      const double rj = 1.0 / dj;
+      const int m = min(b, n - 1 - j);
+      for (int ii = tid; ii < m; ii += nt) W[slot(ii + 1) * w + (ii + 1)] *= rj;
+      for (int k = tid; k < w; k += nt) out[(int64_t)j * w + k] = k == 0 ? dj : W[sj * w + k];
+      __syncthreads();
+      for (int idx = tid; idx < m * m; idx += nt) {
+        const int ii = idx / m, kk = idx - ii * m;
+        if (kk > ii) continue;
+        // rows i = j + 1 + ii, k = j + 1 + kk: W[i][i - k] -= L[i][j] L[k][j]
+        W[slot(ii + 1) * w + (ii - kk)] -= W[slot(ii + 1) * w + (ii + 1)] * W[slot(kk + 1) * w + (kk + 1)];
+      }
+      // row j + w (first touched by step j + 1) into the slot row j has left
+      if (tid < w) W[sj * w + tid] = pre[d];
+      pre[d] = row_entry(j + w + D);
+      sj = sj + 1 == w ? 0 : sj + 1;
+      __syncthreads();
     }
-    for (int k = tid; k < w; k += nt) out[(int64_t)j * w + k] = k == 0 ? d : W[sj * w + k];
-    __syncthreads();
-    for (int idx = tid; idx < m * m; idx += nt) {
-      const int ii = idx / m, kk = idx - ii * m;
-      if (kk > ii) continue;
-      const int i = j + 1 + ii, k = j + 1 + kk;
-      W[(i % w) * w + (i - k)] -= W[(i % w) * w + (i - j)] * W[(k % w) * w + (k - j)];
-    }
-    const int r = j + w;  // first touched by step j + 1
-    for (int k = tid; k < w; k += nt) W[sj * w + k] = (r < n && r - k >= 0) ? band_entry(ch, A, r, r - k) : 0.0;
-    __syncthreads();
   }
 }
 
 // Column c of the inverse (band numbering) per wave: y = L^-1 e_c, then
-// x = L^-T y, held in LDS; each substitution step is a band dot product
-// spread over the 64 lanes.  Stored as row c (the inverse is symmetric, and
-// rows are contiguous).
+// x = L^-T y, by column-oriented substitution: every pending row k of the
+// band keeps its running sum in a register of lane k % 64 (slot (k / 64) % 2;
+// b < 128 keeps the live rows apart).  A step finishes one row in its owner
+// lane, broadcasts the value with a lane read, and every lane updates the
+// rows it owns, so the dependency chain per step is one multiply, one lane
+// read and one FMA; the entries of L for the next step are requested one
+// step ahead.  y and x live in LDS (x overwrites y); the column is written
+// as row c of scr (band order).
 constexpr int MG_INV_WAVES = 2;
+
+// Wait for this wave's LDS operations only (lgkmcnt = 0; vmcnt and expcnt
+// left at their maxima), so prefetched global loads stay in flight.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 __global__ __launch_bounds__(64 * MG_INV_WAVES) void k_mg_coarse_inv(const MgChunk* __restrict__ chunks,
                                                                      const double* __restrict__ band,
-                                                                     double* __restrict__ dense, int nmax) {
-  extern __shared__ double xs_all[];  // [MG_INV_WAVES][nmax]
+                                                                     double* __restrict__ scr, int nmax) {
+  extern __shared__ double ys_all[];  // [MG_INV_WAVES][nmax]
   const MgChunk ch = chunks[blockIdx.y];
   const int n = 2 * (ch.node_end - ch.node_begin);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -301,46 +332,122 @@ __global__ __launch_bounds__(64 * MG_INV_WAVES) void k_mg_coarse_inv(const MgChu
   if (c >= n) return;  // whole wave
   const int b = band_width(ch), w = b + 1;
   const double* __restrict__ L = band + ch.band_off;
-  double* xs = xs_all + wave * nmax;
-  for (int i = lane; i < n; i += 64) xs[i] = 0.0;
-  // forward: rows c .. n-1 (y_i = 0 above c)
-  for (int i = c; i < n; ++i) {
-    double acc = 0.0;
-    for (int k = i - 1 - lane; k >= max(c, i - b); k -= 64) acc = fma(L[(int64_t)i * w + (i - k)], xs[k], acc);
-    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-    const double yi = ((i == c ? 1.0 : 0.0) - acc) / L[(int64_t)i * w];
-    if (lane == 0) xs[i] = yi;
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+  double* ys = ys_all + wave * nmax;
+  for (int i = lane; i < n; i += 64) ys[i] = 0.0;
+  wait_lds();
+  __builtin_amdgcn_wave_barrier();
+  double acc0 = 0.0, acc1 = 0.0;
+  if (lane == (c & 63)) {
+    if ((c >> 6) & 1) acc1 = 1.0;
+    else acc0 = 1.0;
   }
-  // backward: rows n-1 .. 0
-  for (int i = n - 1; i >= 0; --i) {
-    double acc = 0.0;
-    const int kend = min(n - 1, i + b);
-    for (int k = i + 1 + lane; k <= kend; k += 64) acc = fma(L[(int64_t)k * w + (k - i)], xs[k], acc);
-    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-    const double xi = (xs[i] - acc) / L[(int64_t)i * w];
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) xs[i] = xi;
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+  // forward: at step i the lane's rows are k1 = i + 1 + ((lane - i - 1) & 63) and k1 + 64
+  auto fwd_load = [&](int i, double& la, double& lb, double& rd) {
+    const int k1 = i + 1 + ((lane - i - 1) & 63), k2 = k1 + 64, khi = min(i + b, n - 1);
+    la = (i < n && k1 <= khi) ? L[(int64_t)k1 * w + (k1 - i)] : 0.0;
+    lb = (i < n && k2 <= khi) ? L[(int64_t)k2 * w + (k2 - i)] : 0.0;
+    rd = i < n ? L[(int64_t)i * w] : 1.0;  // the diagonal; its reciprocal is formed at use
+  };
+  // entries of L for the next PD steps in flight (a ring, indexed at compile time)
+  constexpr int PD = 8;
+  double pla[PD], plb[PD], prd[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) fwd_load(c + d, pla[d], plb[d], prd[d]);
+  for (int i0 = c; i0 < n; i0 += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int i = i0 + d;
+      if (i >= n) break;  // uniform
+      const int oi = i & 63, si = (i >> 6) & 1;
+      const double y = readlane_f64((si ? acc1 : acc0) * (1.0 / prd[d]), oi);
+      if (lane == oi) {
+        if (si) acc1 = 0.0;
+        else acc0 = 0.0;
+        ys[i] = y;
+      }
+      const int k1 = i + 1 + ((lane - i - 1) & 63), k2 = k1 + 64, khi = min(i + b, n - 1);
+      if (k1 <= khi) {
+        if ((k1 >> 6) & 1) acc1 = fma(-pla[d], y, acc1);
+        else acc0 = fma(-pla[d], y, acc0);
+      }
+      if (k2 <= khi) {
+        if ((k2 >> 6) & 1) acc1 = fma(-plb[d], y, acc1);
+        else acc0 = fma(-plb[d], y, acc0);
+      }
+      fwd_load(i + PD, pla[d], plb[d], prd[d]);
+    }
   }
-  double* __restrict__ X = dense + ch.dense_off + (int64_t)c * n;
-  for (int i = lane; i < n; i += 64) X[i] = xs[i];
+  wait_lds();  // ys complete (each wave reads only its own ys; no block barrier, waves may have left)
+  __builtin_amdgcn_wave_barrier();
+  // backward: rows j in [i - b, i - 1], the lane's being j1 = i - 1 - ((i - 1 - lane) & 63) and j1 - 64
+  acc0 = acc1 = 0.0;
+  {
+    const int jlo = max(0, n - 1 - b);
+    for (int j = jlo + ((lane - jlo) & 63); j < n; j += 64) {  // the rows this lane owns (j % 64 == lane)
+      if ((j >> 6) & 1) acc1 = ys[j];
+      else acc0 = ys[j];
+    }
+  }
+  auto bwd_load = [&](int i, double& la_, double& lb_, double& rd_) {
+    const int j1 = i - 1 - ((i - 1 - lane) & 63), j2 = j1 - 64, jlo = max(0, i - b);
+    la_ = (i >= 0 && j1 >= jlo) ? L[(int64_t)i * w + (i - j1)] : 0.0;
+    lb_ = (i >= 0 && j2 >= jlo) ? L[(int64_t)i * w + (i - j2)] : 0.0;
+    rd_ = i >= 0 ? L[(int64_t)i * w] : 1.0;
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d) bwd_load(n - 1 - d, pla[d], plb[d], prd[d]);
+  for (int i0 = n - 1; i0 >= 0; i0 -= PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int i = i0 - d;
+      if (i < 0) break;  // uniform
+      const int oi = i & 63, si = (i >> 6) & 1;
+      const double x = readlane_f64((si ? acc1 : acc0) * (1.0 / prd[d]), oi);
+      if (lane == oi) {
+        if (si) acc1 = 0.0;
+        else acc0 = 0.0;
+        ys[i] = x;
+      }
+      const int j1 = i - 1 - ((i - 1 - lane) & 63), j2 = j1 - 64, jlo = max(0, i - b);
+      if (j1 >= jlo) {
+        if ((j1 >> 6) & 1) acc1 = fma(-pla[d], x, acc1);
+        else acc0 = fma(-pla[d], x, acc0);
+      }
+      if (j2 >= jlo) {
+        if ((j2 >> 6) & 1) acc1 = fma(-plb[d], x, acc1);
+        else acc0 = fma(-plb[d], x, acc0);
+      }
+      // row i - 1 - b enters the window: its sum starts at y
+      const int jn = i - 1 - b;
+      if (jn >= 0 && lane == (jn & 63)) {
+        if ((jn >> 6) & 1) acc1 = ys[jn];
+        else acc0 = ys[jn];
+      }
+      bwd_load(i - PD, pla[d], plb[d], prd[d]);
+    }
+  }
+  wait_lds();
+  __builtin_amdgcn_wave_barrier();
+  double* __restrict__ row = scr + ch.dense_off + (int64_t)c * n;
+  for (int i = lane; i < n; i += 64) row[i] = ys[i];
 }
 
-// X = (X + X^T) / 2
-__global__ __launch_bounds__(256) void k_mg_coarse_sym(const MgChunk* __restrict__ chunks, double* __restrict__ dense) {
+// dense = (P X P^T + (P X P^T)^T) / 2 in natural order, from the band-order
+// rows scr (X = the inverse in band numbering, P the renumbering).
+__global__ __launch_bounds__(256) void k_mg_coarse_sym(const MgChunk* __restrict__ chunks, const double* __restrict__ scr,
+                                                       double* __restrict__ dense) {
   const MgChunk ch = chunks[blockIdx.y];
   const int n = 2 * (ch.node_end - ch.node_begin);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
-  if (j <= i) return;
-  double* __restrict__ X = dense + ch.dense_off;
-  const double v = 0.5 * (X[(int64_t)i * n + j] + X[(int64_t)j * n + i]);
-  X[(int64_t)i * n + j] = v;
-  X[(int64_t)j * n + i] = v;
+  auto band_of = [&](int d) {
+    const int nq = d >> 1, x = nq % (ch.nx + 1), y = nq / (ch.nx + 1);
+    return 2 * (ch.ny <= ch.nx ? x * (ch.ny + 1) + y : y * (ch.nx + 1) + x) + (d & 1);
+  };
+  const int bi = band_of(i), bj = band_of(j);
+  const double* __restrict__ X = scr + ch.dense_off;
+  dense[ch.dense_off + idx] = 0.5 * (X[(int64_t)bi * n + bj] + X[(int64_t)bj * n + bi]);
 }
 
 // Level 0 -> 1: t = r - A0 z at the vertex DOFs (A0 z in the slots), injected;
@@ -489,43 +596,44 @@ __global__ __launch_bounds__(MGB) void k_mg_restrict(const MgChunk* __restrict__
   if (n < ch.node_end) mg_restrict_node(ch, n, mask, dinv, t, r, e);
 }
 
-// Coarsest level: e2 = X r with the dense inverse X (band numbering, so r
-// and e2 are permuted on the way).  Grid (row blocks of 16, systems); 16
-// lanes per row read contiguous stretches of the row.
+// Coarsest level: e2 = X r with the dense inverse X (natural order), one
+// wave per row, the lanes over contiguous stretches of the row.
 __global__ __launch_bounds__(256) void k_mg_coarse_solve(const MgChunk* __restrict__ chunks, PcgDev s,
                                                          const double* __restrict__ dense,
                                                          const double* __restrict__ r, double* __restrict__ e2) {
   const MgChunk ch = chunks[blockIdx.y];
   if (!sys_running(s, ch.sys)) return;
   const int n = 2 * (ch.node_end - ch.node_begin);
-  const int i = blockIdx.x * 16 + (threadIdx.x >> 4), l16 = threadIdx.x & 15;
-  const bool row_ok = i < n;
-  const double* __restrict__ X = dense + ch.dense_off + (int64_t)(row_ok ? i : 0) * n;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= n) return;  // whole wave
+  const double* __restrict__ X = dense + ch.dense_off + (int64_t)i * n;
+  const double* __restrict__ rv = r + ch.vec * 2;
   double acc = 0.0;
-  if (row_ok)
-    for (int j = l16; j < n; j += 16) {
-      int x, y;
-      band_node(ch, j >> 1, x, y);
-      acc = fma(X[j], r[(ch.vec + (int64_t)y * (ch.nx + 1) + x) * 2 + (j & 1)], acc);
-    }
-  for (int m = 8; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-  if (row_ok && l16 == 0) {
-    int x, y;
-    band_node(ch, i >> 1, x, y);
-    e2[(ch.vec + (int64_t)y * (ch.nx + 1) + x) * 2 + (i & 1)] = acc;
-  }
+  for (int j = lane; j < n; j += 64) acc = fma(X[j], rv[j], acc);
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+  if (lane == 0) e2[ch.vec * 2 + i] = acc;
 }
 
+// vfree != NULL (level 1): also z += e2 at the node's free vertex DOFs
+// (the injection back to the hierarchic level).
 __global__ __launch_bounds__(MGB) void k_mg_prolong_smooth(const MgChunk* __restrict__ chunks, PcgDev s,
                                                            const double* __restrict__ A,
                                                            const double* __restrict__ mask,
                                                            const double* __restrict__ dinv,
                                                            const double* __restrict__ r, const double* __restrict__ e,
-                                                           double* __restrict__ e2) {
+                                                           double* __restrict__ e2, const int32_t* __restrict__ vfree) {
   const MgChunk ch = chunks[blockIdx.x];
   if (!sys_running(s, ch.sys)) return;
   const int n = ch.node_begin + threadIdx.x;
-  if (n < ch.node_end) mg_prolong_smooth_node(ch, n, A, mask, dinv, r, e, e2);
+  if (n >= ch.node_end) return;
+  mg_prolong_smooth_node(ch, n, A, mask, dinv, r, e, e2);
+  if (vfree) {
+    const int64_t node = ch.op + n, v = ch.vec + n;
+    for (int c = 0; c < 2; ++c) {
+      const int f = vfree[node * 2 + c];
+      if (f >= 0) s.z[ch.dof_off + f] += e2[v * 2 + c];
+    }
+  }
 }
 
 // Level 1 -> 0: z += injection^T e2_1 at the free vertex DOFs.
@@ -600,7 +708,6 @@ __global__ __launch_bounds__(1024) void k_mg_post0(PcgDev s, int it_k, int init)
 
 namespace {
 constexpr int ASM_BLOCK = 256;
-constexpr int ASM_APPLY_BLOCK = 256;
 
 // Position of (a, b), a <= b, in the row-packed upper triangle of an NE x NE matrix.
 template <int NE>
@@ -705,65 +812,78 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
   }
 }
 
-// slots = omega * B_e v_e: one block per tile, 16 element columns at a time;
-// thread = (row group, column), rows rg, rg + 16, ...  B_e is read from the
-// packed upper triangle (row a takes entry (min(a, b), max(a, b))).
+// slots2 = omega * B_e v_e.  One block per 16 element columns of a tile
+// (blockIdx.y picks the 16-column part); thread = (row, column), one row of
+// B_e per thread.  Each thread first loads its whole row from the packed
+// upper triangle (row a takes entry (min(a, b), max(a, b))), so the loads
+// overlap the gather, then contracts it with the gathered v_e in LDS.
 template <int P>
-__global__ __launch_bounds__(ASM_APPLY_BLOCK) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
-                                                               const double* __restrict__ binv,
-                                                               const double* __restrict__ v, PcgDev s,
-                                                               double omega) {
+constexpr int asm_rows() { return (ne_of(P) + 3) / 4 * 4; }
+
+template <int P>
+__global__ __launch_bounds__(16 * asm_rows<P>()) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
+                                                                  const double* __restrict__ binv,
+                                                                  const double* __restrict__ v, PcgDev s,
+                                                                  double* __restrict__ out_slots, double omega,
+                                                                  int resid) {
   constexpr int NE = ne_of(P);
   __shared__ double vs[NE][17];
   const Tile t = tiles[g.tile_begin + blockIdx.x];
-  if (s.status[t.sys] != SYS_RUNNING) return;
-  const int c = threadIdx.x & 15, rg = threadIdx.x >> 4;
-  const double* __restrict__ vsys = v + t.dof_off;
-  double* __restrict__ sl = s.slots + t.slot_off;
+  const int c0 = blockIdx.y * 16;
+  if (c0 >= t.count || s.status[t.sys] != SYS_RUNNING) return;  // uniform over the block
+  const int c = threadIdx.x & 15, a = threadIdx.x >> 4;
+  const bool valid = c0 + c < t.count;
+  const int col = t.elem_begin + c0 + (valid ? c : 0);
   const int64_t np = g.npad;
-  for (int c0 = 0; c0 < t.count; c0 += 16) {
-    const bool valid = c0 + c < t.count;
-    const int col = t.elem_begin + c0 + (valid ? c : 0);
-    for (int r = rg; r < NE; r += 16) {
-      const int id = valid ? g.gidx[r * np + col] : -1;
-      vs[r][c] = id >= 0 ? vsys[id] : 0.0;
+  const double* __restrict__ bp = binv + col;
+  // the first H entries of the row are requested before the gather, the rest
+  // (p = 4 only, to stay within the registers of 13 waves) after it
+  constexpr int H = NE <= 32 ? NE : NE / 2;
+  const int np32 = (int)np;  // (ne (ne + 1) / 2) * npad < 2^31 (checked at plan time)
+  auto entry = [&](int b) -> double {
+    return a < NE ? bp[(b < a ? packed_index<NE>(b, a) : packed_index<NE>(a, b)) * np32] : 0.0;
+  };
+  double brow[H];
+#pragma unroll
+  for (int b = 0; b < H; ++b) brow[b] = entry(b);
+  if (a < NE) {
+    const int id = valid ? g.gidx[a * np + col] : -1;
+    double x = 0.0;
+    if (id >= 0) {
+      const double* __restrict__ vsys = v + t.dof_off;
+      if (resid) {
+        const SysDesc& sd = s.sys[t.sys];
+        x = vsys[id] - slot_sum(s.slots + t.slot_off, id, sd.nfv, sd.nfe);
+      } else {
+        x = vsys[id];
+      }
     }
-    __syncthreads();
-    for (int a = rg; a < NE; a += 16) {
-      const double* __restrict__ bp = binv + col;
-      double acc = 0.0;
-      for (int b = 0; b < a; ++b) acc = fma(bp[packed_index<NE>(b, a) * np], vs[b][c], acc);
-      const double* __restrict__ row = bp + (int64_t)packed_index<NE>(a, a) * np;
-#pragma unroll 8
-      for (int b = a; b < NE; ++b) acc = fma(row[(b - a) * np], vs[b][c], acc);
-      const int si = valid ? g.sidx[a * np + col] : -1;
-      if (si >= 0) sl[si] = omega * acc;
-    }
-    __syncthreads();
+    vs[a][c] = x;
   }
+  __syncthreads();
+  if (a >= NE) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < H; ++b) acc = fma(brow[b], vs[b][c], acc);
+  if constexpr (H < NE) {
+#pragma unroll 5
+    for (int b = H; b < NE; ++b) acc = fma(entry(b), vs[b][c], acc);
+  }
+  const int si = valid ? g.sidx[a * np + col] : -1;
+  if (si >= 0) out_slots[t.slot_off + si] = omega * acc;
 }
 
-// z = assembled slots
-__global__ __launch_bounds__(1024) void k_asm_z(PcgDev s) {
+// z = assembled slots2 (the Schwarz products)
+__global__ __launch_bounds__(1024) void k_asm_z(PcgDev s, const double* __restrict__ slots2) {
   const Chunk ch = s.chunks[blockIdx.x];
   if (!sys_running(s, ch.sys)) return;
   const int i = ch.begin + threadIdx.x;
   if (i >= ch.end) return;
-  s.z[ch.dof_off + i] = slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
-}
-
-// q = r - assembled slots
-__global__ __launch_bounds__(1024) void k_asm_resid(PcgDev s) {
-  const Chunk ch = s.chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;
-  const int i = ch.begin + threadIdx.x;
-  if (i >= ch.end) return;
-  const int64_t o = ch.dof_off + i;
-  s.q[o] = s.r[o] - slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
+  s.z[ch.dof_off + i] = slot_sum(slots2 + ch.slot_off, i, ch.nfv, ch.nfe);
 }
 
 // z += assembled slots; partial sums of r.z for the next PCG iteration
-__global__ __launch_bounds__(1024) void k_asm_post(PcgDev s, int it_k, int init) {
+__global__ __launch_bounds__(1024) void k_asm_post(PcgDev s, const double* __restrict__ slots2, int it_k, int init) {
   __shared__ double lds[20];
   const Chunk ch = s.chunks[blockIdx.x];
   if (!sys_running(s, ch.sys)) return;
@@ -772,7 +892,7 @@ __global__ __launch_bounds__(1024) void k_asm_post(PcgDev s, int it_k, int init)
   double arz = 0.0;
   if (i < ch.end) {
     const int64_t o = ch.dof_off + i;
-    const double zi = s.z[o] + slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
+    const double zi = s.z[o] + slot_sum(slots2 + ch.slot_off, i, ch.nfv, ch.nfe);
     s.z[o] = zi;
     arz = s.r[o] * zi;
   }
@@ -798,15 +918,15 @@ void launch_mg_l1(const MgChunk* ch, int n, const double* A, double* dinv, hipSt
 void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_mg_rap, dim3(n), dim3(MGB), 0, st, ch, A, mask);
 }
-void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* dense,
-                            hipStream_t st) {
+void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* scr,
+                            double* dense, hipStream_t st) {
   if (!n) return;
   const size_t lds = (size_t)(bmax + 1) * (bmax + 1) * 8;
-  hipLaunchKernelGGL(k_mg_coarse_chol, dim3(n), dim3(1024), lds, st, ch, A, band);
+  hipLaunchKernelGGL(k_mg_coarse_chol, dim3(n), dim3(MG_CHOL_BLOCK), lds, st, ch, A, band);
   hipLaunchKernelGGL(k_mg_coarse_inv, dim3((nmax + MG_INV_WAVES - 1) / MG_INV_WAVES, n), dim3(64 * MG_INV_WAVES),
-                     (size_t)MG_INV_WAVES * nmax * 8, st, ch, band, dense, nmax);
+                     (size_t)MG_INV_WAVES * nmax * 8, st, ch, band, scr, nmax);
   const int64_t nn = (int64_t)nmax * nmax;
-  hipLaunchKernelGGL(k_mg_coarse_sym, dim3((unsigned)((nn + 255) / 256), n), dim3(256), 0, st, ch, dense);
+  hipLaunchKernelGGL(k_mg_coarse_sym, dim3((unsigned)((nn + 255) / 256), n), dim3(256), 0, st, ch, scr, dense);
 }
 void launch_mg_restrict0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* dinv,
                          double* r1, double* e1, hipStream_t st) {
@@ -822,11 +942,12 @@ void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double*
 }
 void launch_mg_coarse_solve(const MgChunk* ch, int n, int nmax, const PcgDev& s, const double* dense, const double* r,
                             double* e2, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_mg_coarse_solve, dim3((nmax + 15) / 16, n), dim3(256), 0, st, ch, s, dense, r, e2);
+  if (n) hipLaunchKernelGGL(k_mg_coarse_solve, dim3((nmax + 3) / 4, n), dim3(256), 0, st, ch, s, dense, r, e2);
 }
 void launch_mg_prolong_smooth(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
-                              const double* dinv, const double* r, const double* e, double* e2, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(n), dim3(MGB), 0, st, ch, s, A, mask, dinv, r, e, e2);
+                              const double* dinv, const double* r, const double* e, double* e2, const int32_t* vfree,
+                              hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(n), dim3(MGB), 0, st, ch, s, A, mask, dinv, r, e, e2, vfree);
 }
 void launch_mg_prolong0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* e2,
                         hipStream_t st) {
@@ -847,25 +968,34 @@ void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const i
     default: hipLaunchKernelGGL(k_asm_block<4>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
   }
 }
-void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, const PcgDev& s,
-                      double omega, hipStream_t st) {
+void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, int resid,
+                      const PcgDev& s, double* slots2, double omega, hipStream_t st) {
   if (g.n_tiles == 0) return;
-  const dim3 grid(g.n_tiles), block(ASM_APPLY_BLOCK);
+  const dim3 grid(g.n_tiles, g.ncol);  // tiles hold at most 16 ncol columns
   switch (g.p) {
-    case 1: hipLaunchKernelGGL(k_asm_apply<1>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
-    case 2: hipLaunchKernelGGL(k_asm_apply<2>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
-    case 3: hipLaunchKernelGGL(k_asm_apply<3>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
-    default: hipLaunchKernelGGL(k_asm_apply<4>, grid, block, 0, st, g, tiles, binv, v, s, omega); break;
+    case 1:
+      hipLaunchKernelGGL(k_asm_apply<1>, grid, dim3(16 * asm_rows<1>()), 0, st, g, tiles, binv, v, s, slots2, omega,
+                         resid);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_asm_apply<2>, grid, dim3(16 * asm_rows<2>()), 0, st, g, tiles, binv, v, s, slots2, omega,
+                         resid);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_asm_apply<3>, grid, dim3(16 * asm_rows<3>()), 0, st, g, tiles, binv, v, s, slots2, omega,
+                         resid);
+      break;
+    default:
+      hipLaunchKernelGGL(k_asm_apply<4>, grid, dim3(16 * asm_rows<4>()), 0, st, g, tiles, binv, v, s, slots2, omega,
+                         resid);
+      break;
   }
 }
-void launch_asm_z(const PcgDev& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_asm_z, dim3(s.n_chunks), dim3(1024), 0, st, s);
+void launch_asm_z(const PcgDev& s, const double* slots2, hipStream_t st) {
+  hipLaunchKernelGGL(k_asm_z, dim3(s.n_chunks), dim3(1024), 0, st, s, slots2);
 }
-void launch_asm_resid(const PcgDev& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_asm_resid, dim3(s.n_chunks), dim3(1024), 0, st, s);
-}
-void launch_asm_post(const PcgDev& s, int it_k, int init, hipStream_t st) {
-  hipLaunchKernelGGL(k_asm_post, dim3(s.n_chunks), dim3(1024), 0, st, s, it_k, init);
+void launch_asm_post(const PcgDev& s, const double* slots2, int it_k, int init, hipStream_t st) {
+  hipLaunchKernelGGL(k_asm_post, dim3(s.n_chunks), dim3(1024), 0, st, s, slots2, it_k, init);
 }
 
 

@@ -85,6 +85,7 @@ struct MgHost {
   MgElem* elems = nullptr;
   double* kv = nullptr;
   double* band = nullptr;  // coarsest: band Cholesky factors
+  double* scr = nullptr;   // coarsest: inverse in band order (setup scratch)
   int coarse_nmax = 0, coarse_bmax = 0;
   const MgChunk* sysc(int l) const { return d_chunks + sys_begin[l - 1]; }
   const MgChunk* instc(int l) const { return d_chunks + inst_begin[l - 1]; }
@@ -138,6 +139,7 @@ struct mto_plan {
   // element-block Schwarz smoother (MTO_PRECOND_MG_ASM)
   GroupDev* d_groups = nullptr;
   int32_t *d_el_group = nullptr, *d_el_col = nullptr;
+  double* slots2 = nullptr;  // the Schwarz products, assembled like the slots
   double asm_omega = 0.0;
 
   PcgDev pcg() const {
@@ -425,6 +427,7 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
       (rc = dev_alloc(P, &M.r, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.e, 2 * (size_t)vec_tot)) ||
       (rc = dev_alloc(P, &M.e2, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.t, 2 * (size_t)vec_tot)) ||
       (rc = dev_alloc(P, &M.dense, (size_t)dense_tot)) || (rc = dev_alloc(P, &M.band, (size_t)band_tot)) ||
+      (rc = dev_alloc(P, &M.scr, (size_t)dense_tot)) ||
       (rc = dev_upload(P, &M.vfree, vfree)) || (rc = dev_upload(P, &M.elems, elems)) ||
       (rc = dev_upload(P, &M.kv, kvpool)))
     return rc;
@@ -472,12 +475,15 @@ int build_asm(mto_plan* P, const std::vector<InstanceHost>& I) {
           }
       }
     }
+    if ((int64_t)G.ne * (G.ne + 1) / 2 * G.npad >= ((int64_t)1 << 31))
+      return fail(MTO_EINVAL, "Schwarz smoother: too many elements of one (p, d) group for 32-bit block offsets");
     if ((rc = dev_upload(P, &G.nbr, nbr)) || (rc = dev_alloc(P, &G.binv, (size_t)G.ne * (G.ne + 1) / 2 * G.npad))) return rc;
     gd.push_back(P->gdev(G));
   }
   if ((rc = dev_upload(P, &P->d_groups, gd)) || (rc = dev_upload(P, &P->d_el_group, el_group)) ||
-      (rc = dev_upload(P, &P->d_el_col, el_col)))
+      (rc = dev_upload(P, &P->d_el_col, el_col)) || (rc = dev_alloc(P, &P->slots2, P->n_slots_tot)))
     return rc;
+  launch_fill(P->slots2, 0.0, P->n_slots_tot, 0);  // slots no element writes read as zero
   P->asm_omega = P->prm.mg_omega > 0.0 ? P->prm.mg_omega : 2.0 / (9.0 * 1.05);
   return MTO_OK;
 }
@@ -738,7 +744,7 @@ void enq_mg_setup(mto_plan* P, hipStream_t st) {
     launch_mg_rap(M.instc(l), M.inst_count[l - 1], M.A, M.mask, st);
     launch_mg_l1(M.instc(l), M.inst_count[l - 1], M.A, M.dinv, st);
   }
-  launch_mg_coarse_setup(M.coarse_instc(), P->n_inst, M.coarse_nmax, M.coarse_bmax, M.A, M.band, M.dense, st);
+  launch_mg_coarse_setup(M.coarse_instc(), P->n_inst, M.coarse_nmax, M.coarse_bmax, M.A, M.band, M.scr, M.dense, st);
 }
 
 // z = M r: one V-cycle from z = D0^-1 r (already in z), l1-Jacobi pre- and
@@ -758,9 +764,11 @@ void enq_coarse_correction(mto_plan* P, hipStream_t st) {
     launch_mg_restrict(M.sysc(l), M.sys_count[l - 1], s, M.mask, M.dinv, M.t, M.r, M.e, st);
   }
   launch_mg_coarse_solve(M.coarse_sysc(), P->n_sys, M.coarse_nmax, s, M.dense, M.r, M.e2, st);
+  // level 1 also injects its correction into z (with one level, prolong0 does)
   for (int l = M.L - 1; l >= 1; --l)
-    launch_mg_prolong_smooth(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, M.e2, st);
-  launch_mg_prolong0(M.sysc(1), M.sys_count[0], s, M.vfree, M.e2, st);
+    launch_mg_prolong_smooth(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, M.e2,
+                             l == 1 ? M.vfree : nullptr, st);
+  if (M.L == 1) launch_mg_prolong0(M.sysc(1), M.sys_count[0], s, M.vfree, M.e2, st);
 }
 
 // z = M r: one V-cycle.  Level-0 smoothing is Jacobi-type (z = D0^-1 r is
@@ -770,14 +778,14 @@ void enq_coarse_correction(mto_plan* P, hipStream_t st) {
 void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
   const PcgDev s = P->pcg();
   if (P->prm.precond == MTO_PRECOND_MG_ASM) {
-    for (auto& g : P->groups) launch_asm_apply(P->gdev(g), P->d_tiles, g.binv, P->r, s, P->asm_omega, st);
-    launch_asm_z(s, st);
+    for (auto& g : P->groups) launch_asm_apply(P->gdev(g), P->d_tiles, g.binv, P->r, 0, s, P->slots2, P->asm_omega, st);
+    launch_asm_z(s, P->slots2, st);
     enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
     enq_coarse_correction(P, st);
     enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
-    launch_asm_resid(s, st);
-    for (auto& g : P->groups) launch_asm_apply(P->gdev(g), P->d_tiles, g.binv, P->q, s, P->asm_omega, st);
-    launch_asm_post(s, it_k, init, st);
+    // post-smoothing: the residual r - A0 z is formed in the gather
+    for (auto& g : P->groups) launch_asm_apply(P->gdev(g), P->d_tiles, g.binv, P->r, 1, s, P->slots2, P->asm_omega, st);
+    launch_asm_post(s, P->slots2, it_k, init, st);
     return;
   }
   enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
