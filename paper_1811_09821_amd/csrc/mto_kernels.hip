@@ -127,46 +127,52 @@ __device__ __forceinline__ dd_t dd_scale(double a, dd_t y) {
   return two_sum(p, lo);
 }
 
-// Element contraction in double-double, one thread per element column:
-// y_e = sum_s E_s (K_s x_e) with every product and sum carried to ~2^-104,
-// results to (slots, slots_lo).  Used only for the true residual.
+// Element contraction in double-double: y_e = sum_s E_s (K_s x_e) with every
+// product and sum carried to ~2^-104, results to (slots, slots_lo).  Used
+// only for the true residual.  One block per 16 element columns of a tile
+// (blockIdx.y picks the part), one thread per (row, column); x_e (high and
+// low parts) is gathered once into LDS.
 template <int P>
-__global__ __launch_bounds__(64) void k_elem_dd(GroupDev g, const Tile* __restrict__ tiles,
-                                               const double* __restrict__ E, const double* __restrict__ xhi,
-                                               const double* __restrict__ xlo, double* __restrict__ slots,
-                                               double* __restrict__ slots_lo) {
+constexpr int dd_rows() { return (ne_of(P) + 3) / 4 * 4; }
+
+template <int P>
+__global__ __launch_bounds__(16 * dd_rows<P>()) void k_elem_dd(GroupDev g, const Tile* __restrict__ tiles,
+                                                             const double* __restrict__ E,
+                                                             const double* __restrict__ xhi,
+                                                             const double* __restrict__ xlo,
+                                                             double* __restrict__ slots,
+                                                             double* __restrict__ slots_lo) {
   constexpr int NE = ne_of(P);
+  __shared__ double uh[NE][17], ul[NE][17];
   const Tile t = tiles[g.tile_begin + blockIdx.x];
-  const int col = threadIdx.x;
-  if (col >= t.count) return;
-  const int el = t.elem_begin + col;
-  const double* __restrict__ xh = xhi + t.dof_off;
-  const double* __restrict__ xl = xlo + t.dof_off;
-  double u[NE], ul[NE];
-#pragma unroll
-  for (int j = 0; j < NE; ++j) {
-    const int gi = g.gidx[j * g.npad + el];
-    u[j] = gi >= 0 ? xh[gi] : 0.0;
-    ul[j] = gi >= 0 ? xl[gi] : 0.0;
+  const int c0 = blockIdx.y * 16;
+  if (c0 >= t.count) return;  // uniform over the block
+  const int c = threadIdx.x & 15, row = threadIdx.x >> 4;
+  const bool valid = c0 + c < t.count;
+  const int el = t.elem_begin + c0 + (valid ? c : 0);
+  if (row < NE) {
+    const int gi = valid ? g.gidx[row * g.npad + el] : -1;
+    uh[row][c] = gi >= 0 ? xhi[t.dof_off + gi] : 0.0;
+    ul[row][c] = gi >= 0 ? xlo[t.dof_off + gi] : 0.0;
   }
+  __syncthreads();
+  if (row >= NE || !valid) return;
+  const int si = g.sidx[row * g.npad + el];
+  if (si < 0) return;
   const int cb = g.cell[el];
-  for (int row = 0; row < NE; ++row) {
-    const int si = g.sidx[row * g.npad + el];
-    if (si < 0) continue;
-    dd_t y{0.0, 0.0};
-    for (int sc = 0; sc < g.S; ++sc) {
-      const double* __restrict__ kr = g.ks + ((size_t)sc * NE + row) * NE;
-      dd_t tacc{0.0, 0.0};
-#pragma unroll
-      for (int j = 0; j < NE; ++j) {
-        tacc = dd_fma(tacc, kr[j], u[j]);
-        tacc.lo = fma(kr[j], ul[j], tacc.lo);  // low part of x: one rounding at ~2^-106 relative
-      }
-      y = dd_add(y, dd_scale(E[cb + sc], two_sum(tacc.hi, tacc.lo)));
+  dd_t y{0.0, 0.0};
+  for (int sc = 0; sc < g.S; ++sc) {
+    const double* __restrict__ kr = g.ks + ((size_t)sc * NE + row) * NE;
+    dd_t tacc{0.0, 0.0};
+#pragma unroll 10
+    for (int j = 0; j < NE; ++j) {
+      tacc = dd_fma(tacc, kr[j], uh[j][c]);
+      tacc.lo = fma(kr[j], ul[j][c], tacc.lo);  // low part of x: one rounding at ~2^-106 relative
     }
-    slots[t.slot_off + si] = y.hi;
-    slots_lo[t.slot_off + si] = y.lo;
+    y = dd_add(y, dd_scale(E[cb + sc], two_sum(tacc.hi, tacc.lo)));
   }
+  slots[t.slot_off + si] = y.hi;
+  slots_lo[t.slot_off + si] = y.lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -902,12 +908,20 @@ void launch_residual_dd(const GroupDev* groups, int n_groups, const Tile* tiles,
   for (int k = 0; k < n_groups; ++k) {
     const GroupDev& g = groups[k];
     if (g.n_tiles == 0) continue;
-    const dim3 grid(g.n_tiles), block(64);
+    const dim3 grid(g.n_tiles, g.ncol);  // tiles hold at most 16 ncol columns
     switch (g.p) {
-      case 1: hipLaunchKernelGGL(k_elem_dd<1>, grid, block, 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo); break;
-      case 2: hipLaunchKernelGGL(k_elem_dd<2>, grid, block, 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo); break;
-      case 3: hipLaunchKernelGGL(k_elem_dd<3>, grid, block, 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo); break;
-      default: hipLaunchKernelGGL(k_elem_dd<4>, grid, block, 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo); break;
+      case 1:
+        hipLaunchKernelGGL(k_elem_dd<1>, grid, dim3(16 * dd_rows<1>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_elem_dd<2>, grid, dim3(16 * dd_rows<2>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo);
+        break;
+      case 3:
+        hipLaunchKernelGGL(k_elem_dd<3>, grid, dim3(16 * dd_rows<3>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo);
+        break;
+      default:
+        hipLaunchKernelGGL(k_elem_dd<4>, grid, dim3(16 * dd_rows<4>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo);
+        break;
     }
   }
   hipLaunchKernelGGL(k_residual_dd, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, slots_lo, xhi);
