@@ -1,10 +1,12 @@
 #!/usr/bin/env python3
 """Benchmark of the FEA + sensitivity step on one MI355X.
 
-One step = one full pass of the hot path for one design: SIMP moduli, Jacobi
-diagonal, matrix-free PCG to rtol 1e-11 (true residual checked), compliance
-and sensitivities, replayed from captured HIP graphs.  Inputs (densities)
-are resident in HBM before timing starts.
+One step = one full pass of the hot path for one design: SIMP moduli, the
+preconditioner set-up (element-block Schwarz inverses, vertex-grid Galerkin
+operators, coarsest-grid inverse; or the Jacobi diagonal), matrix-free PCG
+to rtol 1e-11 (true residual checked in double-double), compliance and
+sensitivities, replayed from captured HIP graphs.  Inputs (densities) are
+resident in HBM before timing starts.
 
 Default workload: clamped cantilever 160 x 80, uniform p = 3, d = 4 (16 cells
 per element), FP64, seeded Gaussian-smoothed density field at volume
@@ -132,7 +134,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_source_sha256_16") == kernel_source_hash() and tr.get("config") == args.config:
+        if (tr.get("kernel_source_sha256_16") == kernel_source_hash() and tr.get("config") == args.config
+                and args.path == "mfma"):
             traffic = tr.get("bytes_per_launch")
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": traffic,
