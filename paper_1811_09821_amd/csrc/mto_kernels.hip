@@ -175,6 +175,15 @@ __global__ __launch_bounds__(16 * dd_rows<P>()) void k_elem_dd(GroupDev g, const
   slots_lo[t.slot_off + si] = y.lo;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
+// XCD i mod 8), each with its own L2.  This bijection of [0, T) hands each
+// XCD a contiguous run of tiles, so neighbouring elements, which share vertex
+// and edge DOFs in their gathers, meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int i, int T) {
+  const int q = T >> 3, r = T & 7, x = i & 7, k = i >> 3;
+  return x * q + min(x, r) + k;
+}
+
 // ---------------------------------------------------------------------------
 // Element contraction on MFMA.  One block per tile of 16*NC element columns
 // of one system; the block's KS waves split the density cells of the
@@ -193,7 +202,7 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
   double* red = lds + 2;             // reused after the gather: [KS-1][NACC][64]
   const int ks = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const Tile t = tiles[g.tile_begin + blockIdx.x];
+  const Tile t = tiles[g.tile_begin + xcd_tile(blockIdx.x, g.n_tiles)];
   if (mode == ELEM_APPLY_RUNNING && s.status[t.sys] != SYS_RUNNING) return;
   const bool pcg = mode == ELEM_PCG;
   const int n = lane & 15, kq = lane >> 4;

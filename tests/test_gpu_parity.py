@@ -72,12 +72,12 @@ def check_solution(plan, prs, u, c, g, stats):
     assert stats["status"] == 0, stats
 
 
-GROUPS = [(p, d) for p in (1, 2, 3, 4) for d in (1, 2, 3, 4, 5)]
+GROUPS = [(p, d) for p in (1, 2, 3, 4) for d in range(1, 9)]  # every (p, d) the library accepts
 
 
 @pytest.mark.parametrize("p,d", GROUPS)
 def test_matvec_every_group(cuda, p, d):
-    """y = K x (element contraction + slot assembly) for all 20 (p, d) groups,
+    """y = K x (element contraction + slot assembly) for all 32 (p, d) groups,
     on a 7 x 5 mesh (35 elements: several 16-column tiles and a ragged tail)
     with several tile widths and density-cell splits across waves."""
     pr = P.uniform_random(7, 5, p, d, seed=100 + 10 * p + d)
@@ -144,6 +144,7 @@ CASES = {
     "mixed16x8": lambda: [P.small_mixed(16, 8, seed=3)],
     "mixed_3loads": lambda: [P.small_mixed(14, 7, seed=4, n_loads=3)],
     "cantilever_field": lambda: [P.cantilever_uniform(24, 12, 3, 4, sigma=3.0, volfrac=0.4, seed=2)],
+    "uniform_p4d8_max": lambda: [P.uniform_random(6, 3, 4, 8, 17)],
 }
 
 
