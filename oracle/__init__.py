@@ -15,6 +15,8 @@ What it computes, in plain FP64 (longdouble for residual accumulation):
 * the modified SIMP modulus of Sec. 2.2, E(rho) = Emin + rho^q (E0 - Emin);
 * the assembled global K, the solve Ku = f (Eq. ``eq_comp_1``) by a sparse
   direct factorisation followed by extended-precision iterative refinement;
+* the density filter of Sec. 2.2 (Eqs. (4)-(5)) on the density cells and
+  the chain rule through it (``filter.py``);
 * compliance c = f^T u (Sec. 4.1, z = f) and the per-cell sensitivity
   dc/drho = -E'(rho) u_e^T K_s u_e (the paper names the sensitivity analysis
   in Sec. 1 and Sec. 2.1 but prints no formula; this is the adjoint result for
@@ -35,3 +37,4 @@ from .fem import (  # noqa: F401
 )
 from .space import DofSpace, build_space  # noqa: F401
 from .solve import oracle_solve, assemble, element_dofs_global  # noqa: F401
+from .filter import filter_apply, filter_grad, filter_matrix, filter_weights  # noqa: F401
