@@ -13,7 +13,9 @@ per element), FP64, seeded Gaussian-smoothed density field at volume
 fraction 0.4, unit load at the mid-right vertex.
 
 Prints one JSON line (metric, value in seconds per design, roofline of the
-element-contraction kernel, CPU-oracle baseline).
+element-contraction kernel, CPU-oracle baseline, and the launch time of the
+density filter of Sec. 2.2 and its chain rule on the same cells, outside the
+timed step).
 """
 
 import argparse
@@ -71,6 +73,36 @@ def cpu_baseline(prs, budget_s=30.0):
     return sum(times) / len(times), len(times)
 
 
+def time_filter(mto, prs, rho, R, reps=200):
+    """Density filter (Sec. 2.2, Eqs. (4)-(5)) and its chain rule on the same
+    cells: average launch time over `reps` back-to-back launches, and the
+    HBM rate on algorithmic bytes (x, 1/rowsum and y once per cell; an index
+    and a weight per nonzero of H)."""
+    import torch
+
+    F = mto.Filter(prs, R)
+    y = F.apply(rho)
+    g = F.grad(y)
+    st = torch.cuda.current_stream()
+    res = {"R": R, "n_cells": F.n_cells, "nnz": F.nnz}
+    nbytes = 24 * F.n_cells + 12 * F.nnz
+    for name, fn, x, out in (("apply", mto.lib().mto_filter_apply, rho, y), ("grad", mto.lib().mto_filter_grad, y, g)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(5):
+            mto._check(fn(F.handle, mto._ptr(x), mto._ptr(out), mto._stream(st)))
+        e0.record(st)
+        for _ in range(reps):
+            mto._check(fn(F.handle, mto._ptr(x), mto._ptr(out), mto._stream(st)))
+        e1.record(st)
+        e1.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        res[f"{name}_us"] = round(us, 3)
+        res[f"{name}_GBps"] = round(nbytes / (us * 1e-6) / 1e9, 1)
+    res["bytes_per_launch"] = nbytes
+    res["hbm_frac_apply"] = round(res["apply_GBps"] / 8000.0, 4)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +115,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--compare-plain", action="store_true", help="also time the plain per-element path")
+    ap.add_argument("--filter-radius", type=float, default=0.3,
+                    help="density-filter radius in element edge lengths for the filter timing (0 skips it)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -180,6 +214,9 @@ def main():
         out["plain_path"] = {"s_per_design": (time.perf_counter() - t1) / n_designs,
                              "contraction_ms": plain.time_contraction(rho, reps=20, in_loop=True),
                              "iterations": st_p["iterations"]}
+
+    if args.filter_radius > 0:
+        out["density_filter"] = time_filter(mto, prs, rho, args.filter_radius)
 
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 8

@@ -260,6 +260,39 @@ int mto_time_contraction(mto_plan* plan, const double* rho, int32_t reps, int32_
 /* Frees the plan and its device buffers (NULL is a no-op). */
 void mto_plan_destroy(mto_plan* plan);
 
+/* ---- density filter (Sec. 2.2, Eqs. (4)-(5)) ------------------------------
+ * The step that precedes the analysis: filtered densities
+ *   rho~_i = sum_j H_ij rho_j / sum_j H_ij,   H_ij = R - |c_i - c_j|  (> 0),
+ * over the density cells j of the same instance whose centres c_j lie closer
+ * than R to the centre c_i of cell i (composite integration: one point per
+ * cell).  Lengths are in element edge lengths; cell s = sy*d + sx of element
+ * e = ey*nelx + ex has its centre at (ex + (sx + 1/2)/d, ey + (sy + 1/2)/d).
+ * The chain rule is the transpose: dJ/drho_j = sum_i dJ/drho~_i H_ij / sum_k H_ik.
+ * Cell arrays use the plan layout (instances concatenated, element-major). */
+typedef struct mto_filter mto_filter;
+
+/* Builds H (symmetric, so one pattern serves W and W^T) and the row scales
+ * 1 / sum_j H_ij on the host from the meshes of probs[0..n_inst) (only
+ * mesh.nelx, mesh.nely and mesh.d are read; the same array a batch plan
+ * takes) and uploads them to the current device, on which the filter must
+ * then be used.  Host work and memory grow with n_cells * (R d)^2.  R > 0 and
+ * finite.  MTO_EINVAL on bad arguments, MTO_ENOMEM (host or device). */
+int mto_filter_create(const mto_problem* probs, int32_t n_inst, double R, mto_filter** out);
+
+/* rho_tilde = W rho.  Device arrays of n_cells doubles, distinct (MTO_EINVAL
+ * in place); asynchronous on stream. */
+int mto_filter_apply(const mto_filter* filter, const double* rho, double* rho_tilde, void* stream);
+
+/* g = W^T g_tilde (the chain rule).  Device arrays of n_cells doubles,
+ * distinct (MTO_EINVAL in place); asynchronous on stream. */
+int mto_filter_grad(const mto_filter* filter, const double* g_tilde, double* g, void* stream);
+
+/* Number of cells and of nonzero H_ij (host outputs, may be NULL). */
+int mto_filter_info(const mto_filter* filter, int64_t* n_cells, int64_t* nnz);
+
+/* Frees the filter (NULL is a no-op). */
+void mto_filter_destroy(mto_filter* filter);
+
 #ifdef __cplusplus
 }
 #endif

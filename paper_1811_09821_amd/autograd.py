@@ -1,5 +1,5 @@
-"""torch.autograd.Function: densities -> compliances, with the hand-written
-adjoint.
+"""torch.autograd.Functions: densities -> compliances, with the hand-written
+adjoint, and the density filter (Sec. 2.2, Eqs. (4)-(5)) with its chain rule.
 
 Forward: one FEA + sensitivity step through the C ABI (u, c = f^T u and
 g = dc/drho per load case).  Compliance is self-adjoint (the adjoint state is
@@ -37,3 +37,22 @@ def total_compliance(rho, plan):
     """Sum of the compliances of all load cases and instances (the objective
     of a multi-load compliance design)."""
     return MTOCompliance.apply(rho, plan).sum()
+
+
+class DensityFilter(torch.autograd.Function):
+    """rho~ = DensityFilter.apply(rho, filt): filtered densities; backward is
+    the transposed filter (the chain rule through Eq. (4))."""
+
+    @staticmethod
+    def forward(ctx, rho, filt):
+        ctx.filt = filt
+        return filt.apply(rho.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        return ctx.filt.grad(grad_out.detach().contiguous().to(torch.float64)), None
+
+
+def filtered_total_compliance(rho, plan, filt):
+    """Sum of all compliances at the filtered densities W rho."""
+    return total_compliance(DensityFilter.apply(rho, filt), plan)

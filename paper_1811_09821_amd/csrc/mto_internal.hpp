@@ -46,6 +46,10 @@ struct InstanceHost {
   std::vector<double> f;
 };
 
+// The thread-local message behind mto_last_error (set_error returns code).
+int set_error(int code, const std::string& msg);
+void clear_error();
+
 // Builds the numbering; returns MTO_OK or an error code with `err` filled.
 int build_instance(const mto_problem& prob, InstanceHost& out, std::string& err);
 

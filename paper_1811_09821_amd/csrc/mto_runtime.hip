@@ -28,6 +28,15 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+namespace mto {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+void clear_error() { g_err.clear(); }
+}  // namespace mto
+
+namespace {
+
 #define HIP_TRY(expr)                                                                       \
   do {                                                                                      \
     hipError_t e_ = (expr);                                                                 \

@@ -93,6 +93,11 @@ def _load():
         "mto_set_tile": ([vp, i32, i32, i32, i32], i32),
         "mto_time_contraction": ([vp, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "mto_plan_destroy": ([vp], None),
+        "mto_filter_create": ([ctypes.POINTER(_Problem), i32, ctypes.c_double, ctypes.POINTER(vp)], i32),
+        "mto_filter_apply": ([vp, vp, vp, vp], i32),
+        "mto_filter_grad": ([vp, vp, vp, vp], i32),
+        "mto_filter_info": ([vp, i64p, i64p], i32),
+        "mto_filter_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -104,8 +109,9 @@ def _load():
 _lib = _load()
 EXPORTED = ("mto_last_error", "mto_version", "mto_plan_create", "mto_batch_plan_create", "mto_plan_info",
             "mto_instance_info", "mto_solve", "mto_batch_capture", "mto_batch_replay", "mto_apply_stiffness",
-            "mto_sensitivity", "mto_jacobi_diagonal", "mto_weighted_sensitivity", "mto_autotune", "mto_set_tile", "mto_time_contraction",
-            "mto_plan_destroy")
+            "mto_sensitivity", "mto_jacobi_diagonal", "mto_weighted_sensitivity", "mto_autotune", "mto_set_tile",
+            "mto_time_contraction", "mto_plan_destroy", "mto_filter_create", "mto_filter_apply", "mto_filter_grad",
+            "mto_filter_info", "mto_filter_destroy")
 
 
 def lib():
@@ -158,6 +164,28 @@ def default_params(**kw):
     return prm
 
 
+def _problem_array(problems):
+    """ctypes mto_problem array for `problems` plus the host buffers it
+    points into (keep them alive for the call)."""
+    keep = []
+    arr = (_Problem * len(problems))()
+    for k, pr in enumerate(problems):
+        p = np.ascontiguousarray(pr.p, dtype=np.int8)
+        d = np.ascontiguousarray(pr.d, dtype=np.int8)
+        sup = (_Support * max(1, len(pr.supports)))(*[_Support(*map(int, s)) for s in pr.supports])
+        lds = (_Load * max(1, len(pr.loads)))(
+            *[_Load(int(l[0]), int(l[1]), float(l[2]), float(l[3]), int(l[4])) for l in pr.loads])
+        keep += [p, d, sup, lds]
+        arr[k].mesh = _Mesh(int(pr.nelx), int(pr.nely), p.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                            d.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+        arr[k].supports = ctypes.cast(sup, ctypes.POINTER(_Support))
+        arr[k].n_supports = len(pr.supports)
+        arr[k].loads = ctypes.cast(lds, ctypes.POINTER(_Load))
+        arr[k].n_loads = len(pr.loads)
+        arr[k].n_load_cases = int(pr.n_load_cases)
+    return arr, keep
+
+
 class Plan:
     """A plan for one or several design instances (batch), see mto.h.
 
@@ -169,22 +197,7 @@ class Plan:
             problems = [problems]
         prm = default_params(**params)
         self.params = prm
-        self._keep = []
-        arr = (_Problem * len(problems))()
-        for k, pr in enumerate(problems):
-            p = np.ascontiguousarray(pr.p, dtype=np.int8)
-            d = np.ascontiguousarray(pr.d, dtype=np.int8)
-            sup = (_Support * max(1, len(pr.supports)))(*[_Support(*map(int, s)) for s in pr.supports])
-            lds = (_Load * max(1, len(pr.loads)))(
-                *[_Load(int(l[0]), int(l[1]), float(l[2]), float(l[3]), int(l[4])) for l in pr.loads])
-            self._keep += [p, d, sup, lds]
-            arr[k].mesh = _Mesh(int(pr.nelx), int(pr.nely), p.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
-                                d.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
-            arr[k].supports = ctypes.cast(sup, ctypes.POINTER(_Support))
-            arr[k].n_supports = len(pr.supports)
-            arr[k].loads = ctypes.cast(lds, ctypes.POINTER(_Load))
-            arr[k].n_loads = len(pr.loads)
-            arr[k].n_load_cases = int(pr.n_load_cases)
+        arr, self._keep = _problem_array(problems)
         cp = _Params(prm["E0"], prm["Emin"], prm["nu"], prm["q"], prm["rtol"], prm["max_iter"],
                      prm["kernel_path"], prm["iters_per_launch"], prm["max_restarts"], prm["precond"],
                      prm["mg_omega"])
@@ -331,3 +344,45 @@ class Plan:
 
     def split_c(self, c):
         return [c[r["c_off"]:r["c_off"] + r["n_load_cases"]] for r in self.instances]
+
+
+class Filter:
+    """Density filter of Sec. 2.2 (Eqs. (4)-(5)) over the density cells of
+    `problems` (plan layout), radius R in element edge lengths; see mto.h."""
+
+    def __init__(self, problems, R):
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        arr, keep = _problem_array(problems)
+        h = ctypes.c_void_p()
+        _check(_lib.mto_filter_create(arr, len(problems), float(R), ctypes.byref(h)))
+        del keep
+        self.handle = h
+        self.R = float(R)
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.mto_filter_info(self.handle, ctypes.byref(n), ctypes.byref(nnz)))
+        self.n_cells, self.nnz = n.value, nnz.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mto_filter_destroy(h)
+            self.handle = None
+
+    def apply(self, rho, stream=None):
+        """rho~ = W rho (new device tensor)."""
+        import torch
+
+        _f64_cuda(rho, self.n_cells, "rho")
+        out = torch.empty_like(rho)
+        _check(_lib.mto_filter_apply(self.handle, _ptr(rho), _ptr(out), _stream(stream)))
+        return out
+
+    def grad(self, g_tilde, stream=None):
+        """dJ/drho = W^T dJ/drho~ (new device tensor)."""
+        import torch
+
+        _f64_cuda(g_tilde, self.n_cells, "g_tilde")
+        out = torch.empty_like(g_tilde)
+        _check(_lib.mto_filter_grad(self.handle, _ptr(g_tilde), _ptr(out), _stream(stream)))
+        return out

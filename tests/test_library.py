@@ -116,3 +116,18 @@ def test_generators_are_seeded_and_shaped():
     # neighbouring orders differ by at most 2 (smoothing step of Sec. 3.3)
     pp = m.p.reshape(m.nely, m.nelx).astype(int)
     assert np.abs(np.diff(pp, axis=0)).max() <= 2 and np.abs(np.diff(pp, axis=1)).max() <= 2
+
+
+def test_filter_rejects_bad_radius_and_mesh():
+    """mto_filter_create validates R and d on the host before any device work."""
+    pr = P.uniform_random(3, 2, 2, 2, 0)
+    for R in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(mto.MtoError) as ei:
+            mto.Filter(pr, R)
+        assert ei.value.code == mto.MTO_EINVAL
+    bad = P.uniform_random(3, 2, 2, 2, 0)
+    bad.d = bad.d.copy()
+    bad.d[1] = 9
+    with pytest.raises(mto.MtoError) as ei:
+        mto.Filter(bad, 0.5)
+    assert ei.value.code == mto.MTO_EINVAL
