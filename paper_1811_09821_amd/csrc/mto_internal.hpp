@@ -106,7 +106,22 @@ struct SysDesc {
 
 constexpr int MG_CHUNK = 256;      // nodes per level-kernel block
 constexpr int MG_COARSE_MAX = 3000;  // DOFs of the coarsest grid (dense inverse from a band Cholesky)
-constexpr int MG_BAND_MAX = 88;      // its band width: the Cholesky window of (b+1)^2 doubles fits 64 KB of LDS
+constexpr int MG_BAND_MAX = 80;      // its band width: the Cholesky window of (b+9)(b+1) doubles and an
+                                     // 8-column panel of (b+8) rows fit 64 KB of LDS
+// Band factor storage per instance (n coarsest DOFs), zero outside the band:
+//   row form    rows -MG_INV_PD .. n + MG_INV_PD - 1, stride MG_BAND_RS:
+//               [t] = L[i][i - t] (t = 1 .. b), [128] = 1 / L[i][i]
+//   column form columns 0 .. n + MG_INV_PD - 1, stride MG_BAND_CS:
+//               [t] = L[j + 1 + t][j] (t = 0 .. b - 1), [127] = 1 / L[j][j]
+// The padding lets the substitution kernels load two 64-entry runs per step
+// without bounds tests (b < 64 + 64); the reciprocal diagonal sits where the
+// run of the lane that finishes the row would otherwise read a zero.
+constexpr int MG_INV_PD = 8;     // substitution steps whose factor entries are in flight
+constexpr int MG_BAND_RS = 130;
+constexpr int MG_BAND_CS = 128;
+inline int64_t mg_band_doubles(int64_t n) {
+  return (n + 2 * MG_INV_PD) * MG_BAND_RS + (n + MG_INV_PD) * MG_BAND_CS;
+}
 
 // Work unit of the level kernels: nodes [node_begin, node_end) of the level
 // grid of one system (vector kernels) or one instance (operator kernels; sys

@@ -214,10 +214,11 @@ __global__ __launch_bounds__(MGB) void k_mg_rap(const MgChunk* __restrict__ chun
 // The coarsest grid (up to MG_COARSE_MAX DOFs) is solved exactly by a dense
 // inverse, formed once per design: its DOFs are renumbered with the shorter
 // side of the grid running fastest, which makes the operator banded with
-// lower bandwidth b = 2 m + 5 (m elements along the short side); a
-// right-looking band Cholesky runs in one block with a sliding window of
-// b + 1 rows in LDS; then every column of the inverse is one forward and one
-// backward band substitution, one thread per column; finally symmetrised.
+// lower bandwidth b = 2 m + 5 (m elements along the short side); a blocked
+// right-looking band Cholesky runs in one block with a sliding window of rows
+// in LDS; then every column of the inverse's lower triangle is one forward
+// and one (truncated) backward band substitution in one wave; finally the
+// triangle is mirrored into the natural numbering.
 
 // node q couples to q +- (m + 2) at most (m = elements along the short side),
 // so DOF 2 q + c couples to DOFs at most 2 (m + 2) + 1 away
@@ -245,75 +246,6 @@ __device__ __forceinline__ double band_entry(const MgChunk& ch, const double* __
   return A[node * 36 + ((dy + 1) * 3 + (dx + 1)) * 4 + (d1 & 1) * 2 + (d2 & 1)];
 }
 
-// Band Cholesky of one instance's coarsest operator: band[j][k] = L[j][j - k].
-// Two barriers per column: (1) scale column j below the diagonal and retire
-// row j to global memory; (2) the rank-1 update of the window and the load of
-// row j + b + 1 into the slot row j has left.
-constexpr int MG_CHOL_BLOCK = 1024;
-
-__global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk* __restrict__ chunks,
-                                                                 const double* __restrict__ A,
-                                                                 double* __restrict__ band) {
-  extern __shared__ double W[];  // window [(b + 1)][(b + 1)], row i in slot i % (b + 1)
-  constexpr int D = 4;           // rows of A requested ahead (thread k < b + 1 holds entry k)
-  const MgChunk ch = chunks[blockIdx.x];
-  const int n = 2 * (ch.node_end - ch.node_begin);
-  const int b = band_width(ch), w = b + 1;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  double* __restrict__ out = band + ch.band_off;
-  for (int idx = tid; idx < w * w; idx += nt) {
-    const int r = idx / w, k = idx - r * w;
-    W[idx] = (r < n && r - k >= 0) ? band_entry(ch, A, r, r - k) : 0.0;
-  }
-  auto row_entry = [&](int r) { return (tid < w && r < n && r - tid >= 0) ? band_entry(ch, A, r, r - tid) : 0.0; };
-  double pre[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) pre[d] = row_entry(w + d);
-  __syncthreads();
-  int sj = 0;  // slot of row j
-  for (int j0 = 0; j0 < n; j0 += D) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int j = j0 + d;
-      if (j >= n) break;  // uniform
-      // slot of row j + e (0 <= e <= b)
-      auto slot = [&](int e) { return sj + e >= w ? sj + e - w : sj + e; };
-      const double dj = sqrt(W[sj * w]);
-      const double rj = 1.0 / dj;
-      const int m = min(b, n - 1 - j);
-      for (int ii = tid; ii < m; ii += nt) W[slot(ii + 1) * w + (ii + 1)] *= rj;
-      for (int k = tid; k < w; k += nt) out[(int64_t)j * w + k] = k == 0 ? dj : W[sj * w + k];
-      __syncthreads();
-      for (int idx = tid; idx < m * m; idx += nt) {
-        const int ii = idx / m, kk = idx - ii * m;
-        if (kk > ii) continue;
-        // rows i = j + 1 + ii, k = j + 1 + kk: W[i][i - k] -= L[i][j] L[k][j]
-        W[slot(ii + 1) * w + (ii - kk)] -= W[slot(ii + 1) * w + (ii + 1)] * W[slot(kk + 1) * w + (kk + 1)];
-      }
-      // row j + w (first touched by step j + 1) into the slot row j has left
-      if (tid < w) W[sj * w + tid] = pre[d];
-      pre[d] = row_entry(j + w + D);
-      sj = sj + 1 == w ? 0 : sj + 1;
-      __syncthreads();
-    }
-  }
-}
-
-// Column c of the inverse (band numbering) per wave: y = L^-1 e_c, then
-// x = L^-T y, by column-oriented substitution: every pending row k of the
-// band keeps its running sum in a register of lane k % 64 (slot (k / 64) % 2;
-// b < 128 keeps the live rows apart).  A step finishes one row in its owner
-// lane, broadcasts the value with a lane read, and every lane updates the
-// rows it owns, so the dependency chain per step is one multiply, one lane
-// read and one FMA; the entries of L for the next step are requested one
-// step ahead.  y and x live in LDS (x overwrites y); the column is written
-// as row c of scr (band order).
-constexpr int MG_INV_WAVES = 2;
-
-// Wait for this wave's LDS operations only (lgkmcnt = 0; vmcnt and expcnt
-// left at their maxima), so prefetched global loads stay in flight.
-__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
-
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const long long u = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
@@ -321,119 +253,273 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Blocked band Cholesky of one instance's coarsest operator, NB columns per
+// step.  Outputs: the row form (L[i][i - t]) and the column form
+// (L[j + 1 + t][j]), each with 1 / L[i][i], in the padded layout described
+// with MG_BAND_RS.
+//   Window: rows J .. J + b + NB - 1 in a ring of b + NB slots (row i in
+//   slot i % (b + NB)), slot row t holding entry (i, i - t).
+//   Step J: wave 0 loads the panel (columns J .. J + NB - 1 of its b + NB
+//   rows, two rows per lane) into registers and factors it column by column
+//   (diagonal and column entries broadcast with lane reads), then writes it to
+//   LDS and to both outputs; after a barrier every thread applies the rank-NB
+//   update to its (row, up to 4 columns) of the trailing b x b triangle, and
+//   the NB retired slots are refilled with the next rows of the operator
+//   (loaded before the panel).  Two barriers per NB columns.
+constexpr int MG_CHOL_BLOCK = 1024;
+constexpr int MG_CHOL_NB = 8;
+constexpr int MG_CHOL_LP = MG_CHOL_NB + 1;  // panel row stride in LDS (odd, against bank conflicts)
+
+__host__ __device__ constexpr int chol_items(int b) {  // trailing-update items: sum over rows of ceil((ii + 1) / 4)
+  return b <= 0 ? 0 : chol_items(b - 1) + (b + 3) / 4;
+}
+static_assert(chol_items(MG_BAND_MAX) <= MG_CHOL_BLOCK, "band too wide for one update item per thread");
+static_assert(MG_BAND_MAX + MG_CHOL_NB <= 128, "panel rows must fit two per lane");
+
+size_t chol_lds_bytes(int b) {
+  const int R = b + MG_CHOL_NB;
+  return (size_t)(R * (b + 1) + R * MG_CHOL_LP) * sizeof(double);
+}
+
+__global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk* __restrict__ chunks,
+                                                                 const double* __restrict__ A,
+                                                                 double* __restrict__ band) {
+  extern __shared__ double lds_chol[];
+  constexpr int NB = MG_CHOL_NB, LP = MG_CHOL_LP;
+  const MgChunk ch = chunks[blockIdx.x];
+  const int n = 2 * (ch.node_end - ch.node_begin);
+  const int b = band_width(ch), w = b + 1, R = b + NB;
+  double* __restrict__ W = lds_chol;            // [R][w]
+  double* __restrict__ Lp = lds_chol + R * w;   // [R][LP]: panel row J + r at r
+  const int tid = threadIdx.x, nt = blockDim.x, wave = tid >> 6, lane = tid & 63;
+  double* __restrict__ out = band + ch.band_off + MG_INV_PD * MG_BAND_RS;                   // row form
+  double* __restrict__ outc = band + ch.band_off + (int64_t)(n + 2 * MG_INV_PD) * MG_BAND_RS;  // column form
+  for (int idx = tid; idx < R * w; idx += nt) {
+    const int r = idx / w, t = idx - r * w;
+    W[idx] = (r < n && r - t >= 0) ? band_entry(ch, A, r, r - t) : 0.0;
+  }
+  // this thread's trailing-update item: relative row ii, columns g, g + G, g + 2G, g + 3G (<= ii),
+  // G = ceil((ii + 1) / 4); consecutive threads take consecutive columns of a row
+  int my_ii = -1, my_g = 0, my_G = 1;
+  {
+    int acc = 0;
+    for (int ii = 0; ii < b; ++ii) {
+      const int G = (ii + 4) >> 2;
+      if (tid < acc + G) {
+        my_ii = ii;
+        my_g = tid - acc;
+        my_G = G;
+        break;
+      }
+      acc += G;
+    }
+  }
+  __syncthreads();
+  for (int J = 0; J < n; J += NB) {  // uniform
+    const int nb = min(NB, n - J);
+    // rows J + R .. J + R + NB - 1 enter the slots of rows J .. J + NB - 1 after the panel
+    double pre = 0.0;
+    int pre_at = -1;
+    if (tid < NB * w) {
+      const int r = J + R + tid / w, t = tid - (tid / w) * w;
+      pre_at = (r % R) * w + t;
+      pre = (r < n && r - t >= 0) ? band_entry(ch, A, r, r - t) : 0.0;
+    }
+    if (wave == 0) {
+      double p[2][NB];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q, i = J + r;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          const int o = r - t;
+          p[q][t] = (r < R && i < n && o >= 0 && o <= b) ? W[(i % R) * w + o] : 0.0;
+        }
+      }
+      double rjs[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        rjs[t] = 0.0;
+        if (t >= nb) break;  // uniform
+        const double dj = sqrt(readlane_f64(p[0][t], t));
+        const double rj = 1.0 / dj;
+        rjs[t] = rj;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int r = lane + 64 * q;
+          p[q][t] = r > t ? p[q][t] * rj : (r == t ? dj : 0.0);
+        }
+#pragma unroll
+        for (int t2 = t + 1; t2 < NB; ++t2) {
+          const double v = readlane_f64(p[0][t], t2);  // L[J + t2][J + t]
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int r = lane + 64 * q;
+            if (r >= t2) p[q][t2] = fma(-p[q][t], v, p[q][t2]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q, i = J + r;
+        if (r < R) {
+#pragma unroll
+          for (int t = 0; t < NB; ++t) Lp[r * LP + t] = p[q][t];
+        }
+        if (r < R && i < n) {
+#pragma unroll
+          for (int t = 0; t < NB; ++t) {
+            const int o = r - t;
+            if (t < nb && o >= 0 && o <= b) {
+              if (o == 0) {
+                out[(int64_t)i * MG_BAND_RS + 128] = rjs[t];
+                outc[(int64_t)i * MG_BAND_CS + 127] = rjs[t];
+              } else {
+                out[(int64_t)i * MG_BAND_RS + o] = p[q][t];
+                outc[(int64_t)(J + t) * MG_BAND_CS + (o - 1)] = p[q][t];
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (my_ii >= 0) {
+      const int i = J + NB + my_ii;
+      if (i < n) {
+        double li[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) li[t] = Lp[(NB + my_ii) * LP + t];
+        double* __restrict__ Wi = W + (i % R) * w;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kk = my_g + u * my_G;
+          if (kk <= my_ii) {
+            const double* __restrict__ lk = Lp + (NB + kk) * LP;
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < NB; ++t) s = fma(li[t], lk[t], s);
+            Wi[my_ii - kk] -= s;
+          }
+        }
+      }
+    }
+    if (pre_at >= 0) W[pre_at] = pre;
+    __syncthreads();
+  }
+}
+
+// Column c of the inverse's lower triangle (band numbering) per wave:
+// y = L^-1 e_c (rows c .. n-1), then x = L^-T y for rows n-1 down to c, by
+// column-oriented substitution.  Every pending row keeps its running sum in
+// the lane congruent to it mod 64: before step i a lane holds its nearest
+// row on the unfinished side of i ("near") and the next one beyond ("far",
+// 64 further); b < 128 keeps every row of the band in one of the two.  A
+// step finishes row i in lane i % 64 (one multiply by 1 / L[i][i], which
+// that lane finds in its own run of factor entries),
+// broadcasts the value with a lane read, shifts that lane's far sum into its
+// near one, and every lane applies the step to both its sums with one FMA
+// each.  The factor entries come from the zero-padded row and column forms
+// as two contiguous 64-entry runs, with no bounds tests, and those for the
+// next MG_INV_PD steps are in flight.  y and x live in LDS (x overwrites y);
+// rows c .. n-1 of the column are written to row c of scr.
+constexpr int MG_INV_WAVES = 2;
+
+// Wait for this wave's LDS operations only (lgkmcnt = 0; vmcnt and expcnt
+// left at their maxima), so prefetched global loads stay in flight.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
 __global__ __launch_bounds__(64 * MG_INV_WAVES) void k_mg_coarse_inv(const MgChunk* __restrict__ chunks,
                                                                      const double* __restrict__ band,
                                                                      double* __restrict__ scr, int nmax) {
   extern __shared__ double ys_all[];  // [MG_INV_WAVES][nmax]
+  constexpr int PD = MG_INV_PD;
   const MgChunk ch = chunks[blockIdx.y];
   const int n = 2 * (ch.node_end - ch.node_begin);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * MG_INV_WAVES + wave;
+  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * MG_INV_WAVES + wave);  // wave-uniform
   if (c >= n) return;  // whole wave
-  const int b = band_width(ch), w = b + 1;
-  const double* __restrict__ L = band + ch.band_off;
+  const double* __restrict__ Lr = band + ch.band_off + PD * MG_BAND_RS;
+  const double* __restrict__ Lc = band + ch.band_off + (int64_t)(n + 2 * PD) * MG_BAND_RS;
   double* ys = ys_all + wave * nmax;
   for (int i = lane; i < n; i += 64) ys[i] = 0.0;
   wait_lds();
   __builtin_amdgcn_wave_barrier();
-  double acc0 = 0.0, acc1 = 0.0;
-  if (lane == (c & 63)) {
-    if ((c >> 6) & 1) acc1 = 1.0;
-    else acc0 = 1.0;
-  }
-  // forward: at step i the lane's rows are k1 = i + 1 + ((lane - i - 1) & 63) and k1 + 64
-  auto fwd_load = [&](int i, double& la, double& lb, double& rd) {
-    const int k1 = i + 1 + ((lane - i - 1) & 63), k2 = k1 + 64, khi = min(i + b, n - 1);
-    la = (i < n && k1 <= khi) ? L[(int64_t)k1 * w + (k1 - i)] : 0.0;
-    lb = (i < n && k2 <= khi) ? L[(int64_t)k2 * w + (k2 - i)] : 0.0;
-    rd = i < n ? L[(int64_t)i * w] : 1.0;  // the diagonal; its reciprocal is formed at use
+  double pla[PD], plb[PD];
+  // forward: near = the lane's smallest row >= i, far = near + 64; step i updates
+  // rows i + 1 + t and i + 65 + t, t = (lane - i - 1) & 63 (column i of L); the
+  // owner lane (t = 63) finds 1 / L[i][i] in its second entry
+  auto fwd_load = [&](int i, double& la, double& lb) {
+    const double* __restrict__ col = Lc + (int64_t)i * MG_BAND_CS;
+    const int t = (lane - i - 1) & 63;
+    la = col[t];
+    lb = col[t + 64];
   };
-  // entries of L for the next PD steps in flight (a ring, indexed at compile time)
-  constexpr int PD = 8;
-  double pla[PD], plb[PD], prd[PD];
+  double an = lane == (c & 63) ? 1.0 : 0.0, af = 0.0;
 #pragma unroll
-  for (int d = 0; d < PD; ++d) fwd_load(c + d, pla[d], plb[d], prd[d]);
-  for (int i0 = c; i0 < n; i0 += PD) {
+  for (int d = 0; d < PD; ++d) fwd_load(c + d, pla[d], plb[d]);
+  auto fwd_step = [&](int i, int d) {
+    const int oi = i & 63;
+    const double y = readlane_f64(an * plb[d], oi);
+    const bool own = lane == oi;
+    if (own) ys[i] = y;
+    an = fma(-pla[d], y, own ? af : an);
+    af = own ? 0.0 : fma(-plb[d], y, af);
+    fwd_load(i + PD, pla[d], plb[d]);
+  };
+  int i0 = c;
+  for (; i0 + PD <= n; i0 += PD) {  // full groups: no exits inside
 #pragma unroll
-    for (int d = 0; d < PD; ++d) {
-      const int i = i0 + d;
-      if (i >= n) break;  // uniform
-      const int oi = i & 63, si = (i >> 6) & 1;
-      const double y = readlane_f64((si ? acc1 : acc0) * (1.0 / prd[d]), oi);
-      if (lane == oi) {
-        if (si) acc1 = 0.0;
-        else acc0 = 0.0;
-        ys[i] = y;
-      }
-      const int k1 = i + 1 + ((lane - i - 1) & 63), k2 = k1 + 64, khi = min(i + b, n - 1);
-      if (k1 <= khi) {
-        if ((k1 >> 6) & 1) acc1 = fma(-pla[d], y, acc1);
-        else acc0 = fma(-pla[d], y, acc0);
-      }
-      if (k2 <= khi) {
-        if ((k2 >> 6) & 1) acc1 = fma(-plb[d], y, acc1);
-        else acc0 = fma(-plb[d], y, acc0);
-      }
-      fwd_load(i + PD, pla[d], plb[d], prd[d]);
-    }
+    for (int d = 0; d < PD; ++d) fwd_step(i0 + d, d);
   }
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (i0 + d < n) fwd_step(i0 + d, d);  // uniform
   wait_lds();  // ys complete (each wave reads only its own ys; no block barrier, waves may have left)
   __builtin_amdgcn_wave_barrier();
-  // backward: rows j in [i - b, i - 1], the lane's being j1 = i - 1 - ((i - 1 - lane) & 63) and j1 - 64
-  acc0 = acc1 = 0.0;
-  {
-    const int jlo = max(0, n - 1 - b);
-    for (int j = jlo + ((lane - jlo) & 63); j < n; j += 64) {  // the rows this lane owns (j % 64 == lane)
-      if ((j >> 6) & 1) acc1 = ys[j];
-      else acc0 = ys[j];
-    }
-  }
-  auto bwd_load = [&](int i, double& la_, double& lb_, double& rd_) {
-    const int j1 = i - 1 - ((i - 1 - lane) & 63), j2 = j1 - 64, jlo = max(0, i - b);
-    la_ = (i >= 0 && j1 >= jlo) ? L[(int64_t)i * w + (i - j1)] : 0.0;
-    lb_ = (i >= 0 && j2 >= jlo) ? L[(int64_t)i * w + (i - j2)] : 0.0;
-    rd_ = i >= 0 ? L[(int64_t)i * w] : 1.0;
+  // backward: near = the lane's largest row <= i, far = near - 64; step i updates
+  // rows i - 1 - u and i - 65 - u, u = (i - 1 - lane) & 63 (row i of L); sums
+  // start at y; the owner lane (u = 63) finds 1 / L[i][i] in its second entry
+  auto bwd_load = [&](int i, double& la, double& lb) {
+    const double* __restrict__ row = Lr + (int64_t)i * MG_BAND_RS;
+    const int u = (i - 1 - lane) & 63;
+    la = row[1 + u];
+    lb = row[65 + u];
   };
-#pragma unroll
-  for (int d = 0; d < PD; ++d) bwd_load(n - 1 - d, pla[d], plb[d], prd[d]);
-  for (int i0 = n - 1; i0 >= 0; i0 -= PD) {
-#pragma unroll
-    for (int d = 0; d < PD; ++d) {
-      const int i = i0 - d;
-      if (i < 0) break;  // uniform
-      const int oi = i & 63, si = (i >> 6) & 1;
-      const double x = readlane_f64((si ? acc1 : acc0) * (1.0 / prd[d]), oi);
-      if (lane == oi) {
-        if (si) acc1 = 0.0;
-        else acc0 = 0.0;
-        ys[i] = x;
-      }
-      const int j1 = i - 1 - ((i - 1 - lane) & 63), j2 = j1 - 64, jlo = max(0, i - b);
-      if (j1 >= jlo) {
-        if ((j1 >> 6) & 1) acc1 = fma(-pla[d], x, acc1);
-        else acc0 = fma(-pla[d], x, acc0);
-      }
-      if (j2 >= jlo) {
-        if ((j2 >> 6) & 1) acc1 = fma(-plb[d], x, acc1);
-        else acc0 = fma(-plb[d], x, acc0);
-      }
-      // row i - 1 - b enters the window: its sum starts at y
-      const int jn = i - 1 - b;
-      if (jn >= 0 && lane == (jn & 63)) {
-        if ((jn >> 6) & 1) acc1 = ys[jn];
-        else acc0 = ys[jn];
-      }
-      bwd_load(i - PD, pla[d], plb[d], prd[d]);
-    }
+  {
+    const int jn = n - 1 - ((n - 1 - lane) & 63);
+    an = jn >= 0 ? ys[jn] : 0.0;
+    af = jn >= 64 ? ys[jn - 64] : 0.0;
   }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) bwd_load(n - 1 - d, pla[d], plb[d]);
+  auto bwd_step = [&](int i, int d) {
+    const int oi = i & 63;
+    const double x = readlane_f64(an * plb[d], oi);
+    const bool own = lane == oi;
+    if (own) ys[i] = x;
+    const double enter = i >= 128 ? ys[i - 128] : 0.0;  // the owner's new far row starts at y
+    an = fma(-pla[d], x, own ? af : an);
+    af = own ? enter : fma(-plb[d], x, af);
+    bwd_load(i - PD, pla[d], plb[d]);
+  };
+  i0 = n - 1;
+  for (; i0 - PD + 1 >= c; i0 -= PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) bwd_step(i0 - d, d);
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (i0 - d >= c) bwd_step(i0 - d, d);  // uniform
   wait_lds();
   __builtin_amdgcn_wave_barrier();
   double* __restrict__ row = scr + ch.dense_off + (int64_t)c * n;
-  for (int i = lane; i < n; i += 64) row[i] = ys[i];
+  for (int i = c + lane; i < n; i += 64) row[i] = ys[i];
 }
 
-// dense = (P X P^T + (P X P^T)^T) / 2 in natural order, from the band-order
-// rows scr (X = the inverse in band numbering, P the renumbering).
+// dense = P X P^T in natural order from the lower triangle of X (band
+// numbering, column j stored from entry j on as row j of scr); P is the
+// renumbering.  X is symmetric, so the upper triangle is its mirror.
 __global__ __launch_bounds__(256) void k_mg_coarse_sym(const MgChunk* __restrict__ chunks, const double* __restrict__ scr,
                                                        double* __restrict__ dense) {
   const MgChunk ch = chunks[blockIdx.y];
@@ -446,8 +532,8 @@ __global__ __launch_bounds__(256) void k_mg_coarse_sym(const MgChunk* __restrict
     return 2 * (ch.ny <= ch.nx ? x * (ch.ny + 1) + y : y * (ch.nx + 1) + x) + (d & 1);
   };
   const int bi = band_of(i), bj = band_of(j);
-  const double* __restrict__ X = scr + ch.dense_off;
-  dense[ch.dense_off + idx] = 0.5 * (X[(int64_t)bi * n + bj] + X[(int64_t)bj * n + bi]);
+  const int lo = min(bi, bj), hi = max(bi, bj);
+  dense[ch.dense_off + idx] = scr[ch.dense_off + (int64_t)lo * n + hi];
 }
 
 // Level 0 -> 1: t = r - A0 z at the vertex DOFs (A0 z in the slots), injected;
@@ -921,8 +1007,7 @@ void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_
 void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* scr,
                             double* dense, hipStream_t st) {
   if (!n) return;
-  const size_t lds = (size_t)(bmax + 1) * (bmax + 1) * 8;
-  hipLaunchKernelGGL(k_mg_coarse_chol, dim3(n), dim3(MG_CHOL_BLOCK), lds, st, ch, A, band);
+  hipLaunchKernelGGL(k_mg_coarse_chol, dim3(n), dim3(MG_CHOL_BLOCK), chol_lds_bytes(bmax), st, ch, A, band);
   hipLaunchKernelGGL(k_mg_coarse_inv, dim3((nmax + MG_INV_WAVES - 1) / MG_INV_WAVES, n), dim3(64 * MG_INV_WAVES),
                      (size_t)MG_INV_WAVES * nmax * 8, st, ch, band, scr, nmax);
   const int64_t nn = (int64_t)nmax * nmax;

@@ -334,7 +334,7 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
     dense_off[i] = dense_tot;
     dense_tot += 4 * N * N;
     band_off[i] = band_tot;
-    band_tot += 2 * N * (bw + 1);
+    band_tot += mg_band_doubles(2 * N);
     M.coarse_nmax = std::max<int>(M.coarse_nmax, (int)(2 * N));
     M.coarse_bmax = std::max(M.coarse_bmax, bw);
   }
@@ -440,6 +440,7 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
       (rc = dev_upload(P, &M.vfree, vfree)) || (rc = dev_upload(P, &M.elems, elems)) ||
       (rc = dev_upload(P, &M.kv, kvpool)))
     return rc;
+  launch_fill(M.band, 0.0, band_tot, 0);  // the factor kernels write only inside the band
   launch_fill(M.e, 0.0, 2 * vec_tot, 0);
   launch_fill(M.e2, 0.0, 2 * vec_tot, 0);
   launch_fill(M.r, 0.0, 2 * vec_tot, 0);
