@@ -17,6 +17,9 @@ What it computes, in plain FP64 (longdouble for residual accumulation):
   direct factorisation followed by extended-precision iterative refinement;
 * the density filter of Sec. 2.2 (Eqs. (4)-(5)) on the density cells and
   the chain rule through it (``filter.py``);
+* the QR-error indicator of Sec. 3.2.3 (Eq. (9)): the element-level
+  order-(p+1) problem under the element's own load and the strain-energy
+  ratio (``qr.py``);
 * compliance c = f^T u (Sec. 4.1, z = f) and the per-cell sensitivity
   dc/drho = -E'(rho) u_e^T K_s u_e (the paper names the sensitivity analysis
   in Sec. 1 and Sec. 2.1 but prints no formula; this is the adjoint result for
@@ -25,7 +28,8 @@ What it computes, in plain FP64 (longdouble for residual accumulation):
 Every function cites the passage it follows.  Readings of points the paper
 leaves open (basis, mixed-p compatibility, layouts) are listed in the design doc of
 the repository.  Parity status: every function is pinned by ``-m "not gpu"``
-tests in ``tests/test_oracle_pins.py``; none is "parity unpinned".
+tests in ``tests/test_oracle_pins.py``, ``tests/test_filter_pins.py`` and
+``tests/test_qr_pins.py``; none is "parity unpinned".
 """
 
 from .fem import (  # noqa: F401
@@ -38,3 +42,4 @@ from .fem import (  # noqa: F401
 from .space import DofSpace, build_space  # noqa: F401
 from .solve import oracle_solve, assemble, element_dofs_global  # noqa: F401
 from .filter import filter_apply, filter_grad, filter_matrix, filter_weights  # noqa: F401
+from .qr import element_qr_error, qr_error  # noqa: F401

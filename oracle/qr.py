@@ -1,0 +1,93 @@
+"""QR-error indicator of Sec. 3.2.3 (Eq. (9)): for every element, the change
+of its strain energy when its shape functions are raised from order p to
+p + 1 under the same element load.
+
+Test infrastructure only (see the package docstring).
+
+For element k with order p and displacements u^(p) (its local DOFs taken
+from the global solution):
+  * K^(p) = sum_s E(rho_s) K_s^(p), K^(p+1) = sum_s E(rho_s) K_s^(p+1)
+    (composite integration over the element's density cells);
+  * the internal load vector f^(p) = K^(p) u^(p) and J^(p) = 1/2 u^(p)T K^(p) u^(p);
+  * f^(p+1): the same load expressed on the refined functions.  Reading: the
+    basis is hierarchic, so every order-p function is also an order-(p+1)
+    function; the load keeps its value on those and is zero on the new
+    functions (the same work against every order-p field);
+  * u^(p+1) solves K^(p+1) u = f^(p+1) with 3 DOFs (as many as the rigid
+    motions in 2D) copied from u^(p).  Reading: the x and y DOFs of the
+    vertex at (0, 0) and the y DOF of the vertex at (1, 0) of the element;
+  * J^(p+1) = 1/2 u^(p+1)T K^(p+1) u^(p+1) and eps = 1 - J^(p) / J^(p+1).
+    Where J^(p+1) = 0 (a rigid motion) eps is 0.
+
+The load is self-equilibrated (rigid motions lie in the order-p space and
+K^(p) annihilates them), so the reactions at the 3 pinned DOFs vanish and the
+result does not depend on which 3 DOFs are pinned or on their values.
+"""
+
+import numpy as np
+
+from .fem import simp_modulus, subcell_stiffness
+from .solve import cell_offsets, element_dofs_global
+from .space import build_space
+
+PINNED = (0, 1, 3)  # local DOFs: vertex (0,0) x and y, vertex (1,0) y (2a + c with a = i for j = 0)
+
+
+def embed_index(p):
+    """Local DOF of the order-(p+1) element that carries order-p local DOF
+    2 a + c, a = j (p+1) + i: the same tensor-product function, index
+    a' = j (p+2) + i."""
+    n1 = p + 1
+    out = np.empty(2 * n1 * n1, dtype=np.int64)
+    for j in range(n1):
+        for i in range(n1):
+            for c in range(2):
+                out[2 * (j * n1 + i) + c] = 2 * (j * (n1 + 1) + i) + c
+    return out
+
+
+def element_qr_error(Ks_p, Ks_p1, E, ue, p, pinned=PINNED):
+    """eps of Eq. (9) for one element: Ks_p [S, n_e, n_e] and Ks_p1
+    [S, n_e', n_e'] the cell matrices at orders p and p+1, E [S] the cell
+    moduli, ue [n_e] the element's order-p displacements."""
+    Kp = np.einsum("s,sij->ij", E, Ks_p)
+    Kq = np.einsum("s,sij->ij", E, Ks_p1)
+    f = Kp @ ue
+    Jp = 0.5 * ue @ Kp @ ue
+    emb = embed_index(p)
+    nq = Kq.shape[0]
+    fq = np.zeros(nq)
+    fq[emb] = f
+    pin = np.array([emb[k] for k in pinned])
+    vals = ue[list(pinned)]
+    free = np.setdiff1d(np.arange(nq), pin)
+    uq = np.zeros(nq)
+    uq[pin] = vals
+    rhs = fq[free] - Kq[np.ix_(free, pin)] @ vals
+    uq[free] = np.linalg.solve(Kq[np.ix_(free, free)], rhs)
+    Jq = 0.5 * uq @ Kq @ uq
+    return 0.0 if Jq <= 0.0 else 1.0 - Jp / Jq
+
+
+def qr_error(nelx, nely, p, d, rho, u, E0=1.0, Emin=1e-9, q=3.0, nu=0.3):
+    """eps [L, nel] for every load case of the global displacements u
+    [L, n_dof] (the oracle solve's layout)."""
+    p = np.asarray(p, dtype=np.int64).ravel()
+    d = np.asarray(d, dtype=np.int64).ravel()
+    u = np.atleast_2d(np.asarray(u, dtype=np.float64))
+    space = build_space(nelx, nely, p)
+    off = cell_offsets(d)
+    E = simp_modulus(np.asarray(rho, dtype=np.float64), E0, Emin, q)
+    cache = {}
+    out = np.zeros((u.shape[0], nelx * nely))
+    for e in range(nelx * nely):
+        pe, de = int(p[e]), int(d[e])
+        for key in ((pe, de), (pe + 1, de)):
+            if key not in cache:
+                cache[key] = subcell_stiffness(key[0], key[1], nu)
+        G = element_dofs_global(space, e)
+        Ee = E[off[e]:off[e + 1]]
+        for lc in range(u.shape[0]):
+            ue = np.where(G >= 0, u[lc][np.maximum(G, 0)], 0.0)
+            out[lc, e] = element_qr_error(cache[(pe, de)], cache[(pe + 1, de)], Ee, ue, pe)
+    return out
