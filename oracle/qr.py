@@ -46,14 +46,25 @@ def embed_index(p):
     return out
 
 
-def element_qr_error(Ks_p, Ks_p1, E, ue, p, pinned=PINNED):
+def _quad(K, u):
+    """u^T K u with the products accumulated in numpy.longdouble."""
+    ul = np.asarray(u, dtype=np.longdouble)
+    return ul @ (np.asarray(K, dtype=np.longdouble) @ ul)
+
+
+def element_qr_error(Ks_p, Ks_p1, E, ue, p, pinned=PINNED, rounds=3):
     """eps of Eq. (9) for one element: Ks_p [S, n_e, n_e] and Ks_p1
     [S, n_e', n_e'] the cell matrices at orders p and p+1, E [S] the cell
-    moduli, ue [n_e] the element's order-p displacements."""
+    moduli, ue [n_e] the element's order-p displacements.
+
+    An element that moves almost rigidly has a deformation many orders below
+    its displacement, so the energies are accumulated in numpy.longdouble and
+    the element solve is refined against a longdouble residual (as the global
+    solve of this package is)."""
     Kp = np.einsum("s,sij->ij", E, Ks_p)
     Kq = np.einsum("s,sij->ij", E, Ks_p1)
-    f = Kp @ ue
-    Jp = 0.5 * ue @ Kp @ ue
+    f = (np.asarray(Kp, dtype=np.longdouble) @ np.asarray(ue, dtype=np.longdouble)).astype(np.float64)
+    Jp = 0.5 * _quad(Kp, ue)
     emb = embed_index(p)
     nq = Kq.shape[0]
     fq = np.zeros(nq)
@@ -63,10 +74,13 @@ def element_qr_error(Ks_p, Ks_p1, E, ue, p, pinned=PINNED):
     free = np.setdiff1d(np.arange(nq), pin)
     uq = np.zeros(nq)
     uq[pin] = vals
-    rhs = fq[free] - Kq[np.ix_(free, pin)] @ vals
-    uq[free] = np.linalg.solve(Kq[np.ix_(free, free)], rhs)
-    Jq = 0.5 * uq @ Kq @ uq
-    return 0.0 if Jq <= 0.0 else 1.0 - Jp / Jq
+    Kff = Kq[np.ix_(free, free)]
+    for _ in range(rounds):
+        r = (np.asarray(fq[free], dtype=np.longdouble)
+             - np.asarray(Kq[free], dtype=np.longdouble) @ np.asarray(uq, dtype=np.longdouble))
+        uq[free] += np.linalg.solve(Kff, r.astype(np.float64))
+    Jq = 0.5 * _quad(Kq, uq)
+    return 0.0 if Jq <= 0.0 else float(1.0 - Jp / Jq)
 
 
 def qr_error(nelx, nely, p, d, rho, u, E0=1.0, Emin=1e-9, q=3.0, nu=0.3):
