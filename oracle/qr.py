@@ -21,7 +21,8 @@ from the global solution):
 
 The load is self-equilibrated (rigid motions lie in the order-p space and
 K^(p) annihilates them), so the reactions at the 3 pinned DOFs vanish and the
-result does not depend on which 3 DOFs are pinned or on their values.
+result does not depend on which 3 DOFs are pinned or on their values; both
+energies are unchanged by adding a rigid motion to u^(p).
 """
 
 import numpy as np
@@ -52,28 +53,55 @@ def _quad(K, u):
     return ul @ (np.asarray(K, dtype=np.longdouble) @ ul)
 
 
+def rigid_through(ue, p, pinned):
+    """The rigid motion (a - th y, b + th x) of the order-p element that takes
+    the values of ue at the 3 pinned local DOFs (vertex DOFs of the order-p
+    numbering), as order-p element DOFs (only the vertex functions carry it)."""
+    n1 = p + 1
+    rows, rhs = [], []
+    for k in pinned:
+        a = k // 2
+        i, j = a % n1, a // n1
+        assert i <= 1 and j <= 1, "pinned DOFs must be vertex DOFs"
+        rows.append([1.0, 0.0, -float(j)] if k % 2 == 0 else [0.0, 1.0, float(i)])
+        rhs.append(ue[k])
+    a, b, th = np.linalg.solve(np.array(rows), np.array(rhs))
+    r = np.zeros_like(ue)
+    for j in range(2):
+        for i in range(2):
+            k = j * n1 + i
+            r[2 * k] = a - th * j
+            r[2 * k + 1] = b + th * i
+    return r
+
+
 def element_qr_error(Ks_p, Ks_p1, E, ue, p, pinned=PINNED, rounds=3):
     """eps of Eq. (9) for one element: Ks_p [S, n_e, n_e] and Ks_p1
     [S, n_e', n_e'] the cell matrices at orders p and p+1, E [S] the cell
     moduli, ue [n_e] the element's order-p displacements.
 
-    An element that moves almost rigidly has a deformation many orders below
-    its displacement, so the energies are accumulated in numpy.longdouble and
-    the element solve is refined against a longdouble residual (as the global
-    solve of this package is)."""
+    Both energies are unchanged by adding a rigid motion to u^(p) (K^(p)
+    and K^(p+1) annihilate it, the load f^(p) does not see it, and the
+    copied values move u^(p+1) by the same motion), so the rigid motion
+    through the 3 pinned values is subtracted first and the pinned values
+    become zero.  In exact arithmetic this changes nothing; with the cell
+    matrices rounded to FP64 the literal u^T K u of an element that moves
+    almost rigidly (|u| >> |u - rigid|) would carry an error of relative size
+    eps_mach (|u| / |u - rigid|)^2.  The energies are accumulated in
+    numpy.longdouble and the element solve is refined against a longdouble
+    residual (as the global solve of this package is)."""
     Kp = np.einsum("s,sij->ij", E, Ks_p)
     Kq = np.einsum("s,sij->ij", E, Ks_p1)
-    f = (np.asarray(Kp, dtype=np.longdouble) @ np.asarray(ue, dtype=np.longdouble)).astype(np.float64)
-    Jp = 0.5 * _quad(Kp, ue)
+    ud = ue - rigid_through(ue, p, pinned)
+    f = (np.asarray(Kp, dtype=np.longdouble) @ np.asarray(ud, dtype=np.longdouble)).astype(np.float64)
+    Jp = 0.5 * _quad(Kp, ud)
     emb = embed_index(p)
     nq = Kq.shape[0]
     fq = np.zeros(nq)
     fq[emb] = f
     pin = np.array([emb[k] for k in pinned])
-    vals = ue[list(pinned)]
     free = np.setdiff1d(np.arange(nq), pin)
-    uq = np.zeros(nq)
-    uq[pin] = vals
+    uq = np.zeros(nq)  # the pinned values of u - rigid are zero
     Kff = Kq[np.ix_(free, free)]
     for _ in range(rounds):
         r = (np.asarray(fq[free], dtype=np.longdouble)
