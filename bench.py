@@ -14,7 +14,8 @@ fraction 0.4, unit load at the mid-right vertex.
 
 Prints one JSON line (metric, value in seconds per design, roofline of the
 element-contraction kernel, CPU-oracle baseline, and the launch time of the
-density filter of Sec. 2.2 and its chain rule on the same cells, outside the
+density filter of Sec. 2.2 and its chain rule on the same cells and of the
+QR-error indicator of Sec. 3.2.3 on the solved designs, both outside the
 timed step).
 """
 
@@ -103,6 +104,26 @@ def time_filter(mto, prs, rho, R, reps=200):
     return res
 
 
+def time_qr(plan, rho, u, reps=5):
+    """QR-error indicator (Sec. 3.2.3, Eq. (9)) for every element and load
+    case of the solved designs: mean time per call over `reps` calls after
+    one untimed call (which builds the order-(p+1) tables)."""
+    import torch
+
+    eps = plan.qr_error(rho, u)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        eps = plan.qr_error(rho, u)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"ms_per_call": round(ms, 4), "element_problems": plan.n_eps,
+            "element_problems_per_s": round(plan.n_eps / (ms * 1e-3), 1),
+            "eps_mean": round(float(eps.mean()), 6), "eps_gt_0.9": int((eps > 0.9).sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +138,7 @@ def main():
     ap.add_argument("--compare-plain", action="store_true", help="also time the plain per-element path")
     ap.add_argument("--filter-radius", type=float, default=0.3,
                     help="density-filter radius in element edge lengths for the filter timing (0 skips it)")
+    ap.add_argument("--no-qr", action="store_true", help="skip the QR-error indicator timing")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -220,6 +242,8 @@ def main():
 
     if args.filter_radius > 0:
         out["density_filter"] = time_filter(mto, prs, rho, args.filter_radius)
+    if not args.no_qr:
+        out["qr_error"] = time_qr(plan, rho, u)
 
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 8

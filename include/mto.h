@@ -260,6 +260,25 @@ int mto_time_contraction(mto_plan* plan, const double* rho, int32_t reps, int32_
 /* Frees the plan and its device buffers (NULL is a no-op). */
 void mto_plan_destroy(mto_plan* plan);
 
+/* QR-error indicator of Sec. 3.2.3 (Eq. (9)) for every element and load case:
+ * eps = 1 - J^(p) / J^(p+1), with J^(p) = u_e^T K^(p) u_e / 2 the element's
+ * strain energy at order p (K^(p) = sum_s E(rho_s) K_s^(p)) and J^(p+1) that
+ * of the element-level problem at order p + 1, K^(p+1) u' = f', under the
+ * element's own load f^(p) = K^(p) u_e kept on the (hierarchic) order-p
+ * functions and zero on the new ones, with 3 DOFs (vertex (0,0) x and y,
+ * vertex (1,0) y) taken from u_e; eps = 0 where J^(p+1) = 0.  The energies do
+ * not depend on the choice or the values of the 3 DOFs (the load is
+ * self-equilibrated), so the rigid motion they carry is removed first.
+ *   rho  device, n_cells doubles (the densities u was computed for)
+ *   u    device, u layout (as written by mto_solve)
+ *   eps  device, sum over instances of L_i nel_i doubles: instance-major,
+ *        then load case, then element e = ey*nelx + ex
+ * Overwrites the plan's moduli and PCG work vectors (like mto_sensitivity).
+ * The order-(p+1) cell tables are built on the host and uploaded at the
+ * first call (p + 1 <= MTO_MAX_P + 1), which therefore allocates: do not
+ * make the first call inside stream capture.  MTO_EINVAL, MTO_ENOMEM. */
+int mto_qr_error(mto_plan* plan, const double* rho, const double* u, double* eps, void* stream);
+
 /* ---- density filter (Sec. 2.2, Eqs. (4)-(5)) ------------------------------
  * The step that precedes the analysis: filtered densities
  *   rho~_i = sum_j H_ij rho_j / sum_j H_ij,   H_ij = R - |c_i - c_j|  (> 0),

@@ -23,6 +23,18 @@ struct GroupDev {
   const int32_t* cell;     // [npad] first density cell (global)
 };
 
+// One (p, d) group for the QR-error indicator: order-(p+1) cell tables and
+// the instance and element of every group column.
+struct QrGroupDev {
+  int32_t p, d, S, npad;
+  int32_t n_elems;
+  const double* tab;      // [S][NT] packed lower triangle of K_s^(p+1), (i, j <= i) at i (i+1)/2 + j
+  const int32_t* gidx;    // as GroupDev::gidx
+  const int32_t* cell;    // as GroupDev::cell
+  const int32_t* eid;     // [n_elems] element index within its instance
+  const int32_t* einst;   // [n_elems] instance
+};
+
 // Slots of free DOF i of a system: 4 per vertex DOF, 2 per edge DOF, 1 per
 // interior DOF, in that order.
 __device__ __forceinline__ void slot_range(int i, int nfv, int nfe, int64_t& base, int& cnt) {
@@ -124,6 +136,11 @@ void launch_accumulate(const PcgDev& s, double* xhi, double* xlo, hipStream_t st
 void launch_assemble_to_full(const PcgDev& s, const int32_t* free_to_full, double* yfull, int diag_mode,
                              hipStream_t st);
 // x (free) <-> u layout
+// QR-error indicator of every element of group g (see mto_qr.hip); x holds
+// the displacements in the free-DOF layout of the systems.
+void launch_qr(const QrGroupDev& g, const double* E, const double* x, const SysDesc* sys, const int32_t* inst_sys0,
+               const int32_t* inst_L, const int64_t* inst_eoff, const int32_t* inst_nel, double* eps,
+               hipStream_t st);
 void launch_gather_free(const PcgDev& s, const int32_t* free_to_full, const double* ufull, double* xfree,
                         hipStream_t st);
 void launch_scatter_full(const PcgDev& s, const int32_t* free_to_full, const double* xfree, double* ufull,

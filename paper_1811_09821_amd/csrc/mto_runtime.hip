@@ -73,6 +73,11 @@ struct GroupHost {
   // element-block Schwarz smoother: packed inverses [ne (ne+1)/2][npad], neighbours [8][npad]
   double* binv = nullptr;
   int32_t* nbr = nullptr;
+  // QR-error indicator (built at its first use): instance and element of every column,
+  // packed order-(p+1) cell tables
+  std::vector<int32_t> eid_h, einst_h;
+  int32_t *d_eid = nullptr, *d_einst = nullptr;
+  double* qtab = nullptr;
 };
 
 // Geometric hierarchy of the multigrid preconditioner (levels 1..L).
@@ -150,6 +155,10 @@ struct mto_plan {
   int32_t *d_el_group = nullptr, *d_el_col = nullptr;
   double* slots2 = nullptr;  // the Schwarz products, assembled like the slots
   double asm_omega = 0.0;
+  // QR-error indicator: per instance first system, load cases, output offset, elements
+  bool qr_ready = false;
+  int32_t *d_qr_sys0 = nullptr, *d_qr_L = nullptr, *d_qr_nel = nullptr;
+  int64_t* d_qr_eoff = nullptr;
 
   PcgDev pcg() const {
     PcgDev s{};
@@ -638,6 +647,12 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     }
     g.inst_begin[n] = (int32_t)elems.size();
     g.n_elems = (int)elems.size();
+    g.eid_h.resize(elems.size());
+    g.einst_h.resize(elems.size());
+    for (size_t k = 0; k < elems.size(); ++k) {
+      g.einst_h[k] = elems[k].first;
+      g.eid_h[k] = elems[k].second;
+    }
     g.npad = std::max(64, (g.n_elems + 63) / 64 * 64);
     std::vector<int32_t> gidx((size_t)g.nep * g.npad, -1), sidx((size_t)g.ne * g.npad, -1), cell(g.npad, 0);
     for (int k = 0; k < g.n_elems; ++k) {
@@ -1138,6 +1153,66 @@ int mto_sensitivity(mto_plan* P, const double* rho, const double* u, double* g, 
   launch_gather_free(s, P->f2f, u, P->q, st);
   for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->q, g, P->d_sys, st);
   return check_launch("sensitivity");
+}
+
+// Tables and index arrays of the QR-error indicator, once per plan.
+static int qr_setup(mto_plan* P) {
+  if (P->qr_ready) return MTO_OK;
+  int rc;
+  for (auto& g : P->groups) {
+    const int q = g.p + 1, nq = ne_of(q), nt = nq * (nq + 1) / 2;
+    const std::vector<double> ks = subcell_tables(q, g.d, P->prm.nu);
+    std::vector<double> packed((size_t)g.S * nt);
+    for (int s = 0; s < g.S; ++s)
+      for (int i = 0; i < nq; ++i)
+        for (int j = 0; j <= i; ++j) packed[(size_t)s * nt + i * (i + 1) / 2 + j] = ks[((size_t)s * nq + i) * nq + j];
+    if ((rc = dev_upload(P, &g.qtab, packed)) || (rc = dev_upload(P, &g.d_eid, g.eid_h)) ||
+        (rc = dev_upload(P, &g.d_einst, g.einst_h)))
+      return rc;
+  }
+  const int n = P->n_inst;
+  std::vector<int32_t> sys0(n), L(n), nel(n, 0);
+  std::vector<int64_t> eoff(n);
+  for (auto& g : P->groups)
+    for (int i = 0; i < n; ++i) nel[i] += g.inst_begin[i + 1] - g.inst_begin[i];
+  int64_t acc = 0;
+  for (int i = 0; i < n; ++i) {
+    sys0[i] = (int32_t)P->c_off[i];  // systems are numbered instance-major, like c
+    L[i] = P->L[i];
+    eoff[i] = acc;
+    acc += (int64_t)L[i] * nel[i];
+  }
+  if ((rc = dev_upload(P, &P->d_qr_sys0, sys0)) || (rc = dev_upload(P, &P->d_qr_L, L)) ||
+      (rc = dev_upload(P, &P->d_qr_nel, nel)) || (rc = dev_upload(P, &P->d_qr_eoff, eoff)))
+    return rc;
+  P->qr_ready = true;
+  return MTO_OK;
+}
+
+int mto_qr_error(mto_plan* P, const double* rho, const double* u, double* eps, void* stream) {
+  g_err.clear();
+  if (!P || !rho || !u || !eps) return fail(MTO_EINVAL, "NULL argument");
+  int rc = qr_setup(P);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const PcgDev s = P->pcg();
+  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  launch_gather_free(s, P->f2f, u, P->q, st);
+  for (auto& g : P->groups) {
+    QrGroupDev qd{};
+    qd.p = g.p;
+    qd.d = g.d;
+    qd.S = g.S;
+    qd.npad = g.npad;
+    qd.n_elems = g.n_elems;
+    qd.tab = g.qtab;
+    qd.gidx = g.gidx;
+    qd.cell = g.cell;
+    qd.eid = g.d_eid;
+    qd.einst = g.d_einst;
+    launch_qr(qd, P->E, P->q, P->d_sys, P->d_qr_sys0, P->d_qr_L, P->d_qr_eoff, P->d_qr_nel, eps, st);
+  }
+  return check_launch("qr_error");
 }
 
 int mto_jacobi_diagonal(mto_plan* P, const double* rho, double* diag, void* stream) {

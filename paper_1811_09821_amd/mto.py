@@ -93,6 +93,7 @@ def _load():
         "mto_set_tile": ([vp, i32, i32, i32, i32], i32),
         "mto_time_contraction": ([vp, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "mto_plan_destroy": ([vp], None),
+        "mto_qr_error": ([vp, vp, vp, vp, vp], i32),
         "mto_filter_create": ([ctypes.POINTER(_Problem), i32, ctypes.c_double, ctypes.POINTER(vp)], i32),
         "mto_filter_apply": ([vp, vp, vp, vp], i32),
         "mto_filter_grad": ([vp, vp, vp, vp], i32),
@@ -110,7 +111,7 @@ _lib = _load()
 EXPORTED = ("mto_last_error", "mto_version", "mto_plan_create", "mto_batch_plan_create", "mto_plan_info",
             "mto_instance_info", "mto_solve", "mto_batch_capture", "mto_batch_replay", "mto_apply_stiffness",
             "mto_sensitivity", "mto_jacobi_diagonal", "mto_weighted_sensitivity", "mto_autotune", "mto_set_tile",
-            "mto_time_contraction", "mto_plan_destroy", "mto_filter_create", "mto_filter_apply", "mto_filter_grad",
+            "mto_time_contraction", "mto_plan_destroy", "mto_qr_error", "mto_filter_create", "mto_filter_apply", "mto_filter_grad",
             "mto_filter_info", "mto_filter_destroy")
 
 
@@ -218,7 +219,13 @@ class Plan:
             keys = ("cell_off", "n_cells", "u_off", "n_dof", "g_off", "c_off", "n_free")
             rec = {k: x.value for k, x in zip(keys, v)}
             rec["n_load_cases"] = nl.value
+            rec["nel"] = int(problems[i].nelx) * int(problems[i].nely)
             self.instances.append(rec)
+        acc = 0
+        for rec in self.instances:  # QR-error indicator layout: instance-major, load case, element
+            rec["eps_off"] = acc
+            acc += rec["n_load_cases"] * rec["nel"]
+        self.n_eps = acc
         self.n_c = sum(r["n_load_cases"] for r in self.instances)
         self._bound = None
 
@@ -296,6 +303,20 @@ class Plan:
         g = self._empty(self.info["n_g"], rho)
         _check(_lib.mto_sensitivity(self.handle, _ptr(rho), _ptr(u), _ptr(g), _stream(stream)))
         return g
+
+    def qr_error(self, rho, u, stream=None):
+        """QR-error indicator (Sec. 3.2.3, Eq. (9)) of every element and load
+        case for displacements u (u layout) at densities rho; see mto.h."""
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        _f64_cuda(u, self.info["n_u"], "u")
+        eps = self._empty(self.n_eps, rho)
+        _check(_lib.mto_qr_error(self.handle, _ptr(rho), _ptr(u), _ptr(eps), _stream(stream)))
+        return eps
+
+    def split_eps(self, eps):
+        """Per instance [L, nel] views of the QR-error layout."""
+        return [eps[r["eps_off"]:r["eps_off"] + r["n_load_cases"] * r["nel"]].view(r["n_load_cases"], r["nel"])
+                for r in self.instances]
 
     def weighted_sensitivity(self, g, w, stream=None):
         """sum_l w_l dc_l/drho per instance (backward of rho -> c)."""
