@@ -176,12 +176,21 @@ __global__ __launch_bounds__(16 * dd_rows<P>()) void k_elem_dd(GroupDev g, const
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
-// XCD i mod 8), each with its own L2.  This bijection of [0, T) hands each
-// XCD a contiguous run of tiles, so neighbouring elements, which share vertex
-// and edge DOFs in their gathers, meet in the same L2.
-__device__ __forceinline__ int xcd_tile(int i, int T) {
-  const int q = T >> 3, r = T & 7, x = i & 7, k = i >> 3;
-  return x * q + min(x, r) + k;
+// XCD i mod 8), each with its own L2.  These bijections of [0, T) keep
+// neighbouring elements, which share vertex and edge DOFs in their gathers,
+// in one L2.  run <= 0: each XCD takes one contiguous eighth of the tiles
+// (best for a single system).  run > 0: each XCD takes runs of `run`
+// consecutive tiles dealt round-robin, so that when the tiles of stopped
+// systems return at once the remaining work is still spread over all XCDs
+// (batches whose systems converge at different iterations).
+__device__ __forceinline__ int xcd_tile(int i, int T, int run) {
+  const int x = i & 7, k = i >> 3;
+  if (run <= 0) {
+    const int q = T >> 3, r = T & 7;
+    return x * q + min(x, r) + k;
+  }
+  if (i >= T / (8 * run) * (8 * run)) return i;  // the tail, in order
+  return ((k / run) * 8 + x) * run + k % run;
 }
 
 // ---------------------------------------------------------------------------
@@ -202,7 +211,7 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
   double* red = lds + 2;             // reused after the gather: [KS-1][NACC][64]
   const int ks = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const Tile t = tiles[g.tile_begin + xcd_tile(blockIdx.x, g.n_tiles)];
+  const Tile t = tiles[g.tile_begin + xcd_tile(blockIdx.x, g.n_tiles, g.xcd_run)];
   if (mode == ELEM_APPLY_RUNNING && s.status[t.sys] != SYS_RUNNING) return;
   const bool pcg = mode == ELEM_PCG;
   const int n = lane & 15, kq = lane >> 4;

@@ -14,6 +14,7 @@ struct GroupDev {
   int32_t n_elems;
   int32_t tile_begin, n_tiles, ncol;  // tiles of this group in the tile array
   int32_t waves;           // waves per tile (density-cell split of the reduction)
+  int32_t xcd_run;         // tile order over the XCDs of the contraction (see xcd_tile)
   const double* kfrag;     // MFMA A fragments [S*NEP/4][MB][64]
   const double* ks;        // plain K_s [S][ne][ne]
   const double* kdiag;     // diag(K_s) [S][ne]

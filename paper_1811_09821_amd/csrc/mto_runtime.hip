@@ -197,6 +197,7 @@ struct mto_plan {
     o.n_tiles = g.n_tiles;
     o.ncol = g.ncol;
     o.waves = g.waves;
+    o.xcd_run = n_sys > 1 ? 8 : 0;  // several systems may stop at different iterations
     o.kfrag = g.kfrag;
     o.ks = g.ks;
     o.kdiag = g.kdiag;
