@@ -20,6 +20,9 @@ What it computes, in plain FP64 (longdouble for residual accumulation):
 * the QR-error indicator of Sec. 3.2.3 (Eq. (9)): the element-level
   order-(p+1) problem under the element's own load and the strain-energy
   ratio (``qr.py``);
+* the compliant-mechanism objective of Sec. 4.1 (force inverter, z = e_out)
+  with ground springs, its adjoint (a unit load at the output DOF) and the
+  bilinear sensitivity -E' lambda_e^T K_s u_e (``mechanism.py``);
 * compliance c = f^T u (Sec. 4.1, z = f) and the per-cell sensitivity
   dc/drho = -E'(rho) u_e^T K_s u_e (the paper names the sensitivity analysis
   in Sec. 1 and Sec. 2.1 but prints no formula; this is the adjoint result for
@@ -28,8 +31,9 @@ What it computes, in plain FP64 (longdouble for residual accumulation):
 Every function cites the passage it follows.  Readings of points the paper
 leaves open (basis, mixed-p compatibility, layouts) are listed in the design doc of
 the repository.  Parity status: every function is pinned by ``-m "not gpu"``
-tests in ``tests/test_oracle_pins.py``, ``tests/test_filter_pins.py`` and
-``tests/test_qr_pins.py``; none is "parity unpinned".
+tests in ``tests/test_oracle_pins.py``, ``tests/test_filter_pins.py``,
+``tests/test_qr_pins.py`` and ``tests/test_mechanism_pins.py``; none is
+"parity unpinned".
 """
 
 from .fem import (  # noqa: F401
@@ -43,3 +47,4 @@ from .space import DofSpace, build_space  # noqa: F401
 from .solve import oracle_solve, assemble, element_dofs_global  # noqa: F401
 from .filter import filter_apply, filter_grad, filter_matrix, filter_weights  # noqa: F401
 from .qr import element_qr_error, qr_error  # noqa: F401
+from .mechanism import bilinear_sensitivity, mechanism  # noqa: F401

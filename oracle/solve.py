@@ -120,12 +120,29 @@ def refined_solve(Kff, lu, b, max_rounds=8):
     return u
 
 
+def spring_matrix(space, springs):
+    """Ground springs (vx, vy, comp, k) as a diagonal matrix on the global
+    DOFs: the force inverter's input and output springs of Sec. 4.1 add
+    k u_i^2 / 2 to the strain energy, i.e. k to K_ii."""
+    diag = np.zeros(space.n_dof)
+    for vx, vy, comp, k in springs:
+        diag[2 * (vy * (space.nelx + 1) + vx) + comp] += k
+    return sp.diags(diag).tocsr()
+
+
 def oracle_solve(nelx, nely, p, d, rho, supports, loads, n_load_cases=1,
-                 E0=1.0, Emin=1e-9, nu=0.3, q=3.0, want_K=False):
+                 E0=1.0, Emin=1e-9, nu=0.3, q=3.0, want_K=False, springs=()):
     """Full reference step: returns dict with
     u [L, n_dof] (zero at supported DOFs), c [L], g [L, n_cells] (dc/drho),
-    w [L, n_cells] (u_e^T K_s u_e), plus bookkeeping."""
+    w [L, n_cells] (u_e^T K_s u_e), plus bookkeeping.  Ground springs
+    (vx, vy, comp, k) are added to K; they do not depend on rho, so g keeps
+    its form."""
     K, space, edofs, off, ks = assemble(nelx, nely, p, d, rho, E0, Emin, q, nu)
+    if len(springs):
+        S = spring_matrix(space, springs)
+        if np.any(S.diagonal()[~free_mask(space, supports)] != 0.0):
+            raise ValueError("a spring acts on a supported DOF")
+        K = (K + S).tocsr()
     free = free_mask(space, supports)
     f = load_vectors(space, loads, n_load_cases)
     if np.any(f[:, ~free] != 0.0):

@@ -58,6 +58,7 @@ class Problem:
     supports: List[Tuple[int, int, int, int]] = field(default_factory=list)  # (kind, a, b, mask)
     loads: List[Tuple[int, int, float, float, int]] = field(default_factory=list)  # (vx, vy, fx, fy, lc)
     n_load_cases: int = 1
+    springs: List[Tuple[int, int, int, float]] = field(default_factory=list)  # (vx, vy, comp, k) to ground
     E0: float = 1.0
     Emin: float = 1e-9
     nu: float = 0.3
@@ -79,7 +80,7 @@ class Problem:
         """Keyword arguments for the oracle's solve."""
         return dict(nelx=self.nelx, nely=self.nely, p=self.p, d=self.d, rho=self.rho,
                     supports=self.supports, loads=self.loads, n_load_cases=self.n_load_cases,
-                    E0=self.E0, Emin=self.Emin, nu=self.nu, q=self.q)
+                    E0=self.E0, Emin=self.Emin, nu=self.nu, q=self.q, springs=self.springs)
 
 
 class RandomField:
@@ -254,6 +255,32 @@ def mixed_cantilever(nelx=200, nely=100, volfrac=0.5, seed=3, load_vy=None, sigm
     rho = map_density(fld(x, y), w, volfrac, solid=load_paths(x, y, loads))
     return Problem(f"mixed{nelx}x{nely}", nelx, nely, p, d, rho, cantilever_supports(), loads,
                    len(load_vy))
+
+
+def force_inverter(nelx=40, nely=20, p=2, d=4, volfrac=0.45, seed=7, sigma=4.0):
+    """Force inverter of Sec. 4.1 as the half model symmetric about its bottom
+    edge (the paper's 40 x 20 initial mesh of Q2 elements with 4 x 4 design
+    points; E0 = 1, nu = 0.3, q = 3): u_y = 0 on the bottom edge, the top-left
+    vertex clamped (the support segment of 0.01 L is shorter than an element),
+    input force f_in = 1 in +x at the bottom-left vertex with a spring
+    k_in = 1, output at the bottom-right vertex with a spring k_out = 0.001,
+    both in x.  Load case 0 is f_in; load case 1 is the unit load at the
+    output DOF, the right-hand side z of the adjoint solve (K is symmetric).
+    The objective is z^T u = u_x at the output (Eq. (1)).  Density: the
+    random field at mean volfrac, solid along the load paths.
+    Returns the Problem; its attributes in_dof and out_dof are (vx, vy, comp)."""
+    pa = np.full(nelx * nely, p, np.int8)
+    da = np.full(nelx * nely, d, np.int8)
+    fld = RandomField(seed, sigma, nelx, nely)
+    x, y, w = cell_centres(nelx, nely, da)
+    loads = [(0, 0, 1.0, 0.0, 0), (nelx, 0, 1.0, 0.0, 1)]
+    rho = map_density(fld(x, y), w, volfrac, solid=load_paths(x, y, loads))
+    sup = [(SUP_EDGE_BOTTOM, 0, 0, 2), (SUP_VERTEX, 0, nely, 3)]
+    springs = [(0, 0, 0, 1.0), (nelx, 0, 0, 0.001)]
+    pr = Problem(f"inverter{nelx}x{nely}_p{p}d{d}", nelx, nely, pa, da, rho, sup, loads, 2, springs)
+    pr.in_dof = (0, 0, 0)
+    pr.out_dof = (nelx, 0, 0)
+    return pr
 
 
 def mixed_200x100(seed=3):
