@@ -128,6 +128,18 @@ typedef struct {
                                the nine-colouring of element blocks guarantees */
 } mto_params;
 
+/* A linear spring from one vertex DOF to ground, stiffness k > 0: adds k to
+ * that diagonal entry of K.  The force inverter of Sec. 4.1 has one at its
+ * input (k_in) and one at its output (k_out).  Springs enter the operator of
+ * the solve and its true residual, not the preconditioner (a rank-n_springs
+ * change costs PCG at most n_springs extra iterations).  A spring on a
+ * supported DOF is MTO_EINVAL. */
+typedef struct {
+  int32_t vx, vy; /* vertex */
+  int32_t comp;   /* 0: x, 1: y */
+  double k;
+} mto_spring;
+
 typedef struct {
   mto_mesh mesh;
   const mto_support* supports; /* host [n_supports] */
@@ -135,6 +147,8 @@ typedef struct {
   const mto_point_load* loads; /* host [n_loads] */
   int32_t n_loads;
   int32_t n_load_cases;        /* >= 1 */
+  const mto_spring* springs;   /* host [n_springs] or NULL */
+  int32_t n_springs;           /* >= 0 */
 } mto_problem;
 
 typedef struct {
@@ -218,6 +232,17 @@ int mto_apply_stiffness(mto_plan* plan, const double* rho, const double* x, doub
 
 /* g = -E'(rho) u_e^T K_s u_e for given displacements u (u layout). */
 int mto_sensitivity(mto_plan* plan, const double* rho, const double* u, double* g, void* stream);
+
+/* Adjoint sensitivity of a linear objective J = z^T u (Eq. (1)): for every
+ * system l, g_l[cell] = -E'(rho) lam_{l,e}^T K_s u_{l,e}, with u and lam
+ * device arrays in the u layout (lam_l the adjoint state of system l, i.e.
+ * the solution of K lam = z for J = z^T u_l) and g in the g layout.  With
+ * lam = u this is mto_sensitivity.  For the force inverter of Sec. 4.1,
+ * solve with load case 0 = f_in and load case 1 = the unit load at the
+ * output DOF and pass lam = u with the two cases swapped: g_0 = dJ/drho.
+ * Overwrites the plan's moduli and PCG work vectors. */
+int mto_adjoint_sensitivity(mto_plan* plan, const double* rho, const double* u, const double* lam, double* g,
+                            void* stream);
 
 /* Backward of the map densities -> compliances: out[cell] = sum over the
  * load cases l of the cell's instance of w[l] g_l[cell], with g as written by

@@ -39,6 +39,33 @@ def total_compliance(rho, plan):
     return MTOCompliance.apply(rho, plan).sum()
 
 
+class MTOMechanism(torch.autograd.Function):
+    """J = MTOMechanism.apply(rho, plan, out_index): the compliant-mechanism
+    objective of Sec. 4.1, J = z^T u = u[out_index] for a one-instance plan
+    whose load case 0 is the input force and load case 1 the unit load at the
+    output DOF (out_index is that DOF in the u layout).  Load case 1's
+    solution is the adjoint state (K lam = z, K symmetric), so backward is
+    dJ/drho = -E'(rho) lam_e^T K_s u_e, from one bilinear sensitivity call."""
+
+    @staticmethod
+    def forward(ctx, rho, plan, out_index):
+        rho = rho.detach().contiguous()
+        u, _, _, stats = plan.solve(rho, sensitivities=False)
+        n = plan.instances[0]["n_dof"]
+        ctx.plan, ctx.stats = plan, stats
+        ctx.save_for_backward(rho, u)
+        return u[out_index].clone()
+
+    @staticmethod
+    def backward(ctx, grad_J):
+        rho, u = ctx.saved_tensors
+        plan = ctx.plan
+        n = plan.instances[0]["n_dof"]
+        lam = torch.cat([u[n:2 * n], u[:n]])  # system 0 pairs with the adjoint state of case 1
+        g = plan.adjoint_sensitivity(rho, u, lam)
+        return grad_J * g[:plan.instances[0]["n_cells"]], None, None
+
+
 class DensityFilter(torch.autograd.Function):
     """rho~ = DensityFilter.apply(rho, filt): filtered densities; backward is
     the transposed filter (the chain rule through Eq. (4))."""

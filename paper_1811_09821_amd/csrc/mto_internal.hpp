@@ -44,6 +44,8 @@ struct InstanceHost {
   std::vector<int64_t> elem_dof_off; // [nel+1]
   // loads: rhs per load case in the free numbering, [L][n_free]
   std::vector<double> f;
+  // ground springs: (free DOF, stiffness)
+  std::vector<std::pair<int32_t, double>> springs;
 };
 
 // The thread-local message behind mto_last_error (set_error returns code).

@@ -400,13 +400,14 @@ __global__ __launch_bounds__(64) void k_elem_plain(GroupDev g, const Tile* __res
 }
 
 // ---------------------------------------------------------------------------
-// Sensitivity: w_{e,s} = u_e^T K_s u_e with K_s u_e on MFMA (same A fragments
+// Sensitivity: w_{e,s} = lam_e^T K_s u_e (lam = u for compliance) with K_s u_e on MFMA (same A fragments
 // as the matvec), then a segmented dot over the rows each lane holds and a
 // 4-lane butterfly; g = -E'(rho) w.
 template <int P, int NC>
 __global__ __launch_bounds__(BLOCK) void k_sens_mfma(GroupDev g, const Tile* __restrict__ tiles,
                                                     const double* __restrict__ dE, const double* __restrict__ x,
-                                                    double* __restrict__ gout, const SysDesc* __restrict__ sys) {
+                                                    const double* __restrict__ y, double* __restrict__ gout,
+                                                    const SysDesc* __restrict__ sys) {
   constexpr int NEP = nep_of(P), MB = mb_of(P), NJ = NEP / 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tix = blockIdx.x * WAVES + wave;
@@ -415,7 +416,8 @@ __global__ __launch_bounds__(BLOCK) void k_sens_mfma(GroupDev g, const Tile* __r
   const SysDesc& sd = sys[t.sys];
   const int n = lane & 15, kq = lane >> 4;
   const double* __restrict__ xs = x + t.dof_off;
-  double u[NC][NJ];
+  const double* __restrict__ ys = y + t.dof_off;
+  double u[NC][NJ], lm[NC][NJ];
   int cellb[NC];
   bool valid[NC];
 #pragma unroll
@@ -428,6 +430,7 @@ __global__ __launch_bounds__(BLOCK) void k_sens_mfma(GroupDev g, const Tile* __r
     for (int jj = 0; jj < NJ; ++jj) {
       const int gi = valid[c] ? g.gidx[(4 * jj + kq) * g.npad + el] : -1;
       u[c][jj] = gi >= 0 ? xs[gi] : 0.0;
+      lm[c][jj] = gi >= 0 ? ys[gi] : 0.0;
     }
   }
   const double* __restrict__ kf = g.kfrag + lane;
@@ -457,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_sens_mfma(GroupDev g, const Tile* __r
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int jr = 4 * b + r;  // row 16b + kq + 4r = 4 jr + kq, held in u[c][jr]
-          if (jr < NJ) w = fma(u[c][jr < NJ ? jr : 0], acc[b][c][r], w);
+          if (jr < NJ) w = fma(lm[c][jr < NJ ? jr : 0], acc[b][c][r], w);
         }
       w += __shfl_xor(w, 16);
       w += __shfl_xor(w, 32);
@@ -518,8 +521,10 @@ __global__ __launch_bounds__(VBLOCK) void k_dinv(PcgDev s, double* __restrict__ 
   const Chunk ch = s.chunks[blockIdx.x];
   if (ch.load != 0) return;
   const double* __restrict__ sl = s.slots + ch.slot_off;
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK)
-    dinv[ch.inst_free_off + i] = scale / slot_sum(sl, i, ch.nfv, ch.nfe);
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK) {
+    const double kd = s.kspr ? s.kspr[ch.inst_free_off + i] : 0.0;
+    dinv[ch.inst_free_off + i] = scale / (slot_sum(sl, i, ch.nfv, ch.nfe) + kd);
+  }
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_init(PcgDev s, int use_slots) {
@@ -574,11 +579,12 @@ __global__ __launch_bounds__(VBLOCK) void k_dof1(PcgDev s, int it_k) {
   const int i = ch.begin + threadIdx.x;
   const bool in = i < ch.end;
   const int64_t o = ch.dof_off;
-  double qi = 0.0, po = 0.0, zi = 0.0;
+  double qi = 0.0, po = 0.0, zi = 0.0, kd = 0.0;
   if (in) {
     qi = slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
     po = s.p[o + i];
     zi = s.z[o + i];
+    if (s.kspr) kd = s.kspr[ch.inst_free_off + i];  // ground springs: q += k p
   }
   const int it = *s.it_base + it_k;
   if (threadIdx.x < 64) {
@@ -600,6 +606,7 @@ __global__ __launch_bounds__(VBLOCK) void k_dof1(PcgDev s, int it_k) {
   double acc = 0.0;
   if (in) {
     const double pi = fma(sc.beta, po, zi);
+    qi = fma(kd, pi, qi);
     s.p[o + i] = pi;
     s.q[o + i] = qi;
     acc = pi * qi;
@@ -705,7 +712,8 @@ __global__ __launch_bounds__(VBLOCK) void k_accumulate(PcgDev s, double* __restr
 // r = f - K x from double-double slots, rounded once; also writes r into the
 // PCG residual (a restart continues from it) and the partial sums.
 __global__ __launch_bounds__(VBLOCK) void k_residual_dd(PcgDev s, const double* __restrict__ slots_lo,
-                                                        const double* __restrict__ xhi) {
+                                                        const double* __restrict__ xhi,
+                                                        const double* __restrict__ xlo) {
   __shared__ double lds[VWAVES + 4];
   const Chunk ch = s.chunks[blockIdx.x];
   const int64_t o = ch.dof_off;
@@ -718,6 +726,7 @@ __global__ __launch_bounds__(VBLOCK) void k_residual_dd(PcgDev s, const double* 
     slot_range(i, ch.nfv, ch.nfe, base, cnt);
     dd_t y{sh[base], sl[base]};
     for (int k = 1; k < cnt; ++k) y = dd_add(y, dd_t{sh[base + k], sl[base + k]});
+    if (s.kspr) y = dd_add(y, dd_scale(s.kspr[ch.inst_free_off + i], dd_t{xhi[o + i], xlo[o + i]}));
     const double fi = s.f[o + i];
     const dd_t r = dd_add(dd_t{fi, 0.0}, dd_t{-y.hi, -y.lo});
     s.r[o + i] = r.hi;
@@ -759,8 +768,14 @@ __global__ __launch_bounds__(VBLOCK) void k_assemble_full(PcgDev s, const int32_
   if (diag_mode && sd.load != 0) return;
   const int64_t yo = diag_mode ? sd.diag_off : sd.u_off;
   const double* __restrict__ sl = s.slots + sd.slot_off;
-  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK)
-    y[yo + f2f[sd.inst_free_off + i]] = slot_sum(sl, i, sd.nfv, sd.nfe);
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK) {
+    double v = slot_sum(sl, i, sd.nfv, sd.nfe);
+    if (s.kspr) {  // ground springs: the diagonal gets k, the product k x (x in q)
+      const double kd = s.kspr[sd.inst_free_off + i];
+      v = diag_mode ? v + kd : fma(kd, s.q[sd.dof_off + i], v);
+    }
+    y[yo + f2f[sd.inst_free_off + i]] = v;
+  }
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_gather_free(PcgDev s, const int32_t* __restrict__ f2f,
@@ -831,13 +846,13 @@ void launch_elem_p(const GroupDev& g, int path, int ncol, const Tile* tiles, con
 }
 
 template <int P>
-void launch_sens_p(const GroupDev& g, int ncol, const Tile* tiles, const double* dE, const double* x, double* gout,
-                   const SysDesc* sys, hipStream_t st) {
+void launch_sens_p(const GroupDev& g, int ncol, const Tile* tiles, const double* dE, const double* x,
+                   const double* y, double* gout, const SysDesc* sys, hipStream_t st) {
   const dim3 grid(nblocks(g.n_tiles, WAVES)), block(BLOCK);
   switch (ncol) {
-    case 1: hipLaunchKernelGGL((k_sens_mfma<P, 1>), grid, block, 0, st, g, tiles, dE, x, gout, sys); break;
-    case 2: hipLaunchKernelGGL((k_sens_mfma<P, 2>), grid, block, 0, st, g, tiles, dE, x, gout, sys); break;
-    default: hipLaunchKernelGGL((k_sens_mfma<P, 4>), grid, block, 0, st, g, tiles, dE, x, gout, sys); break;
+    case 1: hipLaunchKernelGGL((k_sens_mfma<P, 1>), grid, block, 0, st, g, tiles, dE, x, y, gout, sys); break;
+    case 2: hipLaunchKernelGGL((k_sens_mfma<P, 2>), grid, block, 0, st, g, tiles, dE, x, y, gout, sys); break;
+    default: hipLaunchKernelGGL((k_sens_mfma<P, 4>), grid, block, 0, st, g, tiles, dE, x, y, gout, sys); break;
   }
 }
 
@@ -854,14 +869,14 @@ void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E
   }
 }
 
-void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const double* x, double* gout,
-                 const SysDesc* sys, hipStream_t st) {
+void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const double* x, const double* y,
+                 double* gout, const SysDesc* sys, hipStream_t st) {
   if (g.n_tiles == 0) return;
   switch (g.p) {
-    case 1: launch_sens_p<1>(g, g.ncol, tiles, dE, x, gout, sys, st); break;
-    case 2: launch_sens_p<2>(g, g.ncol, tiles, dE, x, gout, sys, st); break;
-    case 3: launch_sens_p<3>(g, g.ncol, tiles, dE, x, gout, sys, st); break;
-    default: launch_sens_p<4>(g, g.ncol, tiles, dE, x, gout, sys, st); break;
+    case 1: launch_sens_p<1>(g, g.ncol, tiles, dE, x, y, gout, sys, st); break;
+    case 2: launch_sens_p<2>(g, g.ncol, tiles, dE, x, y, gout, sys, st); break;
+    case 3: launch_sens_p<3>(g, g.ncol, tiles, dE, x, y, gout, sys, st); break;
+    default: launch_sens_p<4>(g, g.ncol, tiles, dE, x, y, gout, sys, st); break;
   }
 }
 
@@ -942,7 +957,7 @@ void launch_residual_dd(const GroupDev* groups, int n_groups, const Tile* tiles,
         break;
     }
   }
-  hipLaunchKernelGGL(k_residual_dd, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, slots_lo, xhi);
+  hipLaunchKernelGGL(k_residual_dd, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, slots_lo, xhi, xlo);
   hipLaunchKernelGGL(k_residual_sums, dim3(1), dim3(BLOCK), 0, st, s);
 }
 

@@ -74,6 +74,7 @@ struct PcgDev {
   double* q;
   const double* f;
   const double* dinv;      // per instance free DOF
+  const double* kspr;      // per instance free DOF: ground-spring stiffness, or NULL (no springs)
   double* slots;
   double* part_pq;         // [n_chunks]
   double* part_rz;         // [2][n_chunks]
@@ -106,8 +107,10 @@ constexpr size_t ELEM_LDS_LIMIT = 64 * 1024;
 void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E, const double* xin,
                  const PcgDev& s, int mode, int it_k, hipStream_t st, hipEvent_t ev0 = nullptr,
                  hipEvent_t ev1 = nullptr);
-void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const double* x, double* gout,
-                 const SysDesc* sys, hipStream_t st);
+// g = -E' lam_e^T K_s u_e per system, u from x and lam from y (free-DOF
+// layout of the systems; y = x gives the compliance sensitivity)
+void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const double* x, const double* y,
+                 double* gout, const SysDesc* sys, hipStream_t st);
 // per element, sum_s E_s table[s][row] into the slots of load-0 systems
 // (table = diag(K_s) for Jacobi, row sums of |K_s| for the l1 smoother)
 void launch_diag_elem(const GroupDev& g, const Tile* tiles, const double* E, double* slots, const SysDesc* sys,

@@ -21,6 +21,7 @@
 // and the first slot of free DOF i follows from i and the two counts.
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <set>
 
@@ -50,7 +51,8 @@ int build_instance(const mto_problem& prob, InstanceHost& I, std::string& err) {
     return MTO_EINVAL;
   }
   if (prob.n_load_cases < 1 || prob.n_loads < 0 || (prob.n_loads > 0 && !prob.loads) ||
-      prob.n_supports < 0 || (prob.n_supports > 0 && !prob.supports)) {
+      prob.n_supports < 0 || (prob.n_supports > 0 && !prob.supports) || prob.n_springs < 0 ||
+      (prob.n_springs > 0 && !prob.springs)) {
     err = "bad load or support arrays";
     return MTO_EINVAL;
   }
@@ -242,6 +244,25 @@ int build_instance(const mto_problem& prob, InstanceHost& I, std::string& err) {
           }
         }
     }
+
+  // ground springs
+  I.springs.clear();
+  for (int k = 0; k < prob.n_springs; ++k) {
+    const mto_spring& Sp = prob.springs[k];
+    if (Sp.vx < 0 || Sp.vx > nelx || Sp.vy < 0 || Sp.vy > nely || Sp.comp < 0 || Sp.comp > 1 ||
+        !(Sp.k > 0.0) || !std::isfinite(Sp.k)) {
+      snprintf(buf, sizeof buf, "spring %d: vertex (%d,%d) comp %d k %g out of range", k, Sp.vx, Sp.vy, Sp.comp, Sp.k);
+      err = buf;
+      return MTO_EINVAL;
+    }
+    const int32_t f = I.full_to_free[2 * ((int64_t)Sp.vy * (nelx + 1) + Sp.vx) + Sp.comp];
+    if (f < 0) {
+      snprintf(buf, sizeof buf, "spring %d acts on a supported DOF", k);
+      err = buf;
+      return MTO_EINVAL;
+    }
+    I.springs.emplace_back(f, Sp.k);
+  }
 
   // loads
   I.f.assign((size_t)I.L * nf, 0.0);

@@ -135,6 +135,7 @@ struct mto_plan {
   int32_t *status = nullptr, *iters = nullptr, *it_base = nullptr, *n_active = nullptr;
   double *tol2 = nullptr, *sys_out = nullptr;
   int32_t* f2f = nullptr;
+  double* kspr = nullptr;  // ground springs per instance free DOF (NULL: none)
   int64_t *d_inst_cell_off = nullptr, *d_inst_g_off = nullptr;  // [n_inst + 1], [n_inst]
   int32_t *d_inst_c_off = nullptr, *d_inst_L = nullptr;
   // host pinned
@@ -173,6 +174,7 @@ struct mto_plan {
     s.q = q;
     s.f = f;
     s.dinv = dinv;
+    s.kspr = kspr;
     s.slots = slots;
     s.part_pq = part_pq;
     s.part_rz = part_rz;
@@ -723,6 +725,16 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_upload(P, &P->f2f, f2f)))
     return cleanup(rc);
   {
+    bool any = false;
+    for (int i = 0; i < n; ++i) any |= !I[i].springs.empty();
+    if (any) {
+      std::vector<double> ks(P->n_free_inst_tot, 0.0);
+      for (int i = 0; i < n; ++i)
+        for (auto& sp : I[i].springs) ks[P->free_off[i] + sp.first] += sp.second;
+      if ((rc = dev_upload(P, &P->kspr, ks))) return cleanup(rc);
+    }
+  }
+  {
     std::vector<int64_t> co(P->cell_off), go(P->g_off);
     co.push_back(P->n_cells_tot);
     std::vector<int32_t> cc(n), ll(P->L);
@@ -891,7 +903,7 @@ void enq_outputs(mto_plan* P, double* u, double* c, double* g, hipStream_t st) {
   launch_fill(u, 0.0, P->n_u, st);
   launch_scatter_full(s, P->f2f, P->xs_hi, u, st);
   if (g)
-    for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->xs_hi, g, P->d_sys, st);
+    for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->xs_hi, P->xs_hi, g, P->d_sys, st);
 }
 
 int capture(mto_plan* P, hipGraphExec_t* exec, const std::function<void(hipStream_t)>& body) {
@@ -1152,7 +1164,7 @@ int mto_sensitivity(mto_plan* P, const double* rho, const double* u, double* g, 
   const PcgDev s = P->pcg();
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
   launch_gather_free(s, P->f2f, u, P->q, st);
-  for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->q, g, P->d_sys, st);
+  for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->q, P->q, g, P->d_sys, st);
   return check_launch("sensitivity");
 }
 
@@ -1228,6 +1240,19 @@ int mto_jacobi_diagonal(mto_plan* P, const double* rho, double* diag, void* stre
   launch_fill(diag, 0.0, acc, st);
   launch_assemble_to_full(s, P->f2f, diag, 1, st);
   return check_launch("jacobi_diagonal");
+}
+
+int mto_adjoint_sensitivity(mto_plan* P, const double* rho, const double* u, const double* lam, double* g,
+                            void* stream) {
+  g_err.clear();
+  if (!P || !rho || !u || !lam || !g) return fail(MTO_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const PcgDev s = P->pcg();
+  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  launch_gather_free(s, P->f2f, u, P->q, st);
+  launch_gather_free(s, P->f2f, lam, P->z, st);
+  for (auto& gr : P->groups) launch_sens(P->gdev(gr), P->d_tiles, P->dE, P->q, P->z, g, P->d_sys, st);
+  return check_launch("adjoint_sensitivity");
 }
 
 int mto_weighted_sensitivity(mto_plan* P, const double* g, const double* w, double* out, void* stream) {

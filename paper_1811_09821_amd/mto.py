@@ -50,10 +50,15 @@ class _Params(ctypes.Structure):
                 ("mg_omega", ctypes.c_double)]
 
 
+class _Spring(ctypes.Structure):
+    _fields_ = [("vx", ctypes.c_int32), ("vy", ctypes.c_int32), ("comp", ctypes.c_int32), ("k", ctypes.c_double)]
+
+
 class _Problem(ctypes.Structure):
     _fields_ = [("mesh", _Mesh), ("supports", ctypes.POINTER(_Support)), ("n_supports", ctypes.c_int32),
                 ("loads", ctypes.POINTER(_Load)), ("n_loads", ctypes.c_int32),
-                ("n_load_cases", ctypes.c_int32)]
+                ("n_load_cases", ctypes.c_int32), ("springs", ctypes.POINTER(_Spring)),
+                ("n_springs", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -94,6 +99,7 @@ def _load():
         "mto_time_contraction": ([vp, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "mto_plan_destroy": ([vp], None),
         "mto_qr_error": ([vp, vp, vp, vp, vp], i32),
+        "mto_adjoint_sensitivity": ([vp, vp, vp, vp, vp, vp], i32),
         "mto_filter_create": ([ctypes.POINTER(_Problem), i32, ctypes.c_double, ctypes.POINTER(vp)], i32),
         "mto_filter_apply": ([vp, vp, vp, vp], i32),
         "mto_filter_grad": ([vp, vp, vp, vp], i32),
@@ -111,7 +117,7 @@ _lib = _load()
 EXPORTED = ("mto_last_error", "mto_version", "mto_plan_create", "mto_batch_plan_create", "mto_plan_info",
             "mto_instance_info", "mto_solve", "mto_batch_capture", "mto_batch_replay", "mto_apply_stiffness",
             "mto_sensitivity", "mto_jacobi_diagonal", "mto_weighted_sensitivity", "mto_autotune", "mto_set_tile",
-            "mto_time_contraction", "mto_plan_destroy", "mto_qr_error", "mto_filter_create", "mto_filter_apply", "mto_filter_grad",
+            "mto_time_contraction", "mto_plan_destroy", "mto_qr_error", "mto_adjoint_sensitivity", "mto_filter_create", "mto_filter_apply", "mto_filter_grad",
             "mto_filter_info", "mto_filter_destroy")
 
 
@@ -176,7 +182,9 @@ def _problem_array(problems):
         sup = (_Support * max(1, len(pr.supports)))(*[_Support(*map(int, s)) for s in pr.supports])
         lds = (_Load * max(1, len(pr.loads)))(
             *[_Load(int(l[0]), int(l[1]), float(l[2]), float(l[3]), int(l[4])) for l in pr.loads])
-        keep += [p, d, sup, lds]
+        sprs = list(getattr(pr, "springs", ()) or ())
+        spr = (_Spring * max(1, len(sprs)))(*[_Spring(int(a), int(b), int(c), float(k)) for a, b, c, k in sprs])
+        keep += [p, d, sup, lds, spr]
         arr[k].mesh = _Mesh(int(pr.nelx), int(pr.nely), p.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                             d.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
         arr[k].supports = ctypes.cast(sup, ctypes.POINTER(_Support))
@@ -184,6 +192,8 @@ def _problem_array(problems):
         arr[k].loads = ctypes.cast(lds, ctypes.POINTER(_Load))
         arr[k].n_loads = len(pr.loads)
         arr[k].n_load_cases = int(pr.n_load_cases)
+        arr[k].springs = ctypes.cast(spr, ctypes.POINTER(_Spring))
+        arr[k].n_springs = len(sprs)
     return arr, keep
 
 
@@ -302,6 +312,16 @@ class Plan:
         _f64_cuda(u, self.info["n_u"], "u")
         g = self._empty(self.info["n_g"], rho)
         _check(_lib.mto_sensitivity(self.handle, _ptr(rho), _ptr(u), _ptr(g), _stream(stream)))
+        return g
+
+    def adjoint_sensitivity(self, rho, u, lam, stream=None):
+        """-E'(rho) lam_e^T K_s u_e per system (u, lam in the u layout, g
+        layout out); see mto.h."""
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        _f64_cuda(u, self.info["n_u"], "u")
+        _f64_cuda(lam, self.info["n_u"], "lam")
+        g = self._empty(self.info["n_g"], rho)
+        _check(_lib.mto_adjoint_sensitivity(self.handle, _ptr(rho), _ptr(u), _ptr(lam), _ptr(g), _stream(stream)))
         return g
 
     def qr_error(self, rho, u, stream=None):

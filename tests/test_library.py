@@ -131,3 +131,13 @@ def test_filter_rejects_bad_radius_and_mesh():
     with pytest.raises(mto.MtoError) as ei:
         mto.Filter(bad, 0.5)
     assert ei.value.code == mto.MTO_EINVAL
+
+
+@pytest.mark.parametrize("spr", [[(3, 0, 0, 1.0), (0, 2, 0, 1.0)],  # second one on the clamped vertex
+                                 [(3, 0, 2, 1.0)], [(3, 0, 0, 0.0)], [(9, 0, 0, 1.0)]])
+def test_rejects_bad_springs(spr):
+    """Ground springs are checked on the host: vertex, component, k > 0, and
+    not on a supported DOF."""
+    pr = P.force_inverter(3, 2, p=1, d=1)
+    pr.springs = spr
+    assert _err(pr) == mto.MTO_EINVAL
