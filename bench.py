@@ -14,9 +14,10 @@ fraction 0.4, unit load at the mid-right vertex.
 
 Prints one JSON line (metric, value in seconds per design, roofline of the
 element-contraction kernel, CPU-oracle baseline, and the launch time of the
-density filter of Sec. 2.2 and its chain rule on the same cells and of the
-QR-error indicator of Sec. 3.2.3 on the solved designs, both outside the
-timed step).
+density filter of Sec. 2.2 and its chain rule on the same cells, of the
+QR-error indicator of Sec. 3.2.3 on the solved designs, and of the force
+inverter of Sec. 4.1 (input and adjoint solves with ground springs, adjoint
+sensitivity) on a 160 x 80 p = 3, d = 4 mesh, all outside the timed step).
 """
 
 import argparse
@@ -104,6 +105,36 @@ def time_filter(mto, prs, rho, R, reps=200):
     return res
 
 
+def time_mechanism(mto, args, steps=3):
+    """Force inverter of Sec. 4.1 (half model, ground springs k_in = 1 and
+    k_out = 0.001) on a 160 x 80 mesh of p = 3, d = 4 elements: one design =
+    the solve of the input and the adjoint load case (graph replay), J = u_out
+    and dJ/drho from the bilinear sensitivity kernel."""
+    import torch
+
+    from paper_1811_09821_amd import problems as P
+
+    pr = P.force_inverter(160, 80, p=3, d=4, volfrac=0.45, seed=8, sigma=8.0)
+    plan = mto.Plan(pr)
+    rho = torch.tensor(pr.rho, device="cuda:0")
+    u, c, _ = plan.capture(rho)
+    n = plan.instances[0]["n_dof"]
+    out = 2 * (pr.out_dof[1] * (pr.nelx + 1) + pr.out_dof[0]) + pr.out_dof[2]
+    stats = plan.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats = plan.replay()
+        lam = torch.cat([u[n:2 * n], u[:n]])
+        g = plan.adjoint_sensitivity(rho, u, lam)
+        J = u[out]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"workload": "force inverter 160x80 (half model), p=3 d=4, springs k_in=1 k_out=0.001, FP64",
+            "s_per_design": round(dt, 6), "pcg_iterations": stats["iterations"], "J": float(J),
+            "n_free_dofs_per_case": plan.info["n_free_total"] // 2, "grad_norm": float(g[:pr.n_cells].norm())}
+
+
 def time_qr(plan, rho, u, reps=5):
     """QR-error indicator (Sec. 3.2.3, Eq. (9)) for every element and load
     case of the solved designs: mean time per call over `reps` calls after
@@ -139,6 +170,8 @@ def main():
     ap.add_argument("--filter-radius", type=float, default=0.3,
                     help="density-filter radius in element edge lengths for the filter timing (0 skips it)")
     ap.add_argument("--no-qr", action="store_true", help="skip the QR-error indicator timing")
+    ap.add_argument("--no-mechanism", action="store_true",
+                    help="skip the force inverter (compliant mechanism) timing on a 160x80 p=3 d=4 mesh")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -244,6 +277,8 @@ def main():
         out["density_filter"] = time_filter(mto, prs, rho, args.filter_radius)
     if not args.no_qr:
         out["qr_error"] = time_qr(plan, rho, u)
+    if not args.no_mechanism:
+        out["mechanism"] = time_mechanism(mto, args)
 
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 8
