@@ -23,6 +23,9 @@ What it computes, in plain FP64 (longdouble for residual accumulation):
 * the compliant-mechanism objective of Sec. 4.1 (force inverter, z = e_out)
   with ground springs, its adjoint (a unit load at the output DOF) and the
   bilinear sensitivity -E' lambda_e^T K_s u_e (``mechanism.py``);
+* the refinement indicators and the dp update of Sec. 3.2-3.3: the Kelly
+  gradient-jump estimator, the density-based indicator, the ranking and
+  flagging steps and the order smoothing (``adapt.py``);
 * compliance c = f^T u (Sec. 4.1, z = f) and the per-cell sensitivity
   dc/drho = -E'(rho) u_e^T K_s u_e (the paper names the sensitivity analysis
   in Sec. 1 and Sec. 2.1 but prints no formula; this is the adjoint result for
@@ -32,8 +35,8 @@ Every function cites the passage it follows.  Readings of points the paper
 leaves open (basis, mixed-p compatibility, layouts) are listed in the design doc of
 the repository.  Parity status: every function is pinned by ``-m "not gpu"``
 tests in ``tests/test_oracle_pins.py``, ``tests/test_filter_pins.py``,
-``tests/test_qr_pins.py`` and ``tests/test_mechanism_pins.py``; none is
-"parity unpinned".
+``tests/test_qr_pins.py``, ``tests/test_mechanism_pins.py`` and
+``tests/test_adapt_pins.py``; none is "parity unpinned".
 """
 
 from .fem import (  # noqa: F401
@@ -48,3 +51,4 @@ from .solve import oracle_solve, assemble, element_dofs_global  # noqa: F401
 from .filter import filter_apply, filter_grad, filter_matrix, filter_weights  # noqa: F401
 from .qr import element_qr_error, qr_error  # noqa: F401
 from .mechanism import bilinear_sensitivity, mechanism  # noqa: F401
+from .adapt import density_indicator, dp_update, kelly_indicator, qr_update  # noqa: F401
