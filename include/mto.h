@@ -304,6 +304,65 @@ void mto_plan_destroy(mto_plan* plan);
  * make the first call inside stream capture.  MTO_EINVAL, MTO_ENOMEM. */
 int mto_qr_error(mto_plan* plan, const double* rho, const double* u, double* eps, void* stream);
 
+/* ---- refinement indicators and the dp update (Sec. 3.2-3.3) -------------- */
+
+/* Analysis indicator of Sec. 3.2.1 (Kelly): Gamma^a of an element = sum over
+ * its interior edges F of c_F * integral_F |[du/dn]|^2 ds, [.] the jump of
+ * the normal derivative of both displacement components across F, c_F =
+ * h_F / (2 p_F), h_F = sqrt(2) (the element diagonal in element edge
+ * lengths), p_F the larger order of the two elements.  Boundary edges carry
+ * no jump.  u: device, u layout; gamma: device, the QR-error layout
+ * (instance-major, then load case, then element).  Overwrites the plan's
+ * PCG work vectors; the first call allocates lookup tables. */
+int mto_kelly_indicator(mto_plan* plan, const double* u, double* gamma, void* stream);
+
+/* Density indicator of Sec. 3.2.2 for adaptive cycle `cycle` (>= 1): per
+ * element, over its cells rho, the refinement contributions (rho - r_l)/n
+ * for r_l <= rho <= rho_avg and (r_u - rho)/n for rho_avg < rho <= r_u and
+ * the coarsening contributions -(c_l - rho)/n for rho <= c_l and
+ * -(rho - c_u)/n for rho >= c_u, with rho_avg = (rho_min + rho_max)/2,
+ * s = rho_avg exp(-beta (cycle - 1)), r_l = rho_min + (1 - alpha) s,
+ * r_u = rho_max - (1 - alpha) s, c_l = rho_min + alpha s, c_u = rho_max - alpha s
+ * (the paper's alpha = 0.2, beta = 0.8; rho_min = 0, rho_max = 1).  rho: device,
+ * rho layout; gamma: device, one value per element, instances concatenated. */
+int mto_density_indicator(mto_plan* plan, const double* rho, int32_t cycle, double alpha, double beta,
+                          double rho_min, double rho_max, double* gamma, void* stream);
+
+/* Parameters of the dp update (Sec. 3.3): the analysis indicator refines
+ * the top frac_a_refine and coarsens the bottom frac_a_coarsen of the
+ * elements (the paper: 0.10, 0.05); the density indicator refines
+ * frac_d_refine of the elements with Gamma^d > 0 and coarsens frac_d_coarsen of
+ * those with Gamma^d < 0 (the paper: 1.0, 1.0); orders stay in [1, p_max];
+ * an element's design points are capped at d_max (the paper: 64). */
+typedef struct {
+  double frac_a_refine, frac_a_coarsen, frac_d_refine, frac_d_coarsen;
+  int32_t p_max, d_max;
+} mto_dp_params;
+
+/* Steps 2 and 3 of the dp update (Sec. 3.3) on one nelx x nely mesh, all
+ * arrays on the host, one entry per element (e = ey*nelx + ex):
+ *   ranking by ascending Gamma (ties by element index); step 2 sets the
+ *   flag theta = -1 / +1 on the bottom / top fractions of Gamma^a and moves p
+ *   by theta; step 3 lowers p of the density-coarsened elements whose theta
+ *   is 0 (theta = -2 where p is already 1) and raises p of the
+ *   density-refined elements whose theta is 0 or -1; then neighbouring orders
+ *   are brought within 2 of each other by (p_max - p_min - 2) passes over the
+ *   rows from the bottom, each element against its right and upper
+ *   neighbour, raising the lower; design points = 1 where theta = -2, else
+ *   min(2 (p+1)^2 - 3, d_max) (element DOFs minus the 3 rigid modes); the
+ *   background grid gets the smallest perfect square of cells per element
+ *   not below the largest number of design points.
+ * Outputs: p_out, theta_out, design_points [nel], cells_per_element [1].
+ * MTO_EINVAL on bad arguments. */
+int mto_dp_update(int32_t nelx, int32_t nely, const int8_t* p, const double* gamma_a, const double* gamma_d,
+                  const mto_dp_params* params, int8_t* p_out, int8_t* theta_out, int32_t* design_points,
+                  int32_t* cells_per_element);
+
+/* Step 4 of the dp update (Sec. 3.3): p_out = min(p + 1, p_max) where the
+ * QR error (mto_qr_error, computed on the mesh after steps 2-3) exceeds
+ * alpha_qr (the paper: 0.9), else p.  Host arrays [nel]. */
+int mto_qr_update(int32_t nel, const int8_t* p, const double* eps, double alpha_qr, int32_t p_max, int8_t* p_out);
+
 /* ---- density filter (Sec. 2.2, Eqs. (4)-(5)) ------------------------------
  * The step that precedes the analysis: filtered densities
  *   rho~_i = sum_j H_ij rho_j / sum_j H_ij,   H_ij = R - |c_i - c_j|  (> 0),

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmto.so")
-SOURCES = ["mto_tables.cpp", "mto_plan.cpp", "mto_kernels.hip", "mto_mg.hip", "mto_runtime.hip", "mto_filter.hip", "mto_qr.hip"]
+SOURCES = ["mto_tables.cpp", "mto_plan.cpp", "mto_kernels.hip", "mto_mg.hip", "mto_runtime.hip", "mto_filter.hip", "mto_qr.hip", "mto_adapt.hip"]
 
 # Packed FP32 instructions are disabled for all device code; the host pass of
 # hipcc warns that it does not know the feature, which is harmless.

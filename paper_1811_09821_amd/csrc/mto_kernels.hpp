@@ -36,6 +36,23 @@ struct QrGroupDev {
   const int32_t* einst;   // [n_elems] instance
 };
 
+// Element lookup for the refinement indicators: element e of instance i is
+// column el_col[el_base[i] + e] of group el_group[el_base[i] + e].
+struct AdaptDev {
+  const GroupDev* groups;
+  const int32_t* el_group;
+  const int32_t* el_col;
+  const int32_t* nelx;       // per instance
+  const int32_t* nely;
+  const int64_t* el_base;    // per instance
+  const int64_t* inst_eoff;  // per instance: offset of its [load case][element] block
+};
+
+// Bounds of the density indicator (Sec. 3.2.2) for one adaptive cycle.
+struct DensityBounds {
+  double rl, ru, cl, cu, avg;
+};
+
 // Slots of free DOF i of a system: 4 per vertex DOF, 2 per edge DOF, 1 per
 // interior DOF, in that order.
 __device__ __forceinline__ void slot_range(int i, int nfv, int nfe, int64_t& base, int& cnt) {
@@ -145,6 +162,12 @@ void launch_assemble_to_full(const PcgDev& s, const int32_t* free_to_full, doubl
 void launch_qr(const QrGroupDev& g, const double* E, const double* x, const SysDesc* sys, const int32_t* inst_sys0,
                const int32_t* inst_L, const int64_t* inst_eoff, const int32_t* inst_nel, double* eps,
                hipStream_t st);
+// Refinement indicators (see mto_adapt.hip): Gamma^a per (system, element)
+// from displacements x in the free-DOF layout; Gamma^d per element.
+void launch_kelly(const AdaptDev& a, const SysDesc* sys, int n_sys, int nel_max, const double* x, double* gamma,
+                  hipStream_t st);
+void launch_density_indicator(const AdaptDev& a, const double* rho, const DensityBounds& b, double* gamma,
+                              int64_t n_el, hipStream_t st);
 void launch_gather_free(const PcgDev& s, const int32_t* free_to_full, const double* ufull, double* xfree,
                         hipStream_t st);
 void launch_scatter_full(const PcgDev& s, const int32_t* free_to_full, const double* xfree, double* ufull,

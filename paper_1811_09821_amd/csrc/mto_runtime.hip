@@ -157,7 +157,11 @@ struct mto_plan {
   double* slots2 = nullptr;  // the Schwarz products, assembled like the slots
   double asm_omega = 0.0;
   // QR-error indicator: per instance first system, load cases, output offset, elements
-  bool qr_ready = false;
+  bool qr_ready = false, ad_ready = false;
+  std::vector<int32_t> inst_nelx, inst_nely;
+  GroupDev* d_ad_groups = nullptr;
+  int32_t *d_ad_elgroup = nullptr, *d_ad_elcol = nullptr, *d_ad_nelx = nullptr, *d_ad_nely = nullptr;
+  int64_t* d_ad_base = nullptr;
   int32_t *d_qr_sys0 = nullptr, *d_qr_L = nullptr, *d_qr_nel = nullptr;
   int64_t* d_qr_eoff = nullptr;
 
@@ -565,6 +569,8 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     P->n_free[i] = I[i].n_free;
     P->free_off[i] = P->n_free_inst_tot;
     P->L[i] = I[i].L;
+    P->inst_nelx.push_back(I[i].nelx);
+    P->inst_nely.push_back(I[i].nely);
     P->n_cells_tot += I[i].n_cells;
     P->n_u += (int64_t)I[i].L * I[i].n_dof;
     P->n_g += (int64_t)I[i].L * I[i].n_cells;
@@ -1200,6 +1206,77 @@ static int qr_setup(mto_plan* P) {
     return rc;
   P->qr_ready = true;
   return MTO_OK;
+}
+
+// Per-instance output offsets (as for the QR indicator) and the element
+// lookup of the refinement indicators, once per plan.
+static int adapt_setup(mto_plan* P) {
+  if (P->ad_ready) return MTO_OK;
+  const int n = P->n_inst;
+  std::vector<int64_t> base(n + 1, 0);
+  for (int i = 0; i < n; ++i) base[i + 1] = base[i] + (int64_t)P->inst_nelx[i] * P->inst_nely[i];
+  std::vector<int32_t> elg(base[n], -1), elc(base[n], -1);
+  std::vector<GroupDev> gd;
+  for (size_t g = 0; g < P->groups.size(); ++g) {
+    const GroupHost& G = P->groups[g];
+    for (size_t k = 0; k < G.eid_h.size(); ++k) {
+      elg[base[G.einst_h[k]] + G.eid_h[k]] = (int32_t)g;
+      elc[base[G.einst_h[k]] + G.eid_h[k]] = (int32_t)k;
+    }
+    gd.push_back(P->gdev(G));
+  }
+  base.pop_back();
+  int rc;
+  if ((rc = dev_upload(P, &P->d_ad_groups, gd)) || (rc = dev_upload(P, &P->d_ad_elgroup, elg)) ||
+      (rc = dev_upload(P, &P->d_ad_elcol, elc)) || (rc = dev_upload(P, &P->d_ad_nelx, P->inst_nelx)) ||
+      (rc = dev_upload(P, &P->d_ad_nely, P->inst_nely)) || (rc = dev_upload(P, &P->d_ad_base, base)))
+    return rc;
+  P->ad_ready = true;
+  return MTO_OK;
+}
+
+static AdaptDev adapt_dev(const mto_plan* P) {
+  AdaptDev a{};
+  a.groups = P->d_ad_groups;
+  a.el_group = P->d_ad_elgroup;
+  a.el_col = P->d_ad_elcol;
+  a.nelx = P->d_ad_nelx;
+  a.nely = P->d_ad_nely;
+  a.el_base = P->d_ad_base;
+  a.inst_eoff = P->d_qr_eoff;
+  return a;
+}
+
+int mto_kelly_indicator(mto_plan* P, const double* u, double* gamma, void* stream) {
+  g_err.clear();
+  if (!P || !u || !gamma) return fail(MTO_EINVAL, "NULL argument");
+  int rc;
+  if ((rc = qr_setup(P)) || (rc = adapt_setup(P))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  launch_gather_free(P->pcg(), P->f2f, u, P->q, st);
+  int nel_max = 0;
+  for (int i = 0; i < P->n_inst; ++i) nel_max = std::max(nel_max, P->inst_nelx[i] * P->inst_nely[i]);
+  launch_kelly(adapt_dev(P), P->d_sys, P->n_sys, nel_max, P->q, gamma, st);
+  return check_launch("kelly_indicator");
+}
+
+int mto_density_indicator(mto_plan* P, const double* rho, int32_t cycle, double alpha, double beta, double rho_min,
+                          double rho_max, double* gamma, void* stream) {
+  g_err.clear();
+  if (!P || !rho || !gamma) return fail(MTO_EINVAL, "NULL argument");
+  if (cycle < 1 || !(rho_max > rho_min) || !std::isfinite(alpha) || !std::isfinite(beta))
+    return fail(MTO_EINVAL, "density indicator: cycle >= 1 and rho_max > rho_min required");
+  int rc;
+  if ((rc = qr_setup(P)) || (rc = adapt_setup(P))) return rc;
+  DensityBounds b{};
+  b.avg = 0.5 * (rho_max + rho_min);
+  const double s = b.avg * std::exp(-beta * (cycle - 1));
+  b.rl = rho_min + (1.0 - alpha) * s;
+  b.ru = rho_max - (1.0 - alpha) * s;
+  b.cl = rho_min + alpha * s;
+  b.cu = rho_max - alpha * s;
+  launch_density_indicator(adapt_dev(P), rho, b, gamma, P->n_elements, (hipStream_t)stream);
+  return check_launch("density_indicator");
 }
 
 int mto_qr_error(mto_plan* P, const double* rho, const double* u, double* eps, void* stream) {

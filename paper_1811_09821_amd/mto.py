@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmto.so")
 
 MTO_OK, MTO_EINVAL, MTO_ESINGULAR, MTO_ENOCONV, MTO_EBREAKDOWN, MTO_EHIP, MTO_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+MTO_MAX_P, MTO_MAX_D = 4, 8  # as in mto.h
 PATH_MFMA, PATH_PLAIN = 0, 1
 PRECOND_JACOBI, PRECOND_MG, PRECOND_MG_ASM = 0, 1, 2
 ERROR_NAMES = {MTO_EINVAL: "MTO_EINVAL", MTO_ESINGULAR: "MTO_ESINGULAR", MTO_ENOCONV: "MTO_ENOCONV",
@@ -52,6 +53,12 @@ class _Params(ctypes.Structure):
 
 class _Spring(ctypes.Structure):
     _fields_ = [("vx", ctypes.c_int32), ("vy", ctypes.c_int32), ("comp", ctypes.c_int32), ("k", ctypes.c_double)]
+
+
+class _DpParams(ctypes.Structure):
+    _fields_ = [("frac_a_refine", ctypes.c_double), ("frac_a_coarsen", ctypes.c_double),
+                ("frac_d_refine", ctypes.c_double), ("frac_d_coarsen", ctypes.c_double),
+                ("p_max", ctypes.c_int32), ("d_max", ctypes.c_int32)]
 
 
 class _Problem(ctypes.Structure):
@@ -100,6 +107,11 @@ def _load():
         "mto_plan_destroy": ([vp], None),
         "mto_qr_error": ([vp, vp, vp, vp, vp], i32),
         "mto_adjoint_sensitivity": ([vp, vp, vp, vp, vp, vp], i32),
+        "mto_kelly_indicator": ([vp, vp, vp, vp], i32),
+        "mto_density_indicator": ([vp, vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, vp, vp], i32),
+        "mto_dp_update": ([i32, i32, vp, vp, vp, ctypes.POINTER(_DpParams), vp, vp, vp, vp], i32),
+        "mto_qr_update": ([i32, vp, vp, ctypes.c_double, i32, vp], i32),
         "mto_filter_create": ([ctypes.POINTER(_Problem), i32, ctypes.c_double, ctypes.POINTER(vp)], i32),
         "mto_filter_apply": ([vp, vp, vp, vp], i32),
         "mto_filter_grad": ([vp, vp, vp, vp], i32),
@@ -117,7 +129,8 @@ _lib = _load()
 EXPORTED = ("mto_last_error", "mto_version", "mto_plan_create", "mto_batch_plan_create", "mto_plan_info",
             "mto_instance_info", "mto_solve", "mto_batch_capture", "mto_batch_replay", "mto_apply_stiffness",
             "mto_sensitivity", "mto_jacobi_diagonal", "mto_weighted_sensitivity", "mto_autotune", "mto_set_tile",
-            "mto_time_contraction", "mto_plan_destroy", "mto_qr_error", "mto_adjoint_sensitivity", "mto_filter_create", "mto_filter_apply", "mto_filter_grad",
+            "mto_time_contraction", "mto_plan_destroy", "mto_qr_error", "mto_adjoint_sensitivity", "mto_kelly_indicator",
+            "mto_density_indicator", "mto_dp_update", "mto_qr_update", "mto_filter_create", "mto_filter_apply", "mto_filter_grad",
             "mto_filter_info", "mto_filter_destroy")
 
 
@@ -333,6 +346,23 @@ class Plan:
         _check(_lib.mto_qr_error(self.handle, _ptr(rho), _ptr(u), _ptr(eps), _stream(stream)))
         return eps
 
+    def kelly_indicator(self, u, stream=None):
+        """Analysis indicator of Sec. 3.2.1 per (instance, load case, element)
+        for displacements u (u layout); see mto.h."""
+        _f64_cuda(u, self.info["n_u"], "u")
+        gam = self._empty(self.n_eps, u)
+        _check(_lib.mto_kelly_indicator(self.handle, _ptr(u), _ptr(gam), _stream(stream)))
+        return gam
+
+    def density_indicator(self, rho, cycle, alpha=0.2, beta=0.8, rho_min=0.0, rho_max=1.0, stream=None):
+        """Density indicator of Sec. 3.2.2 per element (instances
+        concatenated); see mto.h."""
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        gam = self._empty(self.info["n_elements"], rho)
+        _check(_lib.mto_density_indicator(self.handle, _ptr(rho), int(cycle), float(alpha), float(beta),
+                                          float(rho_min), float(rho_max), _ptr(gam), _stream(stream)))
+        return gam
+
     def split_eps(self, eps):
         """Per instance [L, nel] views of the QR-error layout."""
         return [eps[r["eps_off"]:r["eps_off"] + r["n_load_cases"] * r["nel"]].view(r["n_load_cases"], r["nel"])
@@ -427,3 +457,36 @@ class Filter:
         out = torch.empty_like(g_tilde)
         _check(_lib.mto_filter_grad(self.handle, _ptr(g_tilde), _ptr(out), _stream(stream)))
         return out
+
+
+def dp_update(nelx, nely, p, gamma_a, gamma_d, frac_a_refine=0.10, frac_a_coarsen=0.05, frac_d_refine=1.0,
+              frac_d_coarsen=1.0, p_max=MTO_MAX_P, d_max=64):
+    """Steps 2-3 of the dp update of Sec. 3.3 (host arrays in, numpy out):
+    returns (p_new, theta, design_points, cells_per_element); see mto.h."""
+    nel = int(nelx) * int(nely)
+    p = np.ascontiguousarray(p, dtype=np.int8)
+    ga = np.ascontiguousarray(gamma_a, dtype=np.float64)
+    gd = np.ascontiguousarray(gamma_d, dtype=np.float64)
+    if p.size != nel or ga.size != nel or gd.size != nel:
+        raise ValueError("p, gamma_a and gamma_d need one entry per element")
+    prm = _DpParams(frac_a_refine, frac_a_coarsen, frac_d_refine, frac_d_coarsen, int(p_max), int(d_max))
+    p_out = np.empty(nel, np.int8)
+    th = np.empty(nel, np.int8)
+    dp = np.empty(nel, np.int32)
+    cells = ctypes.c_int32()
+    _check(_lib.mto_dp_update(int(nelx), int(nely), p.ctypes.data, ga.ctypes.data, gd.ctypes.data,
+                              ctypes.byref(prm), p_out.ctypes.data, th.ctypes.data, dp.ctypes.data,
+                              ctypes.byref(cells)))
+    return p_out, th, dp, cells.value
+
+
+def qr_update(p, eps, alpha_qr=0.9, p_max=MTO_MAX_P):
+    """Step 4 of the dp update of Sec. 3.3: p + 1 where eps > alpha_qr."""
+    p = np.ascontiguousarray(p, dtype=np.int8)
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    if e.size != p.size:
+        raise ValueError("one QR error per element")
+    out = np.empty(p.size, np.int8)
+    _check(_lib.mto_qr_update(int(p.size), p.ctypes.data, e.ctypes.data, float(alpha_qr), int(p_max),
+                              out.ctypes.data))
+    return out
