@@ -15,7 +15,8 @@ fraction 0.4, unit load at the mid-right vertex.
 Prints one JSON line (metric, value in seconds per design, roofline of the
 element-contraction kernel, CPU-oracle baseline, and the launch time of the
 density filter of Sec. 2.2 and its chain rule on the same cells, of the
-QR-error indicator of Sec. 3.2.3 on the solved designs, and of the force
+QR-error indicator of Sec. 3.2.3 and the other refinement indicators and
+the dp update of Sec. 3.2-3.3 on the solved designs, and of the force
 inverter of Sec. 4.1 (input and adjoint solves with ground springs, adjoint
 sensitivity) on a 160 x 80 p = 3, d = 4 mesh, all outside the timed step).
 """
@@ -133,6 +134,37 @@ def time_mechanism(mto, args, steps=3):
     return {"workload": "force inverter 160x80 (half model), p=3 d=4, springs k_in=1 k_out=0.001, FP64",
             "s_per_design": round(dt, 6), "pcg_iterations": stats["iterations"], "J": float(J),
             "n_free_dofs_per_case": plan.info["n_free_total"] // 2, "grad_norm": float(g[:pr.n_cells].norm())}
+
+
+def time_adapt(mto, plan, prs, rho, u, reps=5):
+    """Refinement indicators of Sec. 3.2 (Kelly, density) on the solved
+    designs and the host dp update of Sec. 3.3 on the first design: mean
+    time per call."""
+    import numpy as np
+    import torch
+
+    st = torch.cuda.current_stream()
+    res = {}
+    for name, fn in (("kelly", lambda: plan.kelly_indicator(u)), ("density", lambda: plan.density_indicator(rho, 1))):
+        out = fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            out = fn()
+        e1.record(st)
+        e1.synchronize()
+        res[f"{name}_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+        res[f"{name}_out"] = out
+    pr = prs[0]
+    ga = res.pop("kelly_out")[:pr.nelx * pr.nely].cpu().numpy()
+    gd = res.pop("density_out")[:pr.nelx * pr.nely].cpu().numpy()
+    t0 = time.perf_counter()
+    p_new, theta, dp, cells = mto.dp_update(pr.nelx, pr.nely, pr.p, ga, gd)
+    res["dp_update_host_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+    res["refined"] = int((p_new > pr.p).sum())
+    res["coarsened"] = int((p_new < pr.p).sum())
+    res["cells_per_element"] = cells
+    return res
 
 
 def time_qr(plan, rho, u, reps=5):
@@ -277,6 +309,8 @@ def main():
         out["density_filter"] = time_filter(mto, prs, rho, args.filter_radius)
     if not args.no_qr:
         out["qr_error"] = time_qr(plan, rho, u)
+    if not args.no_qr:
+        out["adapt"] = time_adapt(mto, plan, prs, rho, u)
     if not args.no_mechanism:
         out["mechanism"] = time_mechanism(mto, args)
 
