@@ -84,6 +84,13 @@ class _Info(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run paper_1811_09821_amd.build.build()")
+    # The library and torch must share one HIP runtime in the process.  torch
+    # ships its own libamdhip64 with the same soname as the system one the
+    # library links against, plus its own HSA runtime; loading torch first
+    # makes the dynamic loader bind the library to torch's HIP runtime.  The
+    # other order mixes two HSA runtimes, and the library then finds no device.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
     sig = {
