@@ -142,6 +142,9 @@ struct mto_plan {
   int32_t* h_active = nullptr;  // [2]
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
+  // the multigrid set-up runs on side_stream beside the Schwarz block inverses
+  hipStream_t side_stream = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // graphs
   hipGraphExec_t chunk_exec = nullptr;
   int chunk_G = 0;
@@ -759,8 +762,12 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
   for (int k = 0; k < 2; ++k)
     if (hipEventCreateWithFlags(&P->ev[k], hipEventDisableTiming) != hipSuccess)
       return cleanup(fail(MTO_EHIP, "hipEventCreate failed"));
-  if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess)
+  if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(fail(MTO_EHIP, "hipStreamCreate failed"));
+  if (hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming) != hipSuccess)
+    return cleanup(fail(MTO_EHIP, "hipEventCreate failed"));
   if (P->prm.precond != MTO_PRECOND_JACOBI && (rc = build_mg(P, I))) return cleanup(rc);
   if (P->prm.precond == MTO_PRECOND_MG_ASM && (rc = build_asm(P, I))) return cleanup(rc);
   if ((rc = rebuild_tiles(P))) return cleanup(rc);
@@ -848,12 +855,23 @@ void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st)
   for (auto& g : P->groups)
     launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, l1 ? g.kabs : g.kdiag, st);
   launch_dinv(s, P->dinv, damped ? P->prm.mg_omega : 1.0, st);
+  // The multigrid set-up (Galerkin operators, then the coarsest factor and
+  // inverse, which keep one CU busy for most of their time) depends only on
+  // the moduli, as do the Schwarz block inverses: it runs as a branch on the
+  // side stream (under capture, a parallel branch of the graph) and joins
+  // before the first V-cycle.  Nothing on the main stream until the join
+  // touches the multigrid buffers.
+  if (mg) {
+    (void)hipEventRecord(P->fork_ev, st);
+    (void)hipStreamWaitEvent(P->side_stream, P->fork_ev, 0);
+    enq_mg_setup(P, P->side_stream);
+    (void)hipEventRecord(P->join_ev, P->side_stream);
+  }
   if (P->prm.precond == MTO_PRECOND_MG_ASM)
     for (size_t gi = 0; gi < P->groups.size(); ++gi) {
       const GroupHost& g = P->groups[gi];
       launch_asm_block(P->gdev(g), (int)gi, P->d_groups, g.nbr, P->d_el_group, P->d_el_col, P->E, g.binv, st);
     }
-  if (mg) enq_mg_setup(P, st);
   // PCG iterates on the correction x (from 0); the solution is xs_hi + xs_lo
   launch_fill(P->x, 0.0, P->n_vec, st);
   launch_fill(P->xs_lo, 0.0, P->n_vec, st);
@@ -866,7 +884,10 @@ void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st)
     launch_init(s, 0, st);
   }
   launch_sys_setup(s, P->prm.rtol, st);
-  if (mg) enq_vcycle(P, 0, 1, st);
+  if (mg) {
+    (void)hipStreamWaitEvent(st, P->join_ev, 0);
+    enq_vcycle(P, 0, 1, st);
+  }
 }
 
 void enq_chunk(mto_plan* P, int G, hipStream_t st) {
@@ -1483,6 +1504,9 @@ void mto_plan_destroy(mto_plan* P) {
   for (int k = 0; k < 2; ++k)
     if (P->ev[k]) (void)hipEventDestroy(P->ev[k]);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
+  if (P->fork_ev) (void)hipEventDestroy(P->fork_ev);
+  if (P->join_ev) (void)hipEventDestroy(P->join_ev);
   delete P;
 }
 
