@@ -195,6 +195,9 @@ void launch_mg_resid(const MgChunk* ch, int n, const PcgDev& s, const double* A,
                      double* t, hipStream_t st);
 void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* mask, const double* dinv,
                         const double* t, double* r, double* e, hipStream_t st);
+// levels l-1 -> l of the V-cycle in one launch (ch: the level-l system chunks)
+void launch_mg_resid_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
+                              const double* dinv, double* r, double* e, hipStream_t st);
 void launch_mg_coarse_solve(const MgChunk* ch, int n, int nmax, const PcgDev& s, const double* dense, const double* r,
                             double* e2, hipStream_t st);
 // vfree != NULL (level 1): also z += e2 at the free vertex DOFs

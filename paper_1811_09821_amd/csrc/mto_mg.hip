@@ -682,6 +682,64 @@ __global__ __launch_bounds__(MGB) void k_mg_restrict(const MgChunk* __restrict__
   if (n < ch.node_end) mg_restrict_node(ch, n, mask, dinv, t, r, e);
 }
 
+// Levels l-1 -> l in one launch: r_l = R^T (mask * (r_{l-1} - A_{l-1} e_{l-1}))
+// with the level l-1 residual formed where the restriction needs it.  16
+// lanes per coarse node: lane k < 9 takes the fine node at offset
+// (k % 3 - 1, k / 3 - 1) from the node's fine position, its weight and its
+// 9-point residual; the 16 lanes sum with a fixed butterfly; then
+// e_l = D^-1 r_l (pre-smoothing from zero).  A fine node is evaluated by each
+// coarse node it restricts to (2.25 times on average) instead of being
+// written and read back by a separate residual pass.
+constexpr int MG_RR_NODES = 16;  // coarse nodes per 256-thread block
+
+__global__ __launch_bounds__(256) void k_mg_resid_restrict(const MgChunk* __restrict__ chunks, PcgDev s,
+                                                           const double* __restrict__ A,
+                                                           const double* __restrict__ mask,
+                                                           const double* __restrict__ dinv, double* __restrict__ r,
+                                                           double* __restrict__ e) {
+  const MgChunk ch = chunks[blockIdx.x];
+  if (!sys_running(s, ch.sys)) return;  // whole block
+  const int sub = threadIdx.x & 15;
+  const int n = ch.node_begin + blockIdx.y * MG_RR_NODES + (threadIdx.x >> 4);
+  const bool node_ok = n < ch.node_end;
+  double acc0 = 0.0, acc1 = 0.0;
+  if (node_ok && sub < 9) {
+    const int nx = ch.nx, fnx = ch.fnx, fny = ch.fny;
+    const int cx = n % (nx + 1), cy = n / (nx + 1);
+    const int fx = fine_of(cx, fnx) + sub % 3 - 1, fy = fine_of(cy, fny) + sub / 3 - 1;
+    if (fx >= 0 && fx <= fnx && fy >= 0 && fy <= fny) {
+      const double w = weight1d(fx, fnx, cx) * weight1d(fy, fny, cy);
+      if (w != 0.0) {
+        const int64_t fo = (int64_t)fy * (fnx + 1) + fx;
+        const int64_t fnode = ch.fop + fo, fv = ch.fvec + fo;
+        double t0 = r[fv * 2], t1 = r[fv * 2 + 1];
+        for (int k = 0; k < 9; ++k) {
+          const int jx = fx + k % 3 - 1, jy = fy + k / 3 - 1;
+          if (jx < 0 || jx > fnx || jy < 0 || jy > fny) continue;
+          const int64_t jv = ch.fvec + (int64_t)jy * (fnx + 1) + jx;
+          const double* a = A + fnode * 36 + k * 4;
+          const double ej0 = e[jv * 2], ej1 = e[jv * 2 + 1];
+          t0 -= a[0] * ej0 + a[1] * ej1;
+          t1 -= a[2] * ej0 + a[3] * ej1;
+        }
+        acc0 = w * mask[fnode * 2] * t0;
+        acc1 = w * mask[fnode * 2 + 1] * t1;
+      }
+    }
+  }
+  for (int o = 8; o > 0; o >>= 1) {
+    acc0 += __shfl_xor(acc0, o, 16);
+    acc1 += __shfl_xor(acc1, o, 16);
+  }
+  if (node_ok && sub == 0) {
+    const int64_t node = ch.op + n, v = ch.vec + n;
+    r[v * 2] = acc0;
+    r[v * 2 + 1] = acc1;
+    e[v * 2] = dinv[node * 2] * acc0;
+    e[v * 2 + 1] = dinv[node * 2 + 1] * acc1;
+  }
+}
+
 // Coarsest level: e2 = X r with the dense inverse X (natural order), one
 // wave per row, the lanes over contiguous stretches of the row.
 __global__ __launch_bounds__(256) void k_mg_coarse_solve(const MgChunk* __restrict__ chunks, PcgDev s,
@@ -1024,6 +1082,12 @@ void launch_mg_resid(const MgChunk* ch, int n, const PcgDev& s, const double* A,
 void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* mask, const double* dinv,
                         const double* t, double* r, double* e, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_mg_restrict, dim3(n), dim3(MGB), 0, st, ch, s, mask, dinv, t, r, e);
+}
+void launch_mg_resid_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
+                              const double* dinv, double* r, double* e, hipStream_t st) {
+  if (n)
+    hipLaunchKernelGGL(k_mg_resid_restrict, dim3(n, MG_CHUNK / MG_RR_NODES), dim3(256), 0, st, ch, s, A, mask, dinv,
+                       r, e);
 }
 void launch_mg_coarse_solve(const MgChunk* ch, int n, int nmax, const PcgDev& s, const double* dense, const double* r,
                             double* e2, hipStream_t st) {

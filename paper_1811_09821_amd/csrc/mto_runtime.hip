@@ -810,10 +810,8 @@ void enq_coarse_correction(mto_plan* P, hipStream_t st) {
   const MgHost& M = P->mg;
   const PcgDev s = P->pcg();
   launch_mg_restrict0(M.sysc(1), M.sys_count[0], s, M.vfree, M.dinv, M.r, M.e, st);
-  for (int l = 2; l <= M.L; ++l) {
-    launch_mg_resid(M.sysc(l - 1), M.sys_count[l - 2], s, M.A, M.r, M.e, M.t, st);
-    launch_mg_restrict(M.sysc(l), M.sys_count[l - 1], s, M.mask, M.dinv, M.t, M.r, M.e, st);
-  }
+  for (int l = 2; l <= M.L; ++l)
+    launch_mg_resid_restrict(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, st);
   launch_mg_coarse_solve(M.coarse_sysc(), P->n_sys, M.coarse_nmax, s, M.dense, M.r, M.e2, st);
   // level 1 also injects its correction into z (with one level, prolong0 does)
   for (int l = M.L - 1; l >= 1; --l)
