@@ -670,9 +670,11 @@ __global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
 
 __global__ __launch_bounds__(BLOCK) void k_advance(PcgDev s, int G) {
   __shared__ int cnt[WAVES];
+  __shared__ double far_w[WAVES];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int it_new = *s.it_base + G;
   int active = 0;
+  double far = 0.0;  // largest rr / tol2 of a running system (how far it is from stopping)
   for (int sys = wave; sys < s.n_sys; sys += WAVES) {
     const SysDesc& sd = s.sys[sys];
     const double rr = wave_sum(s.part_rr + (it_new & 1) * s.n_chunks, sd.chunk_begin, sd.chunk_end);
@@ -682,15 +684,24 @@ __global__ __launch_bounds__(BLOCK) void k_advance(PcgDev s, int G) {
         if (lane == 0) s.status[sys] = SYS_CONVERGED;
       } else {
         ++active;
+        far = fmax(far, rr / s.tol2[sys]);
       }
     }
   }
-  if (lane == 0) cnt[wave] = active;
+  if (lane == 0) {
+    cnt[wave] = active;
+    far_w[wave] = far;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     int tot = 0;
-    for (int w = 0; w < WAVES; ++w) tot += cnt[w];
-    *s.n_active = tot;
+    double f = 0.0;
+    for (int w = 0; w < WAVES; ++w) {
+      tot += cnt[w];
+      f = fmax(f, far_w[w]);
+    }
+    s.progress[0] = (double)tot;
+    s.progress[1] = f;
     *s.it_base = it_new;
   }
 }

@@ -102,7 +102,7 @@ struct PcgDev {
   double* tol2;            // [n_sys]
   double* sys_out;         // [n_sys][4]: f.f, f.x, |f-Kx|^2, spare
   int32_t* it_base;        // [1]
-  int32_t* n_active;       // [1]
+  double* progress;        // [2]: systems still running, largest rr / tol2 among them
 };
 
 // ELEM_APPLY_RUNNING: as ELEM_APPLY, skipping systems whose PCG has stopped.

@@ -46,6 +46,7 @@ namespace {
   } while (0)
 
 constexpr int CHUNK = 1024;  // free DOFs per vector-kernel block (one per thread)
+constexpr int N_PROG = 4;    // PCG chunk launches in flight at most
 
 struct DevBuf {
   void* ptr = nullptr;
@@ -132,22 +133,25 @@ struct mto_plan {
   double* slots_lo = nullptr;  // low parts of the double-double residual contraction
   double *xs_hi = nullptr, *xs_lo = nullptr;  // refined solution, double-double
   double *part_pq = nullptr, *part_rz = nullptr, *part_rr = nullptr, *part_aux = nullptr;
-  int32_t *status = nullptr, *iters = nullptr, *it_base = nullptr, *n_active = nullptr;
+  int32_t *status = nullptr, *iters = nullptr, *it_base = nullptr;
+  double* progress = nullptr;  // [2], written by each chunk's last kernel
   double *tol2 = nullptr, *sys_out = nullptr;
   int32_t* f2f = nullptr;
   double* kspr = nullptr;  // ground springs per instance free DOF (NULL: none)
   int64_t *d_inst_cell_off = nullptr, *d_inst_g_off = nullptr;  // [n_inst + 1], [n_inst]
   int32_t *d_inst_c_off = nullptr, *d_inst_L = nullptr;
-  // host pinned
-  int32_t* h_active = nullptr;  // [2]
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  // host pinned: one progress report per chunk launch in flight
+  double* h_prog = nullptr;  // [N_PROG][2]
+  hipEvent_t ev[N_PROG] = {};
+  // per-iteration decrease of log(rr / tol2) seen last (0: none yet)
+  double rate_hint = 0.0;
   hipStream_t cap_stream = nullptr;
   // the multigrid set-up runs on side_stream beside the Schwarz block inverses
   hipStream_t side_stream = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // graphs
-  hipGraphExec_t chunk_exec = nullptr;
-  int chunk_G = 0;
+  hipGraphExec_t chunk_exec = nullptr, small_exec = nullptr;
+  int chunk_G = 0, small_G = 0;
   // bound (captured) buffers
   bool bound = false;
   const double* b_rho = nullptr;
@@ -192,7 +196,7 @@ struct mto_plan {
     s.tol2 = tol2;
     s.sys_out = sys_out;
     s.it_base = it_base;
-    s.n_active = n_active;
+    s.progress = progress;
     return s;
   }
   GroupDev gdev(const GroupHost& g) const {
@@ -240,7 +244,7 @@ int dev_upload(mto_plan* P, T** out, const std::vector<T>& h) {
 }
 
 void destroy_graphs(mto_plan* P) {
-  hipGraphExec_t* gs[] = {&P->chunk_exec, &P->setup_exec, &P->resid_exec, &P->restart_exec, &P->out_exec};
+  hipGraphExec_t* gs[] = {&P->chunk_exec, &P->small_exec, &P->setup_exec, &P->resid_exec, &P->restart_exec, &P->out_exec};
   for (auto g : gs)
     if (*g) {
       (void)hipGraphExecDestroy(*g);
@@ -729,7 +733,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_alloc(P, &P->part_pq, nch)) || (rc = dev_alloc(P, &P->part_rz, 2 * nch)) ||
       (rc = dev_alloc(P, &P->part_rr, 2 * nch)) || (rc = dev_alloc(P, &P->part_aux, 3 * nch)) ||
       (rc = dev_alloc(P, &P->status, P->n_sys)) || (rc = dev_alloc(P, &P->iters, P->n_sys)) ||
-      (rc = dev_alloc(P, &P->it_base, 1)) || (rc = dev_alloc(P, &P->n_active, 1)) ||
+      (rc = dev_alloc(P, &P->it_base, 1)) || (rc = dev_alloc(P, &P->progress, 2)) ||
       (rc = dev_alloc(P, &P->tol2, P->n_sys)) || (rc = dev_alloc(P, &P->sys_out, 4 * (size_t)P->n_sys)) ||
       (rc = dev_upload(P, &P->f2f, f2f)))
     return cleanup(rc);
@@ -757,9 +761,9 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
   launch_fill(P->slots_lo, 0.0, P->n_slots_tot, 0);
   launch_fill(P->x, 0.0, P->n_vec, 0);
   if ((rc = check_launch("fill"))) return cleanup(rc);
-  if (hipHostMalloc((void**)&P->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void**)&P->h_prog, 2 * N_PROG * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(MTO_ENOMEM, "hipHostMalloc failed"));
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < N_PROG; ++k)
     if (hipEventCreateWithFlags(&P->ev[k], hipEventDisableTiming) != hipSuccess)
       return cleanup(fail(MTO_EHIP, "hipEventCreate failed"));
   if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess ||
@@ -947,40 +951,90 @@ int capture(mto_plan* P, hipGraphExec_t* exec, const std::function<void(hipStrea
   return MTO_OK;
 }
 
+// The chunk graphs: G iterations, and a short one of max(2, G / 4) for the
+// last iterations before convergence (both even: the parity of it_base).
 int ensure_chunk_graph(mto_plan* P) {
   const int G = P->prm.iters_per_launch;
-  if (P->chunk_exec && P->chunk_G == G) return MTO_OK;
+  if (P->chunk_exec && P->small_exec && P->chunk_G == G) return MTO_OK;
+  const int Gs = std::max(2, (G / 4) & ~1);
   int rc = capture(P, &P->chunk_exec, [&](hipStream_t st) { enq_chunk(P, G, st); });
   if (rc) return rc;
+  if ((rc = capture(P, &P->small_exec, [&](hipStream_t st) { enq_chunk(P, Gs, st); }))) return rc;
   P->chunk_G = G;
+  P->small_G = Gs;
   return MTO_OK;
 }
 
 // Runs PCG iterations until every system has stopped or the cap is reached.
-int iterate(mto_plan* P, hipStream_t st, int64_t& launched) {
+// Each chunk ends by reporting the number of running systems and the largest
+// rr / tol2 among them.  The host keeps at most two full chunks queued past
+// the last report, as a plain pipeline would, but no more iterations than
+// the log-linear extrapolation of that ratio to 1 asks for; near the end it
+// queues short chunks, so that few iterations are launched after the last
+// system has stopped (those return at once but still cost their launches).
+// r0 is rr / tol2 at iteration 0 when the caller knows it (else <= 0).
+int iterate(mto_plan* P, hipStream_t st, int64_t& launched, double r0) {
   int rc = ensure_chunk_graph(P);
   if (rc) return rc;
-  const int G = P->chunk_G;
+  const int G = P->chunk_G, Gs = P->small_G;
   int64_t cap = P->prm.max_iter;
   if (cap <= 0) {
     int64_t mx = 0;
     for (int i = 0; i < P->n_inst; ++i) mx = std::max(mx, P->n_free[i]);
     cap = std::max<int64_t>(20 * mx, 1000);
   }
-  int64_t k = 0;
-  launched = 0;
+  struct Pending {
+    int slot;
+    int64_t end;
+  };
+  Pending pend[N_PROG];
+  int head = 0, n_pend = 0, next_slot = 0;
+  int64_t queued = 0, known = 0;
+  // reports (iteration, rr / tol2) of this cycle while systems still run
+  std::vector<std::pair<int64_t, double>> hist;
+  if (r0 > 1.0 && std::isfinite(r0)) hist.emplace_back(0, r0);
+  auto launch = [&](bool full) -> int {
+    const int slot = next_slot;
+    next_slot = (next_slot + 1) % N_PROG;
+    HIP_TRY(hipGraphLaunch(full ? P->chunk_exec : P->small_exec, st));
+    HIP_TRY(hipMemcpyAsync(P->h_prog + 2 * slot, P->progress, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(P->ev[slot], st));
+    queued += full ? G : Gs;
+    pend[(head + n_pend) % N_PROG] = Pending{slot, queued};
+    ++n_pend;
+    return MTO_OK;
+  };
+  double rate = 0.0;
   while (true) {
-    HIP_TRY(hipGraphLaunch(P->chunk_exec, st));
-    HIP_TRY(hipMemcpyAsync(&P->h_active[k & 1], P->n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipEventRecord(P->ev[k & 1], st));
-    launched += G;
-    if (k >= 1) {
-      HIP_TRY(hipEventSynchronize(P->ev[(k - 1) & 1]));
-      if (P->h_active[(k - 1) & 1] == 0) break;
+    int64_t target = known + 2 * G;
+    rate = 0.0;
+    if (hist.size() >= 2) {
+      // the latest report against the newest one at least G iterations older
+      size_t j = hist.size() - 2;
+      while (j > 0 && hist.back().first - hist[j].first < G) --j;
+      rate = std::log(hist[j].second / hist.back().second) / double(hist.back().first - hist[j].first);
     }
-    if (launched >= cap) break;
-    ++k;
+    if (!(rate > 0.0 && std::isfinite(rate))) rate = P->rate_hint;
+    if (rate > 0.0 && !hist.empty()) {
+      const double need = std::ceil(std::log(hist.back().second) / rate);  // >= 1: the ratio is > 1
+      if (need < double(cap)) target = std::min(target, hist.back().first + (int64_t)need);
+    }
+    if (queued < target && queued < cap && n_pend < N_PROG) {
+      if ((rc = launch(target - queued >= G))) return rc;
+      continue;
+    }
+    if (n_pend == 0) break;  // the cap is reached
+    const Pending pd = pend[head];
+    head = (head + 1) % N_PROG;
+    --n_pend;
+    HIP_TRY(hipEventSynchronize(P->ev[pd.slot]));
+    known = pd.end;
+    const double running = P->h_prog[2 * pd.slot], far = P->h_prog[2 * pd.slot + 1];
+    if (running == 0.0) break;
+    if (far > 1.0 && std::isfinite(far)) hist.emplace_back(pd.end, far);
   }
+  if (rate > 0.0 && std::isfinite(rate)) P->rate_hint = rate;
+  launched = queued;
   HIP_TRY(hipStreamSynchronize(st));
   return MTO_OK;
 }
@@ -1017,9 +1071,13 @@ int run_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, c
   std::vector<int32_t> iters_total(P->n_sys, 0);
   std::vector<double> prev_res(P->n_sys, 0.0);
   int final_status = MTO_OK;
+  // rr / tol2 at the start of a cycle: 1 / rtol^2 from x = 0, else from the
+  // true residuals of the last cycle (unknown for a given initial guess)
+  const double rtol2 = P->prm.rtol * P->prm.rtol;
+  double r0 = u0 ? 0.0 : 1.0 / rtol2;
   while (true) {
     int64_t launched = 0;
-    if ((rc = iterate(P, st, launched))) return rc;
+    if ((rc = iterate(P, st, launched, r0))) return rc;
     if (graphs) {
       HIP_TRY(hipGraphLaunch(P->resid_exec, st));
     } else {
@@ -1040,6 +1098,8 @@ int run_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, c
       const bool improving = restarts == 0 || res < 0.25 * prev_res[s];
       if (R.status[s] == SYS_CONVERGED && misses && improving) need_restart = true;
       prev_res[s] = res;
+      if (s == 0) r0 = 0.0;
+      if (ff > 0.0) r0 = std::max(r0, res / (rtol2 * ff));
     }
     if (any_breakdown) {
       final_status = MTO_EBREAKDOWN;
@@ -1498,8 +1558,8 @@ void mto_plan_destroy(mto_plan* P) {
   destroy_graphs(P);
   for (auto& a : P->allocs)
     if (a.ptr) (void)hipFree(a.ptr);
-  if (P->h_active) (void)hipHostFree(P->h_active);
-  for (int k = 0; k < 2; ++k)
+  if (P->h_prog) (void)hipHostFree(P->h_prog);
+  for (int k = 0; k < N_PROG; ++k)
     if (P->ev[k]) (void)hipEventDestroy(P->ev[k]);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
