@@ -126,6 +126,8 @@ typedef struct {
                                factor if > 0, else l1-Jacobi.  MTO_PRECOND_MG_ASM: Schwarz
                                damping if > 0, else 2 / (9 * 1.05), below the bound 2 / 9 that
                                the nine-colouring of element blocks guarantees */
+  int32_t mg_coarse_max;    /* multigrid: coarsen until the largest instance's grid has at most this
+                               many DOFs, solved exactly (<= 0: 3000, the most allowed) */
 } mto_params;
 
 /* A linear spring from one vertex DOF to ground, stiffness k > 0: adds k to

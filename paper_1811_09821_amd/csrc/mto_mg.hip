@@ -257,29 +257,40 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 // step.  Outputs: the row form (L[i][i - t]) and the column form
 // (L[j + 1 + t][j]), each with 1 / L[i][i], in the padded layout described
 // with MG_BAND_RS.
-//   Window: rows J .. J + b + NB - 1 in a ring of b + NB slots (row i in
-//   slot i % (b + NB)), slot row t holding entry (i, i - t).
-//   Step J: wave 0 loads the panel (columns J .. J + NB - 1 of its b + NB
-//   rows, two rows per lane) into registers and factors it column by column
-//   (diagonal and column entries broadcast with lane reads), then writes it to
-//   LDS and to both outputs; after a barrier every thread applies the rank-NB
-//   update to its (row, up to 4 columns) of the trailing b x b triangle, and
-//   the NB retired slots are refilled with the next rows of the operator
-//   (loaded before the panel).  Two barriers per NB columns.
+//   Window: rows J .. J + b + NB - 1 in a ring of R = b + NB slots (row i in
+//   slot i % R), slot row t holding entry (i, i - t).
+//   Step J: wave 0 factors the panel (columns J .. J + NB - 1 of its R rows,
+//   two rows per lane, in registers; diagonal and column entries broadcast
+//   with lane reads) and leaves it, with the reciprocal diagonal, in LDS.
+//   After a barrier the rank-NB update of the trailing b x b triangle runs
+//   on the matrix cores: 16 x 16 tiles of it, one per wave (at most 15), each
+//   two v_mfma_f64_16x16x4f64 on panel rows read from LDS.  Meanwhile waves
+//   1 .. 11 refill the NB retired slots with the next rows of the operator
+//   (loaded before the barrier) and waves 12 .. 15 write the panel to both
+//   outputs.  Two barriers per NB columns.  Only the writer waves issue
+//   global stores, so no other wave ever waits for their completion.
 constexpr int MG_CHOL_BLOCK = 1024;
 constexpr int MG_CHOL_NB = 8;
 constexpr int MG_CHOL_LP = MG_CHOL_NB + 1;  // panel row stride in LDS (odd, against bank conflicts)
 
-__host__ __device__ constexpr int chol_items(int b) {  // trailing-update items: sum over rows of ceil((ii + 1) / 4)
-  return b <= 0 ? 0 : chol_items(b - 1) + (b + 3) / 4;
+__host__ __device__ constexpr int chol_tiles(int b) {  // 16 x 16 tiles of the trailing triangle
+  return ((b + 15) / 16) * ((b + 15) / 16 + 1) / 2;
 }
-static_assert(chol_items(MG_BAND_MAX) <= MG_CHOL_BLOCK, "band too wide for one update item per thread");
-static_assert(MG_BAND_MAX + MG_CHOL_NB <= 128, "panel rows must fit two per lane");
+static_assert(chol_tiles(MG_BAND_MAX) <= MG_CHOL_BLOCK / 64 - 1, "one trailing tile per wave 1..");
+constexpr int MG_CHOL_WRITER0 = 768;  // first writer thread (waves 12 .. 15)
+static_assert(64 + MG_CHOL_NB * (MG_BAND_MAX + 1) <= MG_CHOL_WRITER0, "one refill entry per thread of waves 1 .. 11");
+static_assert(MG_CHOL_NB + 16 * ((MG_BAND_MAX + 15) / 16) <= 128, "panel rows must fit two per lane");
+static_assert(MG_CHOL_NB == 8, "two MFMA k-steps of 4");
+
+// panel rows kept in LDS: the window's R rows and zero rows up to whole tiles
+__host__ __device__ constexpr int chol_panel_rows(int b) { return MG_CHOL_NB + 16 * ((b + 15) / 16); }
 
 size_t chol_lds_bytes(int b) {
   const int R = b + MG_CHOL_NB;
-  return (size_t)(R * (b + 1) + R * MG_CHOL_LP) * sizeof(double);
+  return (size_t)(R * (b + 1) + chol_panel_rows(b) * MG_CHOL_LP + MG_CHOL_NB) * sizeof(double);
 }
+
+typedef double chol_d4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk* __restrict__ chunks,
                                                                  const double* __restrict__ A,
@@ -288,9 +299,10 @@ __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk*
   constexpr int NB = MG_CHOL_NB, LP = MG_CHOL_LP;
   const MgChunk ch = chunks[blockIdx.x];
   const int n = 2 * (ch.node_end - ch.node_begin);
-  const int b = band_width(ch), w = b + 1, R = b + NB;
+  const int b = band_width(ch), w = b + 1, R = b + NB, RP = chol_panel_rows(b);
   double* __restrict__ W = lds_chol;            // [R][w]
-  double* __restrict__ Lp = lds_chol + R * w;   // [R][LP]: panel row J + r at r
+  double* __restrict__ Lp = lds_chol + R * w;   // [RP][LP]: panel row J + r at r
+  double* __restrict__ rjl = Lp + RP * LP;      // [NB]: 1 / L[J + t][J + t]
   const int tid = threadIdx.x, nt = blockDim.x, wave = tid >> 6, lane = tid & 63;
   double* __restrict__ out = band + ch.band_off + MG_INV_PD * MG_BAND_RS;                   // row form
   double* __restrict__ outc = band + ch.band_off + (int64_t)(n + 2 * MG_INV_PD) * MG_BAND_RS;  // column form
@@ -298,32 +310,33 @@ __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk*
     const int r = idx / w, t = idx - r * w;
     W[idx] = (r < n && r - t >= 0) ? band_entry(ch, A, r, r - t) : 0.0;
   }
-  // this thread's trailing-update item: relative row ii, columns g, g + G, g + 2G, g + 3G (<= ii),
-  // G = ceil((ii + 1) / 4); consecutive threads take consecutive columns of a row
-  int my_ii = -1, my_g = 0, my_G = 1;
+  // this wave's trailing tile (rows 16 tI.., columns 16 tK.., tK <= tI), if any
+  int tI = -1, tK = 0;
   {
-    int acc = 0;
-    for (int ii = 0; ii < b; ++ii) {
-      const int G = (ii + 4) >> 2;
-      if (tid < acc + G) {
-        my_ii = ii;
-        my_g = tid - acc;
-        my_G = G;
-        break;
+    const int nT = (b + 15) >> 4;
+    int k = wave - 1;
+    if (k >= 0 && k < nT * (nT + 1) / 2)
+      for (int I = 0; I < nT; ++I) {
+        if (k <= I) {
+          tI = I;
+          tK = k;
+          break;
+        }
+        k -= I + 1;
       }
-      acc += G;
-    }
   }
+  const int at = tid - 64;                                         // refill entry (waves 1 .. 11)
+  const int wt = tid - MG_CHOL_WRITER0, n_wt = nt - MG_CHOL_WRITER0;  // writer index (waves 12 .. 15)
   __syncthreads();
   for (int J = 0; J < n; J += NB) {  // uniform
     const int nb = min(NB, n - J);
-    // rows J + R .. J + R + NB - 1 enter the slots of rows J .. J + NB - 1 after the panel
+    // rows J + R .. J + R + NB - 1 go to the slots of rows J .. J + NB - 1 after the panel
     double pre = 0.0;
     int pre_at = -1;
-    if (tid < NB * w) {
-      const int r = J + R + tid / w, t = tid - (tid / w) * w;
+    if (at >= 0 && tid < MG_CHOL_WRITER0 && at < NB * w) {
+      const int r = J + R + at / w, t = at - (at / w) * w;
       pre_at = (r % R) * w + t;
-      pre = (r < n && r - t >= 0) ? band_entry(ch, A, r, r - t) : 0.0;
+      if (r < n && r - t >= 0) pre = band_entry(ch, A, r, r - t);
     }
     if (wave == 0) {
       double p[2][NB];
@@ -336,14 +349,13 @@ __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk*
           p[q][t] = (r < R && i < n && o >= 0 && o <= b) ? W[(i % R) * w + o] : 0.0;
         }
       }
-      double rjs[NB];
+      double rjs = 0.0;  // lane t < NB keeps 1 / L[J + t][J + t]
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
-        rjs[t] = 0.0;
         if (t >= nb) break;  // uniform
         const double dj = sqrt(readlane_f64(p[0][t], t));
         const double rj = 1.0 / dj;
-        rjs[t] = rj;
+        if (lane == t) rjs = rj;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int r = lane + 64 * q;
@@ -361,50 +373,49 @@ __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk*
       }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int r = lane + 64 * q, i = J + r;
-        if (r < R) {
+        const int r = lane + 64 * q;
+        if (r < RP) {
 #pragma unroll
           for (int t = 0; t < NB; ++t) Lp[r * LP + t] = p[q][t];
         }
-        if (r < R && i < n) {
-#pragma unroll
-          for (int t = 0; t < NB; ++t) {
-            const int o = r - t;
-            if (t < nb && o >= 0 && o <= b) {
-              if (o == 0) {
-                out[(int64_t)i * MG_BAND_RS + 128] = rjs[t];
-                outc[(int64_t)i * MG_BAND_CS + 127] = rjs[t];
-              } else {
-                out[(int64_t)i * MG_BAND_RS + o] = p[q][t];
-                outc[(int64_t)(J + t) * MG_BAND_CS + (o - 1)] = p[q][t];
-              }
-            }
-          }
-        }
       }
+      if (lane < NB) rjl[lane] = rjs;
     }
     __syncthreads();
-    if (my_ii >= 0) {
-      const int i = J + NB + my_ii;
-      if (i < n) {
-        double li[NB];
+    if (tI >= 0) {
+      // A[m][k] = L[J + NB + 16 tI + m][J + k], B[k][c] = L[J + NB + 16 tK + c][J + k]
+      const int m = lane & 15, k4 = lane >> 4;
+      const double* __restrict__ la = Lp + (NB + 16 * tI + m) * LP + k4;
+      const double* __restrict__ lb = Lp + (NB + 16 * tK + m) * LP + k4;
+      chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(la[0], lb[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(la[4], lb[4], acc, 0, 0, 0);
+      // D lane l holds D[l / 16 + 4 r][l % 16]
+      const int kk = 16 * tK + m;
 #pragma unroll
-        for (int t = 0; t < NB; ++t) li[t] = Lp[(NB + my_ii) * LP + t];
-        double* __restrict__ Wi = W + (i % R) * w;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int kk = my_g + u * my_G;
-          if (kk <= my_ii) {
-            const double* __restrict__ lk = Lp + (NB + kk) * LP;
-            double s = 0.0;
-#pragma unroll
-            for (int t = 0; t < NB; ++t) s = fma(li[t], lk[t], s);
-            Wi[my_ii - kk] -= s;
-          }
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int ii = 16 * tI + k4 + 4 * r, i = J + NB + ii;
+        if (kk <= ii && ii < b && i < n) W[(i % R) * w + (ii - kk)] -= acc[r];
       }
     }
     if (pre_at >= 0) W[pre_at] = pre;
+    if (wt >= 0) {
+      // the panel's entries (J + r, J + t), o = r - t, to both output forms
+      for (int e = wt; e < R * NB; e += n_wt) {
+        const int r = e / NB, t = e - (e / NB) * NB, i = J + r, o = r - t;
+        if (t < nb && i < n && o >= 0 && o <= b) {
+          if (o == 0) {
+            const double rj = rjl[t];
+            out[(int64_t)i * MG_BAND_RS + 128] = rj;
+            outc[(int64_t)i * MG_BAND_CS + 127] = rj;
+          } else {
+            const double v = Lp[r * LP + t];
+            out[(int64_t)i * MG_BAND_RS + o] = v;
+            outc[(int64_t)(J + t) * MG_BAND_CS + (o - 1)] = v;
+          }
+        }
+      }
+    }
     __syncthreads();
   }
 }

@@ -309,16 +309,17 @@ int check_launch(const char* what) {
 
 // Builds the multigrid hierarchy: per instance the vertex grid of the mesh
 // (level 1) and its coarsenings by two, until the largest instance's grid
-// has at most MG_COARSE_MAX DOFs (smaller instances continue to coarsen,
+// has at most mg_coarse_max DOFs (smaller instances continue to coarsen,
 // down to one element, so every instance has the same number of levels).
 int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
   MgHost& M = P->mg;
   const int n = P->n_inst;
   std::vector<std::vector<std::pair<int, int>>> dims(n);
+  const int64_t cmax = P->prm.mg_coarse_max;
   int L = 1;
   for (int i = 0; i < n; ++i) {
     int nx = I[i].nelx, ny = I[i].nely, l = 1;
-    while ((2LL * (nx + 1) * (ny + 1) > MG_COARSE_MAX || 2 * std::min(nx, ny) + 5 > MG_BAND_MAX) &&
+    while ((2LL * (nx + 1) * (ny + 1) > cmax || 2 * std::min(nx, ny) + 5 > MG_BAND_MAX) &&
            (nx > 1 || ny > 1)) {
       nx = (nx + 1) / 2;
       ny = (ny + 1) / 2;
@@ -548,6 +549,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
   if (P->prm.iters_per_launch <= 0) P->prm.iters_per_launch = P->prm.precond == MTO_PRECOND_JACOBI ? 32 : 8;
   if (P->prm.iters_per_launch % 2) P->prm.iters_per_launch += 1;  // keeps the parity of it_base even
   if (P->prm.max_restarts < 0) P->prm.max_restarts = 3;
+  if (P->prm.mg_coarse_max <= 0 || P->prm.mg_coarse_max > MG_COARSE_MAX) P->prm.mg_coarse_max = MG_COARSE_MAX;
   (void)hipGetDevice(&P->device);
   P->n_inst = n;
   auto cleanup = [&](int rc) {
