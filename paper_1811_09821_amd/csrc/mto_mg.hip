@@ -151,11 +151,13 @@ __global__ __launch_bounds__(MGB) void k_mg_rap(const MgChunk* __restrict__ chun
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[k][c] = 0.0;
   const int fxc0 = fine_of(cx, fnx), fyc0 = fine_of(cy, fny);
+#pragma unroll
   for (int oy = -1; oy <= 1; ++oy) {
     const int fy = fyc0 + oy;
     if (fy < 0 || fy > fny) continue;
     const double wy = weight1d(fy, fny, cy);
     if (wy == 0.0) continue;
+#pragma unroll
     for (int ox = -1; ox <= 1; ++ox) {
       const int fx = fxc0 + ox;
       if (fx < 0 || fx > fnx) continue;
@@ -164,6 +166,7 @@ __global__ __launch_bounds__(MGB) void k_mg_rap(const MgChunk* __restrict__ chun
       const int64_t fi = ch.fop + (int64_t)fy * (fnx + 1) + fx;
       const double wi = wx * wy;
       const double mi0 = mask[fi * 2], mi1 = mask[fi * 2 + 1];
+#pragma unroll
       for (int k = 0; k < 9; ++k) {
         const int jx = fx + k % 3 - 1, jy = fy + k / 3 - 1;
         if (jx < 0 || jx > fnx || jy < 0 || jy > fny) continue;
@@ -172,40 +175,44 @@ __global__ __launch_bounds__(MGB) void k_mg_rap(const MgChunk* __restrict__ chun
         const double* a = A + fi * 36 + k * 4;
         const double a00 = wi * mi0 * a[0] * mj0, a01 = wi * mi0 * a[1] * mj1;
         const double a10 = wi * mi1 * a[2] * mj0, a11 = wi * mi1 * a[3] * mj1;
+        // weights of fine node j in the coarse nodes around (cx, cy), per axis:
+        // its parents lie within one coarse step, so every accumulator index
+        // below is a compile-time constant (no private-memory array)
         int px0, px1, py0, py1;
         double vx0, vx1, vy0, vy1;
         parents1d(jx, fnx, px0, vx0, px1, vx1);
         parents1d(jy, fny, py0, vy0, py1, vy1);
-        for (int b = 0; b < 2; ++b) {
-          const int py = b == 0 ? py0 : py1;
-          const double vy = b == 0 ? vy0 : vy1;
-          if (py < 0) continue;
-          for (int a2 = 0; a2 < 2; ++a2) {
-            const int px = a2 == 0 ? px0 : px1;
-            const double vx = a2 == 0 ? vx0 : vx1;
-            if (px < 0) continue;
-            const int kk = (py - cy + 1) * 3 + (px - cx + 1);
-            if (kk < 0 || kk > 8) continue;  // cannot happen: parents lie within one coarse step
-            const double w = vx * vy;
-            acc[kk][0] += a00 * w;
-            acc[kk][1] += a01 * w;
-            acc[kk][2] += a10 * w;
-            acc[kk][3] += a11 * w;
-          }
+        double wxk[3], wyk[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          wxk[d] = (px0 == cx + d - 1 ? vx0 : 0.0) + (px1 == cx + d - 1 ? vx1 : 0.0);
+          wyk[d] = (py0 == cy + d - 1 ? vy0 : 0.0) + (py1 == cy + d - 1 ? vy1 : 0.0);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 9; ++kk) {
+          const double w = wyk[kk / 3] * wxk[kk % 3];
+          acc[kk][0] = fma(a00, w, acc[kk][0]);
+          acc[kk][1] = fma(a01, w, acc[kk][1]);
+          acc[kk][2] = fma(a10, w, acc[kk][2]);
+          acc[kk][3] = fma(a11, w, acc[kk][3]);
         }
       }
     }
   }
   const int64_t node = ch.op + n;
+#pragma unroll
   for (int c = 0; c < 2; ++c) {
     const bool live = acc[4][c * 2 + c] != 0.0;
     mask[node * 2 + c] = live ? 1.0 : 0.0;
     if (!live) {
+#pragma unroll
       for (int k = 0; k < 9; ++k) acc[k][c * 2] = acc[k][c * 2 + 1] = 0.0;
       acc[4][c * 2 + c] = 1.0;
     }
   }
+#pragma unroll
   for (int k = 0; k < 9; ++k)
+#pragma unroll
     for (int c = 0; c < 4; ++c) A[node * 36 + k * 4 + c] = acc[k][c];
 }
 
@@ -353,8 +360,14 @@ __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk*
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
         if (t >= nb) break;  // uniform
-        const double dj = sqrt(readlane_f64(p[0][t], t));
-        const double rj = 1.0 / dj;
+        // 1 / sqrt(d): the hardware estimate refined by two Newton steps
+        // y <- y (3/2 - d y^2 / 2), each squaring its relative error; then
+        // L_jj = d / sqrt(d).  Shorter than a rounded sqrt and a division.
+        const double d = readlane_f64(p[0][t], t), hd = 0.5 * d;
+        double rj = __builtin_amdgcn_rsq(d);
+        rj *= fma(-hd * rj, rj, 1.5);
+        rj *= fma(-hd * rj, rj, 1.5);
+        const double dj = d * rj;
         if (lane == t) rjs = rj;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -602,11 +615,13 @@ __device__ __forceinline__ void mg_restrict_node(const MgChunk& ch, int n, const
   const int cx = n % (nx + 1), cy = n / (nx + 1);
   double acc0 = 0.0, acc1 = 0.0;
   const int fxc0 = fine_of(cx, fnx), fyc0 = fine_of(cy, fny);
+#pragma unroll
   for (int oy = -1; oy <= 1; ++oy) {
     const int fy = fyc0 + oy;
     if (fy < 0 || fy > fny) continue;
     const double wy = weight1d(fy, fny, cy);
     if (wy == 0.0) continue;
+#pragma unroll
     for (int ox = -1; ox <= 1; ++ox) {
       const int fx = fxc0 + ox;
       if (fx < 0 || fx > fnx) continue;
@@ -627,51 +642,62 @@ __device__ __forceinline__ void mg_restrict_node(const MgChunk& ch, int n, const
 }
 
 // Going up: e~ = e + P~ e2_coarse, then one l1-Jacobi sweep
-// e2 = e~ + D^-1 (r - A e~).
-__device__ __forceinline__ void mg_prolong_smooth_node(const MgChunk& ch, int n, const double* __restrict__ A,
+// e2 = e~ + D^-1 (r - A e~).  Lane `sub` (< 9) of a node's 16-lane group
+// forms e~ at stencil neighbour sub and its block product; the group sums the
+// products with shuffles and the centre lane (sub 4) writes the node.
+__device__ __forceinline__ void mg_prolong_smooth_node(const MgChunk& ch, int n, int sub, bool node_ok,
+                                                       const double* __restrict__ A,
                                                        const double* __restrict__ mask,
                                                        const double* __restrict__ dinv,
                                                        const double* __restrict__ r, const double* __restrict__ e,
-                                                       double* __restrict__ e2) {
+                                                       double* __restrict__ e2, double& out0, double& out1) {
   const int nx = ch.nx, ny = ch.ny, cnx = ch.cnx;
-  const int ix = n % (nx + 1), iy = n / (nx + 1);
-  double et[9][2];
-  for (int k = 0; k < 9; ++k) {
-    const int jx = ix + k % 3 - 1, jy = iy + k / 3 - 1;
-    et[k][0] = et[k][1] = 0.0;
-    if (jx < 0 || jx > nx || jy < 0 || jy > ny) continue;
-    const int64_t jo = (int64_t)jy * (nx + 1) + jx;
-    int px0, px1, py0, py1;
-    double vx0, vx1, vy0, vy1;
-    parents1d(jx, nx, px0, vx0, px1, vx1);
-    parents1d(jy, ny, py0, vy0, py1, vy1);
-    double c0 = 0.0, c1 = 0.0;
-    for (int b = 0; b < 2; ++b) {
-      const int py = b == 0 ? py0 : py1;
-      const double vy = b == 0 ? vy0 : vy1;
-      if (py < 0) continue;
-      for (int a2 = 0; a2 < 2; ++a2) {
-        const int px = a2 == 0 ? px0 : px1;
-        const double vx = a2 == 0 ? vx0 : vx1;
-        if (px < 0) continue;
-        const int64_t cv = ch.cvec + (int64_t)py * (cnx + 1) + px;
-        c0 += vx * vy * e2[cv * 2];
-        c1 += vx * vy * e2[cv * 2 + 1];
+  double et0 = 0.0, et1 = 0.0, c0 = 0.0, c1 = 0.0;
+  if (node_ok && sub < 9) {
+    const int ix = n % (nx + 1), iy = n / (nx + 1);
+    const int jx = ix + sub % 3 - 1, jy = iy + sub / 3 - 1;
+    if (jx >= 0 && jx <= nx && jy >= 0 && jy <= ny) {
+      const int64_t jo = (int64_t)jy * (nx + 1) + jx;
+      int px0, px1, py0, py1;
+      double vx0, vx1, vy0, vy1;
+      parents1d(jx, nx, px0, vx0, px1, vx1);
+      parents1d(jy, ny, py0, vy0, py1, vy1);
+      double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int py = b == 0 ? py0 : py1;
+        const double vy = b == 0 ? vy0 : vy1;
+        if (py < 0) continue;
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2) {
+          const int px = a2 == 0 ? px0 : px1;
+          const double vx = a2 == 0 ? vx0 : vx1;
+          if (px < 0) continue;
+          const int64_t cv = ch.cvec + (int64_t)py * (cnx + 1) + px;
+          p0 += vx * vy * e2[cv * 2];
+          p1 += vx * vy * e2[cv * 2 + 1];
+        }
       }
+      const int64_t jn = ch.op + jo, jv = ch.vec + jo;
+      et0 = e[jv * 2] + mask[jn * 2] * p0;
+      et1 = e[jv * 2 + 1] + mask[jn * 2 + 1] * p1;
+      const double* a = A + (ch.op + n) * 36 + sub * 4;
+      c0 = a[0] * et0 + a[1] * et1;
+      c1 = a[2] * et0 + a[3] * et1;
     }
-    const int64_t jn = ch.op + jo, jv = ch.vec + jo;
-    et[k][0] = e[jv * 2] + mask[jn * 2] * c0;
-    et[k][1] = e[jv * 2 + 1] + mask[jn * 2 + 1] * c1;
   }
-  const int64_t node = ch.op + n, v = ch.vec + n;
-  double t0 = r[v * 2], t1 = r[v * 2 + 1];
-  for (int k = 0; k < 9; ++k) {
-    const double* a = A + node * 36 + k * 4;
-    t0 -= a[0] * et[k][0] + a[1] * et[k][1];
-    t1 -= a[2] * et[k][0] + a[3] * et[k][1];
+  for (int o = 8; o > 0; o >>= 1) {
+    c0 += __shfl_xor(c0, o, 16);
+    c1 += __shfl_xor(c1, o, 16);
   }
-  e2[v * 2] = et[4][0] + dinv[node * 2] * t0;
-  e2[v * 2 + 1] = et[4][1] + dinv[node * 2 + 1] * t1;
+  out0 = out1 = 0.0;
+  if (node_ok && sub == 4) {
+    const int64_t node = ch.op + n, v = ch.vec + n;
+    out0 = et0 + dinv[node * 2] * (r[v * 2] - c0);
+    out1 = et1 + dinv[node * 2 + 1] * (r[v * 2 + 1] - c1);
+    e2[v * 2] = out0;
+    e2[v * 2 + 1] = out1;
+  }
 }
 
 __global__ __launch_bounds__(MGB) void k_mg_resid(const MgChunk* __restrict__ chunks, PcgDev s,
@@ -770,24 +796,26 @@ __global__ __launch_bounds__(256) void k_mg_coarse_solve(const MgChunk* __restri
 }
 
 // vfree != NULL (level 1): also z += e2 at the node's free vertex DOFs
-// (the injection back to the hierarchic level).
-__global__ __launch_bounds__(MGB) void k_mg_prolong_smooth(const MgChunk* __restrict__ chunks, PcgDev s,
+// (the injection back to the hierarchic level).  MG_RR_NODES nodes per
+// 256-thread block, 16 lanes each.
+__global__ __launch_bounds__(256) void k_mg_prolong_smooth(const MgChunk* __restrict__ chunks, PcgDev s,
                                                            const double* __restrict__ A,
                                                            const double* __restrict__ mask,
                                                            const double* __restrict__ dinv,
                                                            const double* __restrict__ r, const double* __restrict__ e,
                                                            double* __restrict__ e2, const int32_t* __restrict__ vfree) {
   const MgChunk ch = chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;
-  const int n = ch.node_begin + threadIdx.x;
-  if (n >= ch.node_end) return;
-  mg_prolong_smooth_node(ch, n, A, mask, dinv, r, e, e2);
-  if (vfree) {
-    const int64_t node = ch.op + n, v = ch.vec + n;
-    for (int c = 0; c < 2; ++c) {
-      const int f = vfree[node * 2 + c];
-      if (f >= 0) s.z[ch.dof_off + f] += e2[v * 2 + c];
-    }
+  if (!sys_running(s, ch.sys)) return;  // whole block
+  const int sub = threadIdx.x & 15;
+  const int n = ch.node_begin + blockIdx.y * MG_RR_NODES + (threadIdx.x >> 4);
+  const bool node_ok = n < ch.node_end;
+  double o0, o1;
+  mg_prolong_smooth_node(ch, n, sub, node_ok, A, mask, dinv, r, e, e2, o0, o1);
+  if (vfree && node_ok && sub == 4) {
+    const int64_t node = ch.op + n;
+    const int f0 = vfree[node * 2], f1 = vfree[node * 2 + 1];
+    if (f0 >= 0) s.z[ch.dof_off + f0] += o0;
+    if (f1 >= 0) s.z[ch.dof_off + f1] += o1;
   }
 }
 
@@ -1107,7 +1135,9 @@ void launch_mg_coarse_solve(const MgChunk* ch, int n, int nmax, const PcgDev& s,
 void launch_mg_prolong_smooth(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
                               const double* dinv, const double* r, const double* e, double* e2, const int32_t* vfree,
                               hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(n), dim3(MGB), 0, st, ch, s, A, mask, dinv, r, e, e2, vfree);
+  if (n)
+    hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(n, MG_CHUNK / MG_RR_NODES), dim3(256), 0, st, ch, s, A, mask, dinv, r,
+                       e, e2, vfree);
 }
 void launch_mg_prolong0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* e2,
                         hipStream_t st) {
