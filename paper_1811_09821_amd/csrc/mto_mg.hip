@@ -267,7 +267,7 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 //   Window: rows J .. J + b + NB - 1 in a ring of R = b + NB slots (row i in
 //   slot i % R), slot row t holding entry (i, i - t).
 //   Step J: wave 0 factors the panel (columns J .. J + NB - 1 of its R rows,
-//   two rows per lane, in registers; diagonal and column entries broadcast
+//   one or two rows per lane, in registers; diagonal and column entries broadcast
 //   with lane reads) and leaves it, with the reciprocal diagonal, in LDS.
 //   After a barrier the rank-NB update of the trailing b x b triangle runs
 //   on the matrix cores: 16 x 16 tiles of it, one per wave (at most 15), each
@@ -299,6 +299,9 @@ size_t chol_lds_bytes(int b) {
 
 typedef double chol_d4 __attribute__((ext_vector_type(4)));
 
+// Q panel rows per lane of wave 0: 1 when the panel (chol_panel_rows) fits in
+// 64 rows, else 2.
+template <int Q>
 __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk* __restrict__ chunks,
                                                                  const double* __restrict__ A,
                                                                  double* __restrict__ band) {
@@ -346,9 +349,9 @@ __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk*
       if (r < n && r - t >= 0) pre = band_entry(ch, A, r, r - t);
     }
     if (wave == 0) {
-      double p[2][NB];
+      double p[Q][NB];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < Q; ++q) {
         const int r = lane + 64 * q, i = J + r;
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
@@ -369,23 +372,20 @@ __global__ __launch_bounds__(MG_CHOL_BLOCK) void k_mg_coarse_chol(const MgChunk*
         rj *= fma(-hd * rj, rj, 1.5);
         const double dj = d * rj;
         if (lane == t) rjs = rj;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int r = lane + 64 * q;
-          p[q][t] = r > t ? p[q][t] * rj : (r == t ? dj : 0.0);
-        }
+        // rows above the diagonal are zeroed here (rows 64.. are all below)
+        p[0][t] = lane > t ? p[0][t] * rj : (lane == t ? dj : 0.0);
+        if (Q == 2) p[Q - 1][t] *= rj;
+        // Unpredicated: a row r < t2 takes garbage in its (upper) column t2,
+        // which the scaling of column t2 zeroes before anything reads it.
 #pragma unroll
         for (int t2 = t + 1; t2 < NB; ++t2) {
           const double v = readlane_f64(p[0][t], t2);  // L[J + t2][J + t]
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const int r = lane + 64 * q;
-            if (r >= t2) p[q][t2] = fma(-p[q][t], v, p[q][t2]);
-          }
+          for (int q = 0; q < Q; ++q) p[q][t2] = fma(-p[q][t], v, p[q][t2]);
         }
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < Q; ++q) {
         const int r = lane + 64 * q;
         if (r < RP) {
 #pragma unroll
@@ -1104,7 +1104,10 @@ void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_
 void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* scr,
                             double* dense, hipStream_t st) {
   if (!n) return;
-  hipLaunchKernelGGL(k_mg_coarse_chol, dim3(n), dim3(MG_CHOL_BLOCK), chol_lds_bytes(bmax), st, ch, A, band);
+  if (chol_panel_rows(bmax) <= 64)
+    hipLaunchKernelGGL(k_mg_coarse_chol<1>, dim3(n), dim3(MG_CHOL_BLOCK), chol_lds_bytes(bmax), st, ch, A, band);
+  else
+    hipLaunchKernelGGL(k_mg_coarse_chol<2>, dim3(n), dim3(MG_CHOL_BLOCK), chol_lds_bytes(bmax), st, ch, A, band);
   hipLaunchKernelGGL(k_mg_coarse_inv, dim3((nmax + MG_INV_WAVES - 1) / MG_INV_WAVES, n), dim3(64 * MG_INV_WAVES),
                      (size_t)MG_INV_WAVES * nmax * 8, st, ch, band, scr, nmax);
   const int64_t nn = (int64_t)nmax * nmax;

@@ -187,6 +187,26 @@ def test_schwarz_multigrid_cuts_iterations(cuda):
     assert abs(cs.item() - cj.item()) <= 1e-9 * abs(cj.item())
 
 
+@pytest.mark.parametrize("coarse_max", [0, 200])
+def test_widest_coarse_band_and_deeper_hierarchy(cuda, coarse_max):
+    """A 74 x 74 mesh coarsens to a 37 x 37 grid whose band width, 79, is the
+    widest the coarsest-level Cholesky takes (its LDS window then exceeds
+    64 KB); with mg_coarse_max = 200 the hierarchy coarsens three levels
+    further.  Both Schwarz-multigrid solves match the Jacobi-preconditioned
+    solve of the same system."""
+    m = mto()
+    pr = P.uniform_random(74, 74, 1, 1, seed=31)
+    rho = torch.tensor(pr.rho, device=cuda)
+    uj, cj, gj, sj = m.Plan(pr, precond=m.PRECOND_JACOBI).solve(rho)
+    us, cs, gs, ss = m.Plan(pr, precond=m.PRECOND_MG_ASM, mg_coarse_max=coarse_max).solve(rho)
+    print(f"\niterations: Jacobi {sj['iterations']}, Schwarz multigrid {ss['iterations']}", flush=True)
+    assert ss["status"] == 0 and sj["status"] == 0
+    assert max(ss["iterations"]) < max(sj["iterations"])
+    assert rel(us.cpu().numpy(), uj.cpu().numpy()) < 1e-9
+    assert abs(cs.item() - cj.item()) <= 1e-9 * abs(cj.item())
+    assert rel(gs.cpu().numpy(), gj.cpu().numpy()) < 1e-8
+
+
 def test_solve_parity_plain_path(cuda):
     prs = [P.small_mixed(12, 6, seed=6, n_loads=2)]
     plan = mto().Plan(prs, kernel_path=1)
