@@ -912,15 +912,22 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
   __shared__ double sc[NE];
   __shared__ int gid[NE];
   __shared__ int pos[NEMAX];
+  __shared__ double Es[MTO_MAX_D * MTO_MAX_D];  // moduli of the element's (or a neighbour's) cells
   const GroupDev g = groups[gi];
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
   for (int a = tid; a < NE; a += ASM_BLOCK) gid[a] = g.gidx[a * g.npad + k];
   const int cell = g.cell[k];
+  for (int c = tid; c < g.S; c += ASM_BLOCK) Es[c] = E[cell + c];
+  __syncthreads();
+  // K_e = sum over cells of E_s K_s; the cell loop is unrolled so its table
+  // loads are in flight together (same summation order)
   for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
     const int a = idx / NE, b = idx - a * NE;
+    const double* __restrict__ kab = g.ks + (int64_t)a * NE + b;
     double v = 0.0;
-    for (int sc_ = 0; sc_ < g.S; ++sc_) v = fma(E[cell + sc_], g.ks[((int64_t)sc_ * NE + a) * NE + b], v);
+#pragma unroll 16
+    for (int sc_ = 0; sc_ < g.S; ++sc_) v = fma(Es[sc_], kab[(int64_t)sc_ * NE * NE], v);
     A[a][b] = v;
   }
   __syncthreads();
@@ -942,14 +949,17 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
           }
       pos[b] = ps;
     }
-    __syncthreads();
     const int celln = gn.cell[kn];
+    for (int c = tid; c < gn.S; c += ASM_BLOCK) Es[c] = E[celln + c];
+    __syncthreads();
     for (int idx = tid; idx < nen * nen; idx += ASM_BLOCK) {
       const int a = idx / nen, b = idx - a * nen;
       const int pa = pos[a], pb = pos[b];
       if (pa < 0 || pb < 0) continue;
+      const double* __restrict__ kab = gn.ks + (int64_t)a * nen + b;
       double v = 0.0;
-      for (int sc_ = 0; sc_ < gn.S; ++sc_) v = fma(E[celln + sc_], gn.ks[((int64_t)sc_ * nen + a) * nen + b], v);
+#pragma unroll 16
+      for (int sc_ = 0; sc_ < gn.S; ++sc_) v = fma(Es[sc_], kab[(int64_t)sc_ * nen * nen], v);
       A[pa][pb] += v;  // (a, b) -> (pa, pb) is one-to-one within a neighbour
     }
     __syncthreads();
