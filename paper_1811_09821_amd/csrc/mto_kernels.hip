@@ -42,8 +42,20 @@ constexpr int VWAVES = VBLOCK / 64;
 // calls it on the same range.
 __device__ __forceinline__ double wave_sum(const double* __restrict__ arr, int a, int b) {
   const int lane = threadIdx.x & 63;
+  // four loads per lane are requested before any is added (a quarter of the
+  // memory round trips); each lane still adds its terms in index order, an
+  // absent term as +0.0, so the sum is the same as term by term
   double v = 0.0;
-  for (int k = a + lane; k < b; k += 64) v += arr[k];
+  for (int k = a + lane; k < b; k += 256) {
+    const double x0 = arr[k];
+    const double x1 = k + 64 < b ? arr[k + 64] : 0.0;
+    const double x2 = k + 128 < b ? arr[k + 128] : 0.0;
+    const double x3 = k + 192 < b ? arr[k + 192] : 0.0;
+    v += x0;
+    v += x1;
+    v += x2;
+    v += x3;
+  }
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
   return v;
 }
@@ -581,10 +593,10 @@ __global__ __launch_bounds__(VBLOCK) void k_dof1(PcgDev s, int it_k) {
   const int64_t o = ch.dof_off;
   double qi = 0.0, po = 0.0, zi = 0.0, kd = 0.0;
   if (in) {
-    qi = slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
     po = s.p[o + i];
     zi = s.z[o + i];
     if (s.kspr) kd = s.kspr[ch.inst_free_off + i];  // ground springs: q += k p
+    qi = slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
   }
   const int it = *s.it_base + it_k;
   if (threadIdx.x < 64) {

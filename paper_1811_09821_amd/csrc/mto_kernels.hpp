@@ -73,9 +73,14 @@ __device__ __forceinline__ double slot_sum(const double* __restrict__ sl, int i,
   int64_t base;
   int cnt;
   slot_range(i, nfv, nfe, base, cnt);
-  double q = sl[base];
-  for (int k = 1; k < cnt; ++k) q += sl[base + k];
-  return q;
+  // every slot is requested before any is added (one memory round trip, not
+  // one per slot); the sum keeps the order ((q0 + q1) + q2) + q3
+  const double q0 = sl[base];
+  const double q1 = cnt > 1 ? sl[base + 1] : 0.0;
+  const double q2 = cnt > 2 ? sl[base + 2] : 0.0;
+  const double q3 = cnt > 3 ? sl[base + 3] : 0.0;
+  const double q01 = q0 + q1;
+  return cnt == 1 ? q0 : (cnt == 2 ? q01 : (q01 + q2) + q3);
 }
 
 // Iteration state shared by the PCG kernels.
@@ -211,8 +216,9 @@ void launch_mg_post0(const PcgDev& s, int it_k, int init, hipStream_t st);
 // ---- element-block additive Schwarz smoother (mto_mg.hip) ----
 // Per element column of group `gi`: the assembled operator restricted to the
 // element's free DOFs (own sum_s E_s K_s plus the shared-DOF entries of the
-// eight neighbours), inverted; binv [ne][ne][npad], zero rows/columns at
-// absent or supported DOFs.  groups: device array of all group views;
+// eight neighbours), inverted; binv holds its upper triangle packed by rows,
+// tile-major: [npad / 16][ne (ne + 1) / 2][16] (16 consecutive element
+// columns entry by entry), zero rows/columns at absent or supported DOFs.  groups: device array of all group views;
 // nbr [8][npad]: global element index of each neighbour (-1: none);
 // el_group / el_col: group and column of every global element.
 void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const int32_t* nbr, const int32_t* el_group,

@@ -1001,7 +1001,8 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
     if (b < a) continue;
     double v = 0.5 * (A[a][b] + A[b][a]) * sc[a] * sc[b];
     if (gid[a] < 0 || gid[b] < 0) v = 0.0;
-    binv[(int64_t)packed_index<NE>(a, b) * g.npad + k] = v;
+    // tile-major: 16 consecutive elements' packed triangles, entry by entry
+    binv[((int64_t)(k >> 4) * (NE * (NE + 1) / 2) + packed_index<NE>(a, b)) * 16 + (k & 15)] = v;
   }
 }
 
@@ -1028,13 +1029,13 @@ __global__ __launch_bounds__(16 * asm_rows<P>()) void k_asm_apply(GroupDev g, co
   const bool valid = c0 + c < t.count;
   const int col = t.elem_begin + c0 + (valid ? c : 0);
   const int64_t np = g.npad;
-  const double* __restrict__ bp = binv + col;
+  // the 16 elements of this block (tile-major storage) read one contiguous run
+  const double* __restrict__ bp = binv + (int64_t)(col >> 4) * (NE * (NE + 1) / 2) * 16 + (col & 15);
   // the first H entries of the row are requested before the gather, the rest
   // (p = 4 only, to stay within the registers of 13 waves) after it
   constexpr int H = NE <= 32 ? NE : NE / 2;
-  const int np32 = (int)np;  // (ne (ne + 1) / 2) * npad < 2^31 (checked at plan time)
   auto entry = [&](int b) -> double {
-    return a < NE ? bp[(b < a ? packed_index<NE>(b, a) : packed_index<NE>(a, b)) * np32] : 0.0;
+    return a < NE ? bp[(b < a ? packed_index<NE>(b, a) : packed_index<NE>(a, b)) * 16] : 0.0;
   };
   double brow[H];
 #pragma unroll

@@ -71,7 +71,7 @@ struct GroupHost {
   double flops = 0.0;  // 2 S ne^2 per element column
   std::vector<double> kv;  // host copy of the vertex-block table
   int kv_off = 0;
-  // element-block Schwarz smoother: packed inverses [ne (ne+1)/2][npad], neighbours [8][npad]
+  // element-block Schwarz smoother: packed inverses [npad/16][ne (ne+1)/2][16], neighbours [8][npad]
   double* binv = nullptr;
   int32_t* nbr = nullptr;
   // QR-error indicator (built at its first use): instance and element of every column,
