@@ -662,20 +662,31 @@ __device__ __forceinline__ void mg_prolong_smooth_node(const MgChunk& ch, int n,
       double vx0, vx1, vy0, vy1;
       parents1d(jx, nx, px0, vx0, px1, vx1);
       parents1d(jy, ny, py0, vy0, py1, vy1);
+      // the four parents' loads are issued together: a missing second
+      // parent (index -1, weight 0) reads the first one and adds 0
       double p0 = 0.0, p1 = 0.0;
+      double c2[2][2][2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2) {
+          const int py = b == 0 || py1 < 0 ? py0 : py1;
+          const int px = a2 == 0 || px1 < 0 ? px0 : px1;
+          const int64_t cv = ch.cvec + (int64_t)py * (cnx + 1) + px;
+          c2[b][a2][0] = e2[cv * 2];
+          c2[b][a2][1] = e2[cv * 2 + 1];
+        }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int py = b == 0 ? py0 : py1;
         const double vy = b == 0 ? vy0 : vy1;
-        if (py < 0) continue;
 #pragma unroll
         for (int a2 = 0; a2 < 2; ++a2) {
           const int px = a2 == 0 ? px0 : px1;
           const double vx = a2 == 0 ? vx0 : vx1;
-          if (px < 0) continue;
-          const int64_t cv = ch.cvec + (int64_t)py * (cnx + 1) + px;
-          p0 += vx * vy * e2[cv * 2];
-          p1 += vx * vy * e2[cv * 2 + 1];
+          const double wv = (py >= 0 && px >= 0) ? vx * vy : 0.0;  // a missing parent adds 0
+          p0 += wv * c2[b][a2][0];
+          p1 += wv * c2[b][a2][1];
         }
       }
       const int64_t jn = ch.op + jo, jv = ch.vec + jo;
@@ -750,14 +761,23 @@ __global__ __launch_bounds__(256) void k_mg_resid_restrict(const MgChunk* __rest
         const int64_t fo = (int64_t)fy * (fnx + 1) + fx;
         const int64_t fnode = ch.fop + fo, fv = ch.fvec + fo;
         double t0 = r[fv * 2], t1 = r[fv * 2 + 1];
+        // all nine neighbours' loads are issued together (a neighbour off the
+        // grid reads a clamped one and counts as 0), then used in order
+        double ej[9][2];
+#pragma unroll
         for (int k = 0; k < 9; ++k) {
           const int jx = fx + k % 3 - 1, jy = fy + k / 3 - 1;
-          if (jx < 0 || jx > fnx || jy < 0 || jy > fny) continue;
-          const int64_t jv = ch.fvec + (int64_t)jy * (fnx + 1) + jx;
+          const bool in = jx >= 0 && jx <= fnx && jy >= 0 && jy <= fny;
+          const int64_t jv = ch.fvec + (int64_t)min(max(jy, 0), fny) * (fnx + 1) + min(max(jx, 0), fnx);
+          const double v0 = e[jv * 2], v1 = e[jv * 2 + 1];
+          ej[k][0] = in ? v0 : 0.0;
+          ej[k][1] = in ? v1 : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
           const double* a = A + fnode * 36 + k * 4;
-          const double ej0 = e[jv * 2], ej1 = e[jv * 2 + 1];
-          t0 -= a[0] * ej0 + a[1] * ej1;
-          t1 -= a[2] * ej0 + a[3] * ej1;
+          t0 -= a[0] * ej[k][0] + a[1] * ej[k][1];
+          t1 -= a[2] * ej[k][0] + a[3] * ej[k][1];
         }
         acc0 = w * mask[fnode * 2] * t0;
         acc1 = w * mask[fnode * 2 + 1] * t1;
@@ -789,8 +809,21 @@ __global__ __launch_bounds__(256) void k_mg_coarse_solve(const MgChunk* __restri
   if (i >= n) return;  // whole wave
   const double* __restrict__ X = dense + ch.dense_off + (int64_t)i * n;
   const double* __restrict__ rv = r + ch.vec * 2;
+  // eight terms per lane are requested before any is added (an eighth of the
+  // memory round trips); each lane adds its terms in index order, an absent
+  // one as 0 * 0, so the sum is the same as term by term
   double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc = fma(X[j], rv[j], acc);
+  for (int j = lane; j < n; j += 512) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = j + 64 * u < n;
+      x[u] = in ? X[j + 64 * u] : 0.0;
+      y[u] = in ? rv[j + 64 * u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(x[u], y[u], acc);
+  }
   for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
   if (lane == 0) e2[ch.vec * 2 + i] = acc;
 }
