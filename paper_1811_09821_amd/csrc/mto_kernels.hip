@@ -47,17 +47,53 @@ __device__ __forceinline__ double wave_sum(const double* __restrict__ arr, int a
   // absent term as +0.0, so the sum is the same as term by term
   double v = 0.0;
   for (int k = a + lane; k < b; k += 256) {
-    const double x0 = arr[k];
-    const double x1 = k + 64 < b ? arr[k + 64] : 0.0;
-    const double x2 = k + 128 < b ? arr[k + 128] : 0.0;
-    const double x3 = k + 192 < b ? arr[k + 192] : 0.0;
-    v += x0;
-    v += x1;
-    v += x2;
-    v += x3;
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // unconditional (clamped) loads, absent terms zeroed after
+      const double t = arr[min(k + 64 * u, b - 1)];
+      x[u] = k + 64 * u < b ? t : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v += x[u];
   }
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
   return v;
+}
+
+// Three wave_sum reductions over the same chunk range in one pass: each
+// array's terms are added in wave_sum's order, so the results are identical
+// to three calls, at one memory round trip instead of three.
+__device__ __forceinline__ void wave_sum3(const double* __restrict__ x, const double* __restrict__ y,
+                                          const double* __restrict__ z, int a, int b, double& sx, double& sy,
+                                          double& sz) {
+  const int lane = threadIdx.x & 63;
+  double vx = 0.0, vy = 0.0, vz = 0.0;
+  for (int k = a + lane; k < b; k += 256) {
+    double tx[4], ty[4], tz[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // unconditional (clamped) loads, absent terms zeroed after
+      const int kk = min(k + 64 * u, b - 1);
+      const bool in = k + 64 * u < b;
+      const double a0 = x[kk], a1 = y[kk], a2 = z[kk];
+      tx[u] = in ? a0 : 0.0;
+      ty[u] = in ? a1 : 0.0;
+      tz[u] = in ? a2 : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      vx += tx[u];
+      vy += ty[u];
+      vz += tz[u];
+    }
+  }
+  for (int m = 32; m >= 1; m >>= 1) {
+    vx += __shfl_xor(vx, m);
+    vy += __shfl_xor(vy, m);
+    vz += __shfl_xor(vz, m);
+  }
+  sx = vx;
+  sy = vy;
+  sz = vz;
 }
 
 // Deterministic block sum (NW waves), valid in thread 0.
@@ -87,11 +123,12 @@ __device__ __forceinline__ Scal pcg_state(const PcgDev& s, int sys, int pc_begin
   const int pi = it & 1;
   const int st = s.status[sys];
   const double tol2 = s.tol2[sys];
-  const double rr = wave_sum(s.part_rr + pi * s.n_chunks, pc_begin, pc_end);
-  double rz_new = 0.0, rz_old = 1.0;
+  double rr, rz_new = 0.0, rz_old = 1.0;
   if (want_beta && it > 0) {
-    rz_new = wave_sum(s.part_rz + pi * s.n_chunks, pc_begin, pc_end);
-    rz_old = wave_sum(s.part_rz + (pi ^ 1) * s.n_chunks, pc_begin, pc_end);
+    wave_sum3(s.part_rr + pi * s.n_chunks, s.part_rz + pi * s.n_chunks, s.part_rz + (pi ^ 1) * s.n_chunks,
+              pc_begin, pc_end, rr, rz_new, rz_old);
+  } else {
+    rr = wave_sum(s.part_rr + pi * s.n_chunks, pc_begin, pc_end);
   }
   Scal o;
   o.active = (st == SYS_RUNNING) && !(rr <= tol2);
@@ -591,14 +628,16 @@ __global__ __launch_bounds__(VBLOCK) void k_dof1(PcgDev s, int it_k) {
   const int i = ch.begin + threadIdx.x;
   const bool in = i < ch.end;
   const int64_t o = ch.dof_off;
-  double qi = 0.0, po = 0.0, zi = 0.0, kd = 0.0;
-  if (in) {
-    po = s.p[o + i];
-    zi = s.z[o + i];
-    if (s.kspr) kd = s.kspr[ch.inst_free_off + i];  // ground springs: q += k p
-    qi = slot_sum(s.slots + ch.slot_off, i, ch.nfv, ch.nfe);
-  }
+  // the iteration counter first: the scalar sums' addresses depend on it, and
+  // the memory counter retires in order
   const int it = *s.it_base + it_k;
+  // loads at a clamped index, unconditional (a lane past the chunk's end
+  // rereads its last DOF and stores nothing)
+  const int ic = in ? i : ch.end - 1;
+  double qi = 0.0, kd = 0.0;
+  const double po = s.p[o + ic], zi = s.z[o + ic];
+  if (s.kspr) kd = s.kspr[ch.inst_free_off + ic];  // ground springs: q += k p
+  const SlotVals sv = slot_fetch(s.slots + ch.slot_off, ic, ch.nfv, ch.nfe);
   if (threadIdx.x < 64) {
     const Scal sc = pcg_state(s, ch.sys, ch.pc_begin, ch.pc_end, it, true);
     if (threadIdx.x == 0) {
@@ -607,6 +646,7 @@ __global__ __launch_bounds__(VBLOCK) void k_dof1(PcgDev s, int it_k) {
     }
   }
   __syncthreads();
+  qi = slot_add(sv);  // added after the scalar loads were issued
   Scal sc;
   sc.beta = lds[VWAVES];
   sc.active = lds[VWAVES + 1] != 0.0;
@@ -633,24 +673,23 @@ __global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
   const int i = ch.begin + threadIdx.x;
   const bool in = i < ch.end;
   const int64_t o = ch.dof_off;
-  double xi = 0.0, pi_ = 0.0, qi = 0.0, ri = 0.0, di = 0.0;
-  if (in) {
-    xi = s.x[o + i];
-    pi_ = s.p[o + i];
-    qi = s.q[o + i];
-    ri = s.r[o + i];
-    di = s.dinv[ch.inst_free_off + i];
-  }
-  const int it = *s.it_base + it_k;
+  const int it = *s.it_base + it_k;  // first: the scalar sums' addresses depend on it
   const int par = it & 1;
+  // loads at a clamped index, unconditional (a lane past the chunk's end
+  // rereads its last DOF and stores nothing)
+  const int ic = in ? i : ch.end - 1;
+  const double xi = s.x[o + ic], pi_ = s.p[o + ic], qi = s.q[o + ic], ri = s.r[o + ic];
+  const double di = s.dinv[ch.inst_free_off + ic];
   if (threadIdx.x < 64) {
-    const Scal sc = pcg_state(s, ch.sys, ch.pc_begin, ch.pc_end, it, false);
-    const double rz = wave_sum(s.part_rz + par * s.n_chunks, ch.pc_begin, ch.pc_end);
-    const double pq = wave_sum(s.part_pq, ch.pc_begin, ch.pc_end);
+    // r.r (convergence), r.z and p.q of this system in one pass
+    double rr, rz, pq;
+    wave_sum3(s.part_rr + par * s.n_chunks, s.part_rz + par * s.n_chunks, s.part_pq, ch.pc_begin, ch.pc_end, rr, rz,
+              pq);
+    const bool active = s.status[ch.sys] == SYS_RUNNING && !(rr <= s.tol2[ch.sys]);
     if (threadIdx.x == 0) {
       lds[VWAVES] = rz;
       lds[VWAVES + 1] = pq;
-      lds[VWAVES + 2] = sc.active ? 1.0 : 0.0;
+      lds[VWAVES + 2] = active ? 1.0 : 0.0;
     }
   }
   __syncthreads();

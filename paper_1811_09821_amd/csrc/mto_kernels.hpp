@@ -69,18 +69,32 @@ __device__ __forceinline__ void slot_range(int i, int nfv, int nfe, int64_t& bas
 }
 
 // Assembled value of DOF i: its slots summed in a fixed order.
-__device__ __forceinline__ double slot_sum(const double* __restrict__ sl, int i, int nfv, int nfe) {
-  int64_t base;
+// Its slots are requested together (one memory round trip, not one per
+// slot) by slot_fetch and added by slot_add in the order ((q0 + q1) + q2) + q3;
+// a caller can put other loads between the two.
+struct SlotVals {
+  double q[4];
   int cnt;
-  slot_range(i, nfv, nfe, base, cnt);
-  // every slot is requested before any is added (one memory round trip, not
-  // one per slot); the sum keeps the order ((q0 + q1) + q2) + q3
-  const double q0 = sl[base];
-  const double q1 = cnt > 1 ? sl[base + 1] : 0.0;
-  const double q2 = cnt > 2 ? sl[base + 2] : 0.0;
-  const double q3 = cnt > 3 ? sl[base + 3] : 0.0;
-  const double q01 = q0 + q1;
-  return cnt == 1 ? q0 : (cnt == 2 ? q01 : (q01 + q2) + q3);
+};
+__device__ __forceinline__ SlotVals slot_fetch(const double* __restrict__ sl, int i, int nfv, int nfe) {
+  int64_t base;
+  SlotVals v;
+  slot_range(i, nfv, nfe, base, v.cnt);
+  // unconditional loads (a slot past the DOF's count rereads its last one),
+  // so no join waits for them; the unused values are zeroed after
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double x = sl[base + (k < v.cnt ? k : v.cnt - 1)];
+    v.q[k] = k < v.cnt ? x : 0.0;
+  }
+  return v;
+}
+__device__ __forceinline__ double slot_add(const SlotVals& v) {
+  const double q01 = v.q[0] + v.q[1];
+  return v.cnt == 1 ? v.q[0] : (v.cnt == 2 ? q01 : (q01 + v.q[2]) + v.q[3]);
+}
+__device__ __forceinline__ double slot_sum(const double* __restrict__ sl, int i, int nfv, int nfe) {
+  return slot_add(slot_fetch(sl, i, nfv, nfe));
 }
 
 // Iteration state shared by the PCG kernels.

@@ -816,10 +816,12 @@ __global__ __launch_bounds__(256) void k_mg_coarse_solve(const MgChunk* __restri
   for (int j = lane; j < n; j += 512) {
     double x[8], y[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 8; ++u) {  // unconditional (clamped) loads, absent terms zeroed after
+      const int jj = min(j + 64 * u, n - 1);
       const bool in = j + 64 * u < n;
-      x[u] = in ? X[j + 64 * u] : 0.0;
-      y[u] = in ? rv[j + 64 * u] : 0.0;
+      const double a0 = X[jj], a1 = rv[jj];
+      x[u] = in ? a0 : 0.0;
+      y[u] = in ? a1 : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc = fma(x[u], y[u], acc);
