@@ -209,11 +209,6 @@ void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const 
                             double* dense, hipStream_t st);
 void launch_mg_restrict0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* dinv,
                          double* r1, double* e1, hipStream_t st);
-// t = r - A e on a level (l >= 1); then r_{l+1} = P~^T t, e_{l+1} = D^-1 r_{l+1}
-void launch_mg_resid(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* r, const double* e,
-                     double* t, hipStream_t st);
-void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* mask, const double* dinv,
-                        const double* t, double* r, double* e, hipStream_t st);
 // levels l-1 -> l of the V-cycle in one launch (ch: the level-l system chunks)
 void launch_mg_resid_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
                               const double* dinv, double* r, double* e, hipStream_t st);

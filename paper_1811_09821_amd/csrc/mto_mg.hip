@@ -582,64 +582,7 @@ __global__ __launch_bounds__(MGB) void k_mg_restrict0(const MgChunk* __restrict_
   }
 }
 
-// ---- per-node steps of levels >= 1 (shared by the one-level kernels and
-// the fused coarse cycle) ----
-
-// Residual of a level after its pre-smoothing: t = r - A e.
-__device__ __forceinline__ void mg_resid_node(const MgChunk& ch, int n, const double* __restrict__ A,
-                                              const double* __restrict__ r, const double* __restrict__ e,
-                                              double* __restrict__ t) {
-  const int nx = ch.nx, ny = ch.ny;
-  const int ix = n % (nx + 1), iy = n / (nx + 1);
-  const int64_t node = ch.op + n, v = ch.vec + n;
-  double t0 = r[v * 2], t1 = r[v * 2 + 1];
-  for (int k = 0; k < 9; ++k) {
-    const int jx = ix + k % 3 - 1, jy = iy + k / 3 - 1;
-    if (jx < 0 || jx > nx || jy < 0 || jy > ny) continue;
-    const int64_t jv = ch.vec + (int64_t)jy * (nx + 1) + jx;
-    const double* a = A + node * 36 + k * 4;
-    const double ej0 = e[jv * 2], ej1 = e[jv * 2 + 1];
-    t0 -= a[0] * ej0 + a[1] * ej1;
-    t1 -= a[2] * ej0 + a[3] * ej1;
-  }
-  t[v * 2] = t0;
-  t[v * 2 + 1] = t1;
-}
-
-// Restriction to this level: r = P~^T t of the finer level's residual, and
-// the pre-smoothing from zero e = D^-1 r.
-__device__ __forceinline__ void mg_restrict_node(const MgChunk& ch, int n, const double* __restrict__ mask,
-                                                 const double* __restrict__ dinv, const double* __restrict__ t,
-                                                 double* __restrict__ r, double* __restrict__ e) {
-  const int nx = ch.nx, fnx = ch.fnx, fny = ch.fny;
-  const int cx = n % (nx + 1), cy = n / (nx + 1);
-  double acc0 = 0.0, acc1 = 0.0;
-  const int fxc0 = fine_of(cx, fnx), fyc0 = fine_of(cy, fny);
-#pragma unroll
-  for (int oy = -1; oy <= 1; ++oy) {
-    const int fy = fyc0 + oy;
-    if (fy < 0 || fy > fny) continue;
-    const double wy = weight1d(fy, fny, cy);
-    if (wy == 0.0) continue;
-#pragma unroll
-    for (int ox = -1; ox <= 1; ++ox) {
-      const int fx = fxc0 + ox;
-      if (fx < 0 || fx > fnx) continue;
-      const double wx = weight1d(fx, fnx, cx);
-      if (wx == 0.0) continue;
-      const int64_t fo = (int64_t)fy * (fnx + 1) + fx;
-      const int64_t fi = ch.fop + fo, fv = ch.fvec + fo;
-      const double w = wx * wy;
-      acc0 += w * mask[fi * 2] * t[fv * 2];
-      acc1 += w * mask[fi * 2 + 1] * t[fv * 2 + 1];
-    }
-  }
-  const int64_t node = ch.op + n, v = ch.vec + n;
-  r[v * 2] = acc0;
-  r[v * 2 + 1] = acc1;
-  e[v * 2] = dinv[node * 2] * acc0;
-  e[v * 2 + 1] = dinv[node * 2 + 1] * acc1;
-}
+// ---- per-node steps of levels >= 1 ----
 
 // Going up: e~ = e + P~ e2_coarse, then one l1-Jacobi sweep
 // e2 = e~ + D^-1 (r - A e~).  Lane `sub` (< 9) of a node's 16-lane group
@@ -709,25 +652,6 @@ __device__ __forceinline__ void mg_prolong_smooth_node(const MgChunk& ch, int n,
     e2[v * 2] = out0;
     e2[v * 2 + 1] = out1;
   }
-}
-
-__global__ __launch_bounds__(MGB) void k_mg_resid(const MgChunk* __restrict__ chunks, PcgDev s,
-                                                  const double* __restrict__ A, const double* __restrict__ r,
-                                                  const double* __restrict__ e, double* __restrict__ t) {
-  const MgChunk ch = chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;
-  const int n = ch.node_begin + threadIdx.x;
-  if (n < ch.node_end) mg_resid_node(ch, n, A, r, e, t);
-}
-
-__global__ __launch_bounds__(MGB) void k_mg_restrict(const MgChunk* __restrict__ chunks, PcgDev s,
-                                                     const double* __restrict__ mask, const double* __restrict__ dinv,
-                                                     const double* __restrict__ t, double* __restrict__ r,
-                                                     double* __restrict__ e) {
-  const MgChunk ch = chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;
-  const int n = ch.node_begin + threadIdx.x;
-  if (n < ch.node_end) mg_restrict_node(ch, n, mask, dinv, t, r, e);
 }
 
 // Levels l-1 -> l in one launch: r_l = R^T (mask * (r_{l-1} - A_{l-1} e_{l-1}))
@@ -1162,14 +1086,6 @@ void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const 
 void launch_mg_restrict0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* dinv,
                          double* r1, double* e1, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_mg_restrict0, dim3(n), dim3(MGB), 0, st, ch, s, vfree, dinv, r1, e1);
-}
-void launch_mg_resid(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* r, const double* e,
-                     double* t, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_mg_resid, dim3(n), dim3(MGB), 0, st, ch, s, A, r, e, t);
-}
-void launch_mg_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* mask, const double* dinv,
-                        const double* t, double* r, double* e, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_mg_restrict, dim3(n), dim3(MGB), 0, st, ch, s, mask, dinv, t, r, e);
 }
 void launch_mg_resid_restrict(const MgChunk* ch, int n, const PcgDev& s, const double* A, const double* mask,
                               const double* dinv, double* r, double* e, hipStream_t st) {

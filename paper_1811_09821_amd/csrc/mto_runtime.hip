@@ -94,7 +94,6 @@ struct MgHost {
   MgChunk* d_chunks = nullptr;
   double *A = nullptr, *dinv = nullptr, *mask = nullptr;  // operators [op nodes]
   double *r = nullptr, *e = nullptr, *e2 = nullptr;       // vectors [vec nodes]
-  double* t = nullptr;                                    // residual after pre-smoothing [vec nodes]
   double* dense = nullptr;                                // coarsest inverses
   int32_t* vfree = nullptr;                               // level 1: free index of vertex DOFs
   MgElem* elems = nullptr;
@@ -458,7 +457,7 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
   if ((rc = dev_upload(P, &M.d_chunks, M.chunks)) || (rc = dev_alloc(P, &M.A, 36 * (size_t)op_tot)) ||
       (rc = dev_alloc(P, &M.dinv, 2 * (size_t)op_tot)) || (rc = dev_alloc(P, &M.mask, 2 * (size_t)op_tot)) ||
       (rc = dev_alloc(P, &M.r, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.e, 2 * (size_t)vec_tot)) ||
-      (rc = dev_alloc(P, &M.e2, 2 * (size_t)vec_tot)) || (rc = dev_alloc(P, &M.t, 2 * (size_t)vec_tot)) ||
+      (rc = dev_alloc(P, &M.e2, 2 * (size_t)vec_tot)) ||
       (rc = dev_alloc(P, &M.dense, (size_t)dense_tot)) || (rc = dev_alloc(P, &M.band, (size_t)band_tot)) ||
       (rc = dev_alloc(P, &M.scr, (size_t)dense_tot)) ||
       (rc = dev_upload(P, &M.vfree, vfree)) || (rc = dev_upload(P, &M.elems, elems)) ||
@@ -468,7 +467,6 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
   launch_fill(M.e, 0.0, 2 * vec_tot, 0);
   launch_fill(M.e2, 0.0, 2 * vec_tot, 0);
   launch_fill(M.r, 0.0, 2 * vec_tot, 0);
-  launch_fill(M.t, 0.0, 2 * vec_tot, 0);
   return check_launch("multigrid setup");
 }
 
