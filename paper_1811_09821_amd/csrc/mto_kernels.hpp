@@ -202,11 +202,13 @@ void launch_mg_assemble1(const MgChunk* ch, int n, const MgElem* elems, const do
                          const int32_t* vfree, double* A, double* mask, hipStream_t st);
 void launch_mg_l1(const MgChunk* ch, int n, const double* A, double* dinv, hipStream_t st);
 void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_t st);
-// coarsest level of each instance: band Cholesky (LDS window), dense inverse
-// (band-order rows in scr), symmetrised into natural order in dense;
-// nmax / bmax: largest DOF count and band width over the instances
-void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* scr,
-                            double* dense, hipStream_t st);
+// coarsest level of each instance: band Cholesky (one LDS-window block per
+// instance) into band; then the dense inverse (band-order rows in scr),
+// symmetrised into natural order in dense; nmax / bmax: largest DOF count and
+// band width over the instances
+void launch_mg_coarse_factor(const MgChunk* ch, int n, int bmax, const double* A, double* band, hipStream_t st);
+void launch_mg_coarse_inverse(const MgChunk* ch, int n, int nmax, double* band, double* scr, double* dense,
+                              hipStream_t st);
 void launch_mg_restrict0(const MgChunk* ch, int n, const PcgDev& s, const int32_t* vfree, const double* dinv,
                          double* r1, double* e1, hipStream_t st);
 // levels l-1 -> l of the V-cycle in one launch (ch: the level-l system chunks)

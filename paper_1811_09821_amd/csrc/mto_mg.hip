@@ -1071,13 +1071,16 @@ void launch_mg_l1(const MgChunk* ch, int n, const double* A, double* dinv, hipSt
 void launch_mg_rap(const MgChunk* ch, int n, double* A, double* mask, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_mg_rap, dim3(n), dim3(MGB), 0, st, ch, A, mask);
 }
-void launch_mg_coarse_setup(const MgChunk* ch, int n, int nmax, int bmax, const double* A, double* band, double* scr,
-                            double* dense, hipStream_t st) {
+void launch_mg_coarse_factor(const MgChunk* ch, int n, int bmax, const double* A, double* band, hipStream_t st) {
   if (!n) return;
   if (chol_panel_rows(bmax) <= 64)
     hipLaunchKernelGGL(k_mg_coarse_chol<1>, dim3(n), dim3(MG_CHOL_BLOCK), chol_lds_bytes(bmax), st, ch, A, band);
   else
     hipLaunchKernelGGL(k_mg_coarse_chol<2>, dim3(n), dim3(MG_CHOL_BLOCK), chol_lds_bytes(bmax), st, ch, A, band);
+}
+void launch_mg_coarse_inverse(const MgChunk* ch, int n, int nmax, double* band, double* scr, double* dense,
+                              hipStream_t st) {
+  if (!n) return;
   hipLaunchKernelGGL(k_mg_coarse_inv, dim3((nmax + MG_INV_WAVES - 1) / MG_INV_WAVES, n), dim3(64 * MG_INV_WAVES),
                      (size_t)MG_INV_WAVES * nmax * 8, st, ch, band, scr, nmax);
   const int64_t nn = (int64_t)nmax * nmax;

@@ -791,7 +791,8 @@ void enq_residual(mto_plan* P, hipStream_t st);
 
 // Per design: level-1 operator, Galerkin coarse operators, l1 diagonals and
 // the dense inverse of the coarsest grid.
-void enq_mg_setup(mto_plan* P, hipStream_t st) {
+// The level operators (Galerkin products) and the coarsest grid's factor.
+void enq_mg_factor(mto_plan* P, hipStream_t st) {
   const MgHost& M = P->mg;
   launch_mg_assemble1(M.instc(1), M.inst_count[0], M.elems, M.kv, P->E, M.vfree, M.A, M.mask, st);
   launch_mg_l1(M.instc(1), M.inst_count[0], M.A, M.dinv, st);
@@ -799,7 +800,13 @@ void enq_mg_setup(mto_plan* P, hipStream_t st) {
     launch_mg_rap(M.instc(l), M.inst_count[l - 1], M.A, M.mask, st);
     launch_mg_l1(M.instc(l), M.inst_count[l - 1], M.A, M.dinv, st);
   }
-  launch_mg_coarse_setup(M.coarse_instc(), P->n_inst, M.coarse_nmax, M.coarse_bmax, M.A, M.band, M.scr, M.dense, st);
+  launch_mg_coarse_factor(M.coarse_instc(), P->n_inst, M.coarse_bmax, M.A, M.band, st);
+}
+
+// The coarsest grid's dense inverse from its factor.
+void enq_mg_inverse(mto_plan* P, hipStream_t st) {
+  const MgHost& M = P->mg;
+  launch_mg_coarse_inverse(M.coarse_instc(), P->n_inst, M.coarse_nmax, M.band, M.scr, M.dense, st);
 }
 
 // z = M r: one V-cycle from z = D0^-1 r (already in z), l1-Jacobi pre- and
@@ -857,16 +864,19 @@ void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st)
   for (auto& g : P->groups)
     launch_diag_elem(P->gdev(g), P->d_tiles, P->E, P->slots, P->d_sys, l1 ? g.kabs : g.kdiag, st);
   launch_dinv(s, P->dinv, damped ? P->prm.mg_omega : 1.0, st);
-  // The multigrid set-up (Galerkin operators, then the coarsest factor and
-  // inverse, which keep one CU busy for most of their time) depends only on
-  // the moduli, as do the Schwarz block inverses: it runs as a branch on the
-  // side stream (under capture, a parallel branch of the graph) and joins
-  // before the first V-cycle.  Nothing on the main stream until the join
-  // touches the multigrid buffers.
+  // The multigrid set-up depends only on the moduli, as do the Schwarz block
+  // inverses.  The coarsest factor is one workgroup on a serial chain that
+  // runs several times slower when it shares its CU with the block inverses,
+  // which fill every CU; so the level operators and the factor run first,
+  // alone, and the dense inverse (many waves) then runs as a branch on the
+  // side stream (under capture, a parallel branch of the graph) beside the
+  // block inverses, joining before the first V-cycle.  Nothing on this
+  // stream until the join touches the buffers of that branch.
   if (mg) {
+    enq_mg_factor(P, st);
     (void)hipEventRecord(P->fork_ev, st);
     (void)hipStreamWaitEvent(P->side_stream, P->fork_ev, 0);
-    enq_mg_setup(P, P->side_stream);
+    enq_mg_inverse(P, P->side_stream);
     (void)hipEventRecord(P->join_ev, P->side_stream);
   }
   if (P->prm.precond == MTO_PRECOND_MG_ASM)
