@@ -308,19 +308,43 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
     }
   }
   {
+    // GU entries per thread at a time: their index loads, then their value
+    // loads, all unconditional (clamped: column to the tile's last element,
+    // DOF to the system's first, which every system has), so each group of
+    // entries costs two memory round trips rather than two per entry
+    constexpr int GU = 4, NT = NEP * TC;
     const double* __restrict__ xs = xin + t.dof_off;
     const double* __restrict__ zs = s.z + t.dof_off;
-    for (int k = threadIdx.x; k < NEP * TC; k += blockDim.x) {
-      const int row = k / TC, col = k - row * TC;
-      const int el = t.elem_begin + col;
-      const int gi = (col < t.count) ? g.gidx[row * g.npad + el] : -1;
-      double v = 0.0, zv = 0.0;
-      if (gi >= 0) {
-        v = xs[gi];
-        if (pcg) zv = zs[gi];
+    for (int k0 = threadIdx.x; k0 < NT; k0 += GU * blockDim.x) {
+      int gi[GU];
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const int k = k0 + u * blockDim.x;
+        const int kc = k < NT ? k : NT - 1;
+        const int row = kc / TC, col = kc - row * TC;
+        const int gl = g.gidx[row * g.npad + t.elem_begin + (col < t.count ? col : t.count - 1)];
+        gi[u] = (k < NT && col < t.count) ? gl : -1;
       }
-      ush[k] = v;
-      if (pcg) ush[NEP * TC + k] = zv;
+      double v[GU], zv[GU];
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const int gc = gi[u] >= 0 ? gi[u] : 0;
+        const double xv = xs[gc];
+        v[u] = gi[u] >= 0 ? xv : 0.0;
+        zv[u] = 0.0;
+        if (pcg) {
+          const double zz = zs[gc];
+          zv[u] = gi[u] >= 0 ? zz : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const int k = k0 + u * blockDim.x;
+        if (k < NT) {
+          ush[k] = v[u];
+          if (pcg) ush[NT + k] = zv[u];
+        }
+      }
     }
   }
   __syncthreads();

@@ -199,6 +199,10 @@ int build_instance(const mto_problem& prob, InstanceHost& I, std::string& err) {
     else if (sid < first_interior_id) ++nfe;
     else ++nfi;
   }
+  if (nf == 0) {
+    err = "no free DOFs (every DOF is supported)";
+    return MTO_EINVAL;
+  }
   I.n_free = (int32_t)nf;
   I.nfv = (int32_t)nfv;
   I.nfe = (int32_t)nfe;
