@@ -189,7 +189,7 @@ const char* mto_version(void);
  * mesh, numbers the conforming space, groups elements by (p, d), uploads the
  * K_s tables and the gather/scatter descriptors.  Host inputs are copied.
  * Uses the current HIP device.  Errors: MTO_EINVAL (p or d out of range, a
- * support or load outside the mesh, a load on a supported DOF),
+ * support or load outside the mesh, a load on a supported DOF, no free DOF),
  * MTO_ESINGULAR (supports do not remove all three rigid-body modes),
  * MTO_ENOMEM, MTO_EHIP.  *out receives the plan (caller destroys it). */
 int mto_plan_create(const mto_problem* prob, const mto_params* params, mto_plan** out);

@@ -72,6 +72,17 @@ def test_accepts_sufficient_supports_until_device_work(sup):
         assert e.code in (mto.MTO_EHIP, mto.MTO_ENOMEM), e
 
 
+def test_rejects_an_instance_without_free_dofs():
+    """Every edge clamped in both directions on a 1 x 1, p = 1 mesh leaves no
+    free DOF: nothing to solve, so the plan is refused."""
+    sup = [(k, 0, 0, 3) for k in (P.SUP_EDGE_LEFT, P.SUP_EDGE_RIGHT, P.SUP_EDGE_BOTTOM, P.SUP_EDGE_TOP)]
+    pr = P.uniform_random(1, 1, 1, 1, 0, supports=sup, loads=[(1, 1, 0.0, -1.0, 0)])
+    with pytest.raises(mto.MtoError) as ei:
+        mto.Plan(pr)
+    assert ei.value.code == mto.MTO_EINVAL
+    assert "no free DOFs" in str(ei.value)
+
+
 def test_rejects_bad_loads_and_supports():
     pr = P.uniform_random(3, 2, 1, 1, 0, loads=[(0, 1, 0.0, -1.0, 0)])  # load on the clamped edge
     assert _err(pr) == mto.MTO_EINVAL
