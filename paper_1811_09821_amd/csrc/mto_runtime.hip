@@ -1045,7 +1045,8 @@ int iterate(mto_plan* P, hipStream_t st, int64_t& launched, double r0) {
   }
   if (rate > 0.0 && std::isfinite(rate)) P->rate_hint = rate;
   launched = queued;
-  HIP_TRY(hipStreamSynchronize(st));
+  // no synchronisation here: the caller's next work (the true residual and
+  // its copy to the host) follows these chunks in stream order
   return MTO_OK;
 }
 
