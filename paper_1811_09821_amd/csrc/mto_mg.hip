@@ -867,11 +867,12 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
   constexpr int NE = ne_of(P);
   constexpr int NEMAX = ne_of(MTO_MAX_P);
   __shared__ double A[NE][NE + 1];
-  __shared__ double fcol[NE];
+  __shared__ double prow[2][NE], pcol[2][NE];
   __shared__ double sc[NE];
   __shared__ int gid[NE];
-  __shared__ int pos[NEMAX];
-  __shared__ double Es[MTO_MAX_D * MTO_MAX_D];  // moduli of the element's (or a neighbour's) cells
+  __shared__ int posn[8][NEMAX];                       // each neighbour's DOFs in this element, or -1
+  __shared__ double Esn[8][MTO_MAX_D * MTO_MAX_D];     // each neighbour's cell moduli
+  __shared__ double Es[MTO_MAX_D * MTO_MAX_D];  // moduli of the element's cells
   const GroupDev g = groups[gi];
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
@@ -885,40 +886,55 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
     const int a = idx / NE, b = idx - a * NE;
     const double* __restrict__ kab = g.ks + (int64_t)a * NE + b;
     double v = 0.0;
-#pragma unroll 16
+#pragma unroll 4
     for (int sc_ = 0; sc_ < g.S; ++sc_) v = fma(Es[sc_], kab[(int64_t)sc_ * NE * NE], v);
     A[a][b] = v;
   }
   __syncthreads();
-  // neighbours: add their entries on pairs of shared DOFs (matched by free index)
+  // neighbours: add their entries on pairs of shared DOFs (matched by free
+  // index).  All eight neighbours' DOF positions and cell moduli are fetched
+  // in one phase; the additions then run neighbour by neighbour, in order.
+  for (int t2 = tid; t2 < 8 * NEMAX; t2 += ASM_BLOCK) {
+    const int m = t2 / NEMAX, b = t2 - m * NEMAX;
+    const int ge = nbr[m * g.npad + k];
+    int ps = -1;
+    if (ge >= 0) {
+      const GroupDev& gn = groups[el_group[ge]];
+      const int kn = el_col[ge];
+      if (b < ne_of(gn.p)) {
+        const int id = gn.gidx[b * gn.npad + kn];
+        if (id >= 0)
+          for (int a = 0; a < NE; ++a)
+            if (gid[a] == id) {
+              ps = a;
+              break;
+            }
+      }
+    }
+    posn[m][b] = ps;
+  }
+  for (int t2 = tid; t2 < 8 * MTO_MAX_D * MTO_MAX_D; t2 += ASM_BLOCK) {
+    const int m = t2 / (MTO_MAX_D * MTO_MAX_D), c = t2 - m * (MTO_MAX_D * MTO_MAX_D);
+    const int ge = nbr[m * g.npad + k];
+    if (ge >= 0) {
+      const GroupDev& gn = groups[el_group[ge]];
+      if (c < gn.S) Esn[m][c] = E[gn.cell[el_col[ge]] + c];
+    }
+  }
+  __syncthreads();
   for (int m = 0; m < 8; ++m) {
     const int ge = nbr[m * g.npad + k];
     if (ge < 0) continue;  // uniform over the block
     const GroupDev& gn = groups[el_group[ge]];
-    const int kn = el_col[ge];
     const int nen = ne_of(gn.p);
-    for (int b = tid; b < nen; b += ASM_BLOCK) {
-      const int id = gn.gidx[b * gn.npad + kn];
-      int ps = -1;
-      if (id >= 0)
-        for (int a = 0; a < NE; ++a)
-          if (gid[a] == id) {
-            ps = a;
-            break;
-          }
-      pos[b] = ps;
-    }
-    const int celln = gn.cell[kn];
-    for (int c = tid; c < gn.S; c += ASM_BLOCK) Es[c] = E[celln + c];
-    __syncthreads();
     for (int idx = tid; idx < nen * nen; idx += ASM_BLOCK) {
       const int a = idx / nen, b = idx - a * nen;
-      const int pa = pos[a], pb = pos[b];
+      const int pa = posn[m][a], pb = posn[m][b];
       if (pa < 0 || pb < 0) continue;
       const double* __restrict__ kab = gn.ks + (int64_t)a * nen + b;
       double v = 0.0;
-#pragma unroll 16
-      for (int sc_ = 0; sc_ < gn.S; ++sc_) v = fma(Es[sc_], kab[(int64_t)sc_ * nen * nen], v);
+#pragma unroll 4
+      for (int sc_ = 0; sc_ < gn.S; ++sc_) v = fma(Esn[m][sc_], kab[(int64_t)sc_ * nen * nen], v);
       A[pa][pb] += v;  // (a, b) -> (pa, pb) is one-to-one within a neighbour
     }
     __syncthreads();
@@ -940,20 +956,43 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
     A[a][b] *= sc[a] * sc[b];
   }
   __syncthreads();
-  // Gauss-Jordan inverse in place, no pivoting (the block is SPD)
+  // Gauss-Jordan inverse, no pivoting (the block is SPD).  Each thread keeps
+  // its entries (idx = tid + r ASM_BLOCK) in registers for all NE steps; per
+  // step only the pivot row and column pass through LDS, double-buffered, so
+  // one barrier per step.  Each entry is updated by the same expression as
+  // with the whole matrix in LDS.
+  constexpr int R = (NE * NE + ASM_BLOCK - 1) / ASM_BLOCK;
+  double av[R];
+  int ai[R], aj[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int idx = tid + r * ASM_BLOCK;
+    ai[r] = idx < NE * NE ? idx / NE : -1;
+    aj[r] = idx < NE * NE ? idx - ai[r] * NE : 0;
+    av[r] = idx < NE * NE ? A[ai[r]][aj[r]] : 0.0;
+  }
   for (int kk = 0; kk < NE; ++kk) {
-    const double piv = A[kk][kk];
-    __syncthreads();
-    for (int j = tid; j < NE; j += ASM_BLOCK) A[kk][j] = (j == kk ? 1.0 : A[kk][j]) / piv;
-    __syncthreads();
-    for (int i = tid; i < NE; i += ASM_BLOCK) fcol[i] = i == kk ? 0.0 : A[i][kk];
-    __syncthreads();
-    for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
-      const int i = idx / NE, j = idx - i * NE;
-      if (i != kk) A[i][j] = (j == kk ? 0.0 : A[i][j]) - fcol[i] * A[kk][j];
+    const int par = kk & 1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (ai[r] == kk) prow[par][aj[r]] = av[r];   // the pivot row
+      if (aj[r] == kk && ai[r] >= 0) pcol[par][ai[r]] = av[r];  // the pivot column
     }
     __syncthreads();
+    const double piv = prow[par][kk];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (ai[r] < 0) continue;
+      const int i = ai[r], j = aj[r];
+      const double rk = (j == kk ? 1.0 : prow[par][j]) / piv;  // the scaled pivot row
+      av[r] = i == kk ? rk : (j == kk ? 0.0 : av[r]) - pcol[par][i] * rk;
+    }
   }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (ai[r] >= 0) A[ai[r]][aj[r]] = av[r];
+  __syncthreads();
   // upper triangle, packed by rows (the inverse is symmetric)
   for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
     const int a = idx / NE, b = idx - a * NE;
