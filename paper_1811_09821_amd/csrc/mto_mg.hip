@@ -980,11 +980,19 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
     }
     __syncthreads();
     const double piv = prow[par][kk];
+    // When NE divides the block size a thread's entries share one column, so
+    // its scaled pivot-row entry is one division per step.
+    double rk0 = 0.0;
+    if constexpr (ASM_BLOCK % NE == 0) rk0 = (aj[0] == kk ? 1.0 : prow[par][aj[0]]) / piv;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (ai[r] < 0) continue;
       const int i = ai[r], j = aj[r];
-      const double rk = (j == kk ? 1.0 : prow[par][j]) / piv;  // the scaled pivot row
+      double rk;  // the scaled pivot row at column j
+      if constexpr (ASM_BLOCK % NE == 0)
+        rk = rk0;
+      else
+        rk = (j == kk ? 1.0 : prow[par][j]) / piv;
       av[r] = i == kk ? rk : (j == kk ? 0.0 : av[r]) - pcol[par][i] * rk;
     }
   }
