@@ -789,9 +789,8 @@ void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_
 
 void enq_residual(mto_plan* P, hipStream_t st);
 
-// Per design: level-1 operator, Galerkin coarse operators, l1 diagonals and
-// the dense inverse of the coarsest grid.
-// The level operators (Galerkin products) and the coarsest grid's factor.
+// Per design, the level operators (level-1 operator, Galerkin products, l1
+// diagonals) and the coarsest grid's factor.
 void enq_mg_factor(mto_plan* P, hipStream_t st) {
   const MgHost& M = P->mg;
   launch_mg_assemble1(M.instc(1), M.inst_count[0], M.elems, M.kv, P->E, M.vfree, M.A, M.mask, st);
