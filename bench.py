@@ -211,7 +211,7 @@ def main():
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus must be 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -31,9 +31,9 @@ What it computes, in plain FP64 (longdouble for residual accumulation):
   in Sec. 1 and Sec. 2.1 but prints no formula; this is the adjoint result for
   the self-adjoint compliance, lambda = -u).
 
-Every function cites the passage it follows.  Readings of points the paper
-leaves open (basis, mixed-p compatibility, layouts) are listed in the design doc of
-the repository.  Parity status: every function is pinned by ``-m "not gpu"``
+Every function cites the passage it follows; where the paper leaves a point
+open (basis, mixed-p compatibility, layouts) the reading taken is stated
+there.  Parity status: every function is pinned by ``-m "not gpu"``
 tests in ``tests/test_oracle_pins.py``, ``tests/test_filter_pins.py``,
 ``tests/test_qr_pins.py``, ``tests/test_mechanism_pins.py`` and
 ``tests/test_adapt_pins.py``; none is "parity unpinned".
