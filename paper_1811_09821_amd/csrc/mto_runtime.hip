@@ -132,9 +132,14 @@ struct mto_plan {
   double* slots_lo = nullptr;  // low parts of the double-double residual contraction
   double *xs_hi = nullptr, *xs_lo = nullptr;  // refined solution, double-double
   double *part_pq = nullptr, *part_rz = nullptr, *part_rr = nullptr, *part_aux = nullptr;
+  // per-system results in one block, fetched with one copy: status and
+  // iteration count (int32 each, one double's width per system), then
+  // sys_out [n_sys][4]
+  double* sysblk = nullptr;
   int32_t *status = nullptr, *iters = nullptr, *it_base = nullptr;
   double* progress = nullptr;  // [2], written by each chunk's last kernel
   double *tol2 = nullptr, *sys_out = nullptr;
+  double* h_sysblk = nullptr;  // host pinned copy of sysblk
   int32_t* f2f = nullptr;
   double* kspr = nullptr;  // ground springs per instance free DOF (NULL: none)
   int64_t *d_inst_cell_off = nullptr, *d_inst_g_off = nullptr;  // [n_inst + 1], [n_inst]
@@ -732,11 +737,16 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_alloc(P, &P->xs_lo, P->n_vec)) ||
       (rc = dev_alloc(P, &P->part_pq, nch)) || (rc = dev_alloc(P, &P->part_rz, 2 * nch)) ||
       (rc = dev_alloc(P, &P->part_rr, 2 * nch)) || (rc = dev_alloc(P, &P->part_aux, 3 * nch)) ||
-      (rc = dev_alloc(P, &P->status, P->n_sys)) || (rc = dev_alloc(P, &P->iters, P->n_sys)) ||
+      (rc = dev_alloc(P, &P->sysblk, 5 * (size_t)P->n_sys)) ||
       (rc = dev_alloc(P, &P->it_base, 1)) || (rc = dev_alloc(P, &P->progress, 2)) ||
-      (rc = dev_alloc(P, &P->tol2, P->n_sys)) || (rc = dev_alloc(P, &P->sys_out, 4 * (size_t)P->n_sys)) ||
+      (rc = dev_alloc(P, &P->tol2, P->n_sys)) ||
       (rc = dev_upload(P, &P->f2f, f2f)))
     return cleanup(rc);
+  P->status = reinterpret_cast<int32_t*>(P->sysblk);
+  P->iters = P->status + P->n_sys;
+  P->sys_out = P->sysblk + P->n_sys;
+  if (hipHostMalloc((void**)&P->h_sysblk, 5 * (size_t)P->n_sys * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(MTO_ENOMEM, "hipHostMalloc failed"));
   {
     bool any = false;
     for (int i = 0; i < n; ++i) any |= !I[i].springs.empty();
@@ -1058,10 +1068,13 @@ int fetch(mto_plan* P, hipStream_t st, SysResult& R) {
   R.status.resize(P->n_sys);
   R.iters.resize(P->n_sys);
   R.out.resize(4 * (size_t)P->n_sys);
-  HIP_TRY(hipMemcpyAsync(R.status.data(), P->status, P->n_sys * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(R.iters.data(), P->iters, P->n_sys * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(R.out.data(), P->sys_out, 4 * P->n_sys * sizeof(double), hipMemcpyDeviceToHost, st));
+  // one copy of the per-system block into pinned memory
+  HIP_TRY(hipMemcpyAsync(P->h_sysblk, P->sysblk, 5 * (size_t)P->n_sys * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  const int32_t* hs = reinterpret_cast<const int32_t*>(P->h_sysblk);
+  std::memcpy(R.status.data(), hs, P->n_sys * sizeof(int32_t));
+  std::memcpy(R.iters.data(), hs + P->n_sys, P->n_sys * sizeof(int32_t));
+  std::memcpy(R.out.data(), P->h_sysblk + P->n_sys, 4 * (size_t)P->n_sys * sizeof(double));
   return MTO_OK;
 }
 
@@ -1569,6 +1582,7 @@ void mto_plan_destroy(mto_plan* P) {
   for (auto& a : P->allocs)
     if (a.ptr) (void)hipFree(a.ptr);
   if (P->h_prog) (void)hipHostFree(P->h_prog);
+  if (P->h_sysblk) (void)hipHostFree(P->h_sysblk);
   for (int k = 0; k < N_PROG; ++k)
     if (P->ev[k]) (void)hipEventDestroy(P->ev[k]);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
