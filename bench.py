@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--precond", choices=["schwarz-mg", "jacobi", "l1-mg"], default="schwarz-mg",
                     help="PCG preconditioner (default: multigrid with element-block Schwarz smoothing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iters-per-launch", type=int, default=0,
+                    help="PCG iterations per captured chunk graph (0: the library default)")
     ap.add_argument("--mg-coarse-max", type=int, default=0,
                     help="DOFs of the coarsest multigrid grid at most (0: the library default)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -224,7 +226,8 @@ def main():
     prs, desc = workload(args.config)
     path = mto.PATH_MFMA if args.path == "mfma" else mto.PATH_PLAIN
     precond = {"jacobi": mto.PRECOND_JACOBI, "l1-mg": mto.PRECOND_MG, "schwarz-mg": mto.PRECOND_MG_ASM}[args.precond]
-    plan = mto.Plan(prs, kernel_path=path, precond=precond, mg_coarse_max=args.mg_coarse_max)
+    plan = mto.Plan(prs, kernel_path=path, precond=precond, mg_coarse_max=args.mg_coarse_max,
+                    iters_per_launch=args.iters_per_launch)
     rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=dev)
     tune = ""
     if path == mto.PATH_MFMA and not args.no_autotune:
