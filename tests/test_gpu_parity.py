@@ -227,6 +227,48 @@ def test_batch_parity_uneven_instances(cuda):
     check_solution(plan, prs, u, c, g, st)
 
 
+DEGENERATE = {
+    "single_p1": lambda: [P.uniform_random(1, 1, 1, 3, 21)],
+    "single_p4": lambda: [P.uniform_random(1, 1, 4, 3, 24)],
+    "strip12x1_p4": lambda: [P.uniform_random(12, 1, 4, 2, 31)],
+    "column1x9_p3": lambda: [P.uniform_random(1, 9, 3, 2, 32, loads=[(1, 9, 0.0, -1.0, 0)])],
+}
+
+
+@pytest.mark.parametrize("precond", [0, 2])
+@pytest.mark.parametrize("name", sorted(DEGENERATE))
+def test_degenerate_meshes(cuda, name, precond):
+    """Meshes one element wide or high: a single element (4 free DOFs at
+    p = 1, one element tile of 16 rows, an 8-DOF coarsest grid whose band is
+    wider than the grid), a 12 x 1 strip and a 1 x 9 column, against the
+    oracle with both preconditioners."""
+    prs = DEGENERATE[name]()
+    plan = mto().Plan(prs, precond=precond)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
+
+
+def test_zero_load_cases(cuda):
+    """A load case with no loads (f = 0) meets the stop test before its first
+    iteration and returns u = 0, c = 0 and dc/drho = 0, while the loaded
+    systems of the same plan (a second case of the same instance, another
+    instance) converge as usual; likewise an instance with no loads at all."""
+    prs = [P.uniform_random(6, 3, 2, 3, 11, loads=[(6, 1, 0.0, -1.0, 0)], n_load_cases=2),
+           P.uniform_random(5, 2, 3, 2, 12, loads=[]),
+           P.small_mixed(8, 4, seed=13)]
+    plan = mto().Plan(prs)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
+    its = st["iterations"]  # systems: instance 0 cases 0 and 1, instance 1, instance 2
+    assert its[1] == 0 and its[2] == 0 and its[0] > 0 and its[3] > 0, its
+    us, cs, gs = plan.split_u(u), plan.split_c(c), plan.split_g(g)
+    assert not us[0][1].any() and not us[1].any()
+    assert cs[0][1].item() == 0.0 and not cs[1].any()
+    assert not gs[0][1].any() and not gs[1].any()
+
+
 def test_capture_replay_matches_eager(cuda):
     """hipGraph capture of the whole step, replayed several times with eager
     work and synchronisation in between and densities changed in place: every
