@@ -117,6 +117,37 @@ def test_matvec_mixed_and_diag(cuda, path):
     assert rel(dg, dref) < 1e-14
 
 
+def random_orders_mesh():
+    """8 x 5 mesh with p in 1..4 and d in 1..8 drawn per element, unsmoothed:
+    order jumps of 3 across edges and 26 (p, d) groups of one to four
+    elements each (every element tile ragged)."""
+    rng = np.random.default_rng(61)
+    return P.uniform_random(8, 5, rng.integers(1, 5, 40), rng.integers(1, 9, 40), 61)
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_matvec_random_orders(cuda, path):
+    pr = random_orders_mesh()
+    K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
+    free = free_mask(space, pr.supports)
+    x = np.random.default_rng(2).standard_normal(space.n_dof)
+    x[~free] = 0.0
+    yref = K @ x
+    yref[~free] = 0.0
+    plan = mto().Plan(pr, kernel_path=path)
+    y = plan.apply_stiffness(torch.tensor(pr.rho, device=cuda), torch.tensor(x, device=cuda)).cpu().numpy()
+    assert rel(y, yref) < 1e-13
+
+
+@pytest.mark.parametrize("precond", [0, 2])
+def test_solve_random_orders(cuda, precond):
+    """The unsmoothed mesh above solved with both preconditioners."""
+    prs = [random_orders_mesh()]
+    plan = mto().Plan(prs, precond=precond)
+    u, c, g, st = plan.solve(torch.tensor(prs[0].rho, device=cuda))
+    check_solution(plan, prs, u, c, g, st)
+
+
 def test_sensitivity_kernel_given_u(cuda):
     """g = -E' u_e^T K_s u_e from given (random) displacements, mixed mesh,
     two load cases."""
