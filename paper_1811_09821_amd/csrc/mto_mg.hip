@@ -873,9 +873,35 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
   __shared__ int posn[8][NEMAX];                       // each neighbour's DOFs in this element, or -1
   __shared__ double Esn[8][MTO_MAX_D * MTO_MAX_D];     // each neighbour's cell moduli
   __shared__ double Es[MTO_MAX_D * MTO_MAX_D];  // moduli of the element's cells
+  // each neighbour's group data, fetched once (nb_p = -1: no neighbour)
+  __shared__ int nb_p[8], nb_S[8], nb_npad[8], nb_cell[8], nb_cnt[8];
+  __shared__ const int32_t* nb_gidx[8];  // the neighbour's column of its group's DOF table
+  __shared__ const double* nb_ks[8];
+  // Two elements share the DOFs of a common edge (at most 2 (P + 1) under the
+  // minimum rule) or of a common vertex (2): four edge and four corner
+  // neighbours give at most PAIRMAX shared DOF pairs.
+  constexpr int SHMAX = 2 * (P + 1);
+  constexpr int PAIRMAX = 4 * SHMAX * SHMAX + 4 * 4;
+  __shared__ uint8_t nb_sh[8][SHMAX];  // the neighbour's local DOFs shared with this element
+  __shared__ double nb_v[PAIRMAX];  // their entries, neighbour by neighbour
   const GroupDev g = groups[gi];
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
+  if (tid < 8) {
+    const int ge = nbr[tid * g.npad + k];
+    int pn = -1;
+    if (ge >= 0) {
+      const GroupDev& gn = groups[el_group[ge]];
+      const int kn = el_col[ge];
+      pn = gn.p;
+      nb_S[tid] = gn.S;
+      nb_npad[tid] = gn.npad;
+      nb_cell[tid] = gn.cell[kn];
+      nb_gidx[tid] = gn.gidx + kn;
+      nb_ks[tid] = gn.ks;
+    }
+    nb_p[tid] = pn;
+  }
   for (int a = tid; a < NE; a += ASM_BLOCK) gid[a] = g.gidx[a * g.npad + k];
   const int cell = g.cell[k];
   for (int c = tid; c < g.S; c += ASM_BLOCK) Es[c] = E[cell + c];
@@ -892,51 +918,66 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
   }
   __syncthreads();
   // neighbours: add their entries on pairs of shared DOFs (matched by free
-  // index).  All eight neighbours' DOF positions and cell moduli are fetched
-  // in one phase; the additions then run neighbour by neighbour, in order.
+  // index).  The DOF positions and cell moduli of all eight neighbours are
+  // fetched in one phase, each neighbour's shared DOFs compacted with a wave
+  // ballot, and the entries of every shared pair computed in one more phase;
+  // the additions then run neighbour by neighbour, in order.
   for (int t2 = tid; t2 < 8 * NEMAX; t2 += ASM_BLOCK) {
     const int m = t2 / NEMAX, b = t2 - m * NEMAX;
-    const int ge = nbr[m * g.npad + k];
+    const int pn = nb_p[m];
     int ps = -1;
-    if (ge >= 0) {
-      const GroupDev& gn = groups[el_group[ge]];
-      const int kn = el_col[ge];
-      if (b < ne_of(gn.p)) {
-        const int id = gn.gidx[b * gn.npad + kn];
-        if (id >= 0)
-          for (int a = 0; a < NE; ++a)
-            if (gid[a] == id) {
-              ps = a;
-              break;
-            }
-      }
+    if (pn >= 0 && b < ne_of(pn)) {
+      const int id = nb_gidx[m][b * nb_npad[m]];
+      if (id >= 0)
+        for (int a = 0; a < NE; ++a)
+          if (gid[a] == id) {
+            ps = a;
+            break;
+          }
     }
     posn[m][b] = ps;
   }
   for (int t2 = tid; t2 < 8 * MTO_MAX_D * MTO_MAX_D; t2 += ASM_BLOCK) {
     const int m = t2 / (MTO_MAX_D * MTO_MAX_D), c = t2 - m * (MTO_MAX_D * MTO_MAX_D);
-    const int ge = nbr[m * g.npad + k];
-    if (ge >= 0) {
-      const GroupDev& gn = groups[el_group[ge]];
-      if (c < gn.S) Esn[m][c] = E[gn.cell[el_col[ge]] + c];
+    if (nb_p[m] >= 0 && c < nb_S[m]) Esn[m][c] = E[nb_cell[m] + c];
+  }
+  __syncthreads();
+  {
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int m = wave; m < 8; m += ASM_BLOCK / 64) {
+      const bool shared = lane < NEMAX && posn[m][lane] >= 0;
+      const unsigned long long bal = __ballot(shared);
+      const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+      if (shared && pos < SHMAX) nb_sh[m][pos] = (uint8_t)lane;
+      if (lane == 0) nb_cnt[m] = min(__popcll(bal), SHMAX);
     }
   }
   __syncthreads();
-  for (int m = 0; m < 8; ++m) {
-    const int ge = nbr[m * g.npad + k];
-    if (ge < 0) continue;  // uniform over the block
-    const GroupDev& gn = groups[el_group[ge]];
-    const int nen = ne_of(gn.p);
-    for (int idx = tid; idx < nen * nen; idx += ASM_BLOCK) {
-      const int a = idx / nen, b = idx - a * nen;
-      const int pa = posn[m][a], pb = posn[m][b];
-      if (pa < 0 || pb < 0) continue;
-      const double* __restrict__ kab = gn.ks + (int64_t)a * nen + b;
-      double v = 0.0;
-#pragma unroll 4
-      for (int sc_ = 0; sc_ < gn.S; ++sc_) v = fma(Esn[m][sc_], kab[(int64_t)sc_ * nen * nen], v);
-      A[pa][pb] += v;  // (a, b) -> (pa, pb) is one-to-one within a neighbour
+  for (int t0 = tid; t0 < PAIRMAX; t0 += ASM_BLOCK) {
+    int rem = t0, m = 0;
+    for (; m < 8; ++m) {
+      const int c = nb_cnt[m];
+      if (rem < c * c) break;
+      rem -= c * c;
     }
+    if (m == 8) break;  // past the last pair
+    const int c = nb_cnt[m], x = rem / c, y = rem - x * c;
+    const int a = nb_sh[m][x], b = nb_sh[m][y], nen = ne_of(nb_p[m]);
+    const double* __restrict__ kab = nb_ks[m] + (int64_t)a * nen + b;
+    double v = 0.0;
+#pragma unroll 4
+    for (int sc_ = 0; sc_ < nb_S[m]; ++sc_) v = fma(Esn[m][sc_], kab[(int64_t)sc_ * nen * nen], v);
+    nb_v[t0] = v;
+  }
+  __syncthreads();
+  for (int m = 0, off = 0; m < 8; ++m) {  // uniform
+    const int c = nb_cnt[m];
+    if (c == 0) continue;
+    for (int t = tid; t < c * c && off + t < PAIRMAX; t += ASM_BLOCK) {
+      const int x = t / c, y = t - x * c;
+      A[posn[m][nb_sh[m][x]]][posn[m][nb_sh[m][y]]] += nb_v[off + t];  // one-to-one within a neighbour
+    }
+    off += c * c;
     __syncthreads();
   }
   // absent or supported DOFs, and DOFs with no stiffness at all (E_min = 0
