@@ -176,6 +176,30 @@ def test_mixed_order_space_dimension():
     assert space.n_scalar == nv + n_edge_modes + n_int
 
 
+def test_elements_share_dofs_only_across_a_common_edge_or_vertex():
+    """Under the minimum rule two elements share exactly the DOFs of their
+    common edge, 2 (min(p_a, p_b) + 1) of them (two vertices and the edge
+    modes up to the lower order, two components each), or of their common
+    vertex (2), and none otherwise; the element-block smoother sizes its
+    neighbour buffers by this.  Every pair of elements of a mesh of random
+    orders against that count."""
+    rng = np.random.default_rng(11)
+    nelx, nely = 5, 4
+    p = rng.integers(1, 5, size=nelx * nely)
+    space = build_space(nelx, nely, p)
+    dofs = [set(int(x) for x in element_dofs_global(space, e) if x >= 0) for e in range(nelx * nely)]
+    for e in range(nelx * nely):
+        for f in range(e + 1, nelx * nely):
+            dx, dy = abs(e % nelx - f % nelx), abs(e // nelx - f // nelx)
+            if dx + dy == 1:
+                expected = 2 * (min(p[e], p[f]) + 1)
+            elif dx == 1 and dy == 1:
+                expected = 2
+            else:
+                expected = 0
+            assert len(dofs[e] & dofs[f]) == expected, (e, f, p[e], p[f])
+
+
 # -- patch test ------------------------------------------------------------
 def test_constant_strain_patch_mixed_orders():
     """Constant-strain patch test on a mixed (p, d) 3 x 3 patch: with a linear
