@@ -9,10 +9,15 @@ from the global solution):
   * K^(p) = sum_s E(rho_s) K_s^(p), K^(p+1) = sum_s E(rho_s) K_s^(p+1)
     (composite integration over the element's density cells);
   * the internal load vector f^(p) = K^(p) u^(p) and J^(p) = 1/2 u^(p)T K^(p) u^(p);
-  * f^(p+1): the same load expressed on the refined functions.  Reading: the
-    basis is hierarchic, so every order-p function is also an order-(p+1)
-    function; the load keeps its value on those and is zero on the new
-    functions (the same work against every order-p field);
+  * f^(p+1): the paper forms it by integrating the interpolated order-p load
+    field against the refined shape functions.  Reading: the load field is
+    the field f_h of the order-p space whose integrals against the order-p
+    functions are the entries of f^(p) (M^(p) c = f^(p), M the element's mass
+    matrix, f_h = sum_a c_a N_a); f^(p+1)_b is the integral of f_h N_b over
+    the element for every order-(p+1) function N_b.  On the order-p functions
+    (which are order-(p+1) functions too) this returns f^(p); the new
+    functions get the moments of f_h.  The reading is dimensionally
+    consistent and does not depend on the basis;
   * u^(p+1) solves K^(p+1) u = f^(p+1) with 3 DOFs (as many as the rigid
     motions in 2D) copied from u^(p).  Reading: the x and y DOFs of the
     vertex at (0, 0) and the y DOF of the vertex at (1, 0) of the element;
@@ -26,8 +31,9 @@ energies are unchanged by adding a rigid motion to u^(p).
 """
 
 import numpy as np
+from numpy.polynomial import legendre as npleg
 
-from .fem import simp_modulus, subcell_stiffness
+from .fem import basis_1d, simp_modulus, subcell_stiffness
 from .solve import cell_offsets, element_dofs_global
 from .space import build_space
 
@@ -45,6 +51,32 @@ def embed_index(p):
             for c in range(2):
                 out[2 * (j * n1 + i) + c] = 2 * (j * (n1 + 1) + i) + c
     return out
+
+
+def mass_matrix(p):
+    """Mass matrix of the order-p element (unit square, vector DOFs 2a + c):
+    M[2a + c, 2b + c] = integral of N_a N_b over the element, from the 1D
+    mass matrix of basis_1d by a (p + 2)-point Gauss rule (exact)."""
+    g, w = npleg.leggauss(p + 2)
+    phi, _ = basis_1d(p, g)
+    m = 0.5 * (phi * w) @ phi.T  # dx = dxi / 2 on the unit interval
+    n1 = p + 1
+    scalar = np.einsum("jl,ik->jilk", m, m).reshape(n1 * n1, n1 * n1)  # a = j n1 + i, b = l n1 + k
+    M = np.zeros((2 * n1 * n1, 2 * n1 * n1))
+    M[0::2, 0::2] = scalar
+    M[1::2, 1::2] = scalar
+    return M
+
+
+def refined_load(f, p):
+    """The order-(p+1) element load of the order-p load f^(p) (Sec. 3.2.3):
+    the load field's coefficients c from M^(p) c = f^(p), then the integrals
+    of that field against every order-(p+1) function, M^(p+1)[:, emb] c (the
+    order-p functions are the embedded order-(p+1) ones)."""
+    Mq = mass_matrix(p + 1)
+    emb = embed_index(p)
+    c = np.linalg.solve(Mq[np.ix_(emb, emb)], np.asarray(f, dtype=np.float64))
+    return Mq[:, emb] @ c
 
 
 def _quad(K, u):
@@ -97,8 +129,7 @@ def element_qr_error(Ks_p, Ks_p1, E, ue, p, pinned=PINNED, rounds=3):
     Jp = 0.5 * _quad(Kp, ud)
     emb = embed_index(p)
     nq = Kq.shape[0]
-    fq = np.zeros(nq)
-    fq[emb] = f
+    fq = refined_load(f, p)
     pin = np.array([emb[k] for k in pinned])
     free = np.setdiff1d(np.arange(nq), pin)
     uq = np.zeros(nq)  # the pinned values of u - rigid are zero

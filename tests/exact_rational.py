@@ -108,3 +108,62 @@ def subcell_stiffness_exact(p, d, nu=F(3, 10)):
                             K[2 * a + 1][2 * b + 1] += D[1][1] * yy + D[2][2] * xx
             out.append(K)
     return out
+
+
+def mass_1d_exact(p):
+    """m[i][k] = integral over the unit interval of phi_i phi_k (dx = dxi / 2)."""
+    phi = basis(p)
+    return [[integral(pmul(phi[i], phi[k]), F(-1), F(1)) / 2 for k in range(p + 1)] for i in range(p + 1)]
+
+
+def moments_exact(beta, p):
+    """Integrals over the unit element of the vector field b against every
+    order-p function: b_c(xi, eta) = sum beta[c][i][j] xi^i eta^j (reference
+    coordinates), result indexed 2a + c with a = j (p+1) + i of N_a =
+    phi_i(xi) phi_j(eta)."""
+    phi = basis(p)
+    n1 = p + 1
+    deg = len(beta[0])
+    # 1D integrals of xi^m phi_i over [-1, 1], times 1/2 for dx = dxi / 2
+    mono = [[integral(pmul([F(0)] * m + [F(1)], phi[i]), F(-1), F(1)) / 2 for i in range(n1)] for m in range(deg)]
+    out = [F(0)] * (2 * n1 * n1)
+    for c in range(2):
+        for ja in range(n1):
+            for ia in range(n1):
+                acc = F(0)
+                for mi in range(deg):
+                    for mj in range(deg):
+                        if beta[c][mi][mj]:
+                            acc += beta[c][mi][mj] * mono[mi][ia] * mono[mj][ja]
+                out[2 * (ja * n1 + ia) + c] = acc
+    return out
+
+
+def solve_exact(A, b):
+    """Gauss-Jordan elimination with Fractions (A nonsingular)."""
+    n = len(b)
+    M = [list(A[i]) + [b[i]] for i in range(n)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[piv] = M[piv], M[c]
+        inv = 1 / M[c][c]
+        M[c] = [v * inv for v in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                fac = M[r][c]
+                M[r] = [vr - fac * vc for vr, vc in zip(M[r], M[c])]
+    return [M[i][n] for i in range(n)]
+
+
+def pinned_solve_exact(K, f, pinned, values):
+    """u with u[pinned] = values and (K u)[free] = f[free]."""
+    n = len(f)
+    free = [i for i in range(n) if i not in pinned]
+    u = [F(0)] * n
+    for k, v in zip(pinned, values):
+        u[k] = v
+    rhs = [f[i] - sum(K[i][k] * u[k] for k in pinned) for i in free]
+    sol = solve_exact([[K[i][j] for j in free] for i in free], rhs)
+    for i, v in zip(free, sol):
+        u[i] = v
+    return u
