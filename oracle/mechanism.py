@@ -13,13 +13,15 @@ dJ/drho_{e,s} = -E'(rho_{e,s}) lambda_e^T K_s u_e.
 import numpy as np
 
 from .fem import simp_modulus_derivative, subcell_stiffness
-from .solve import cell_offsets, element_dofs_global, oracle_solve
+from .solve import cell_offsets, element_dofs_global, oracle_solve, rigid_free
 from .space import build_space
 
 
 def bilinear_sensitivity(nelx, nely, p, d, rho, u, lam, E0=1.0, Emin=1e-9, q=3.0, nu=0.3):
     """-E'(rho_{e,s}) lam_e^T K_s u_e for every cell, global vectors u, lam
-    [n_dof] (with lam = u it is the compliance sensitivity)."""
+    [n_dof] (with lam = u it is the compliance sensitivity).  Both element
+    vectors have their rigid motions removed first (K_s annihilates them;
+    see rigid_free in solve.py)."""
     p = np.asarray(p, dtype=np.int64).ravel()
     d = np.asarray(d, dtype=np.int64).ravel()
     rho = np.asarray(rho, dtype=np.float64).ravel()
@@ -33,8 +35,8 @@ def bilinear_sensitivity(nelx, nely, p, d, rho, u, lam, E0=1.0, Emin=1e-9, q=3.0
         if key not in cache:
             cache[key] = subcell_stiffness(key[0], key[1], nu)
         G = element_dofs_global(space, e)
-        ue = np.where(G >= 0, u[np.maximum(G, 0)], 0.0)
-        le = np.where(G >= 0, lam[np.maximum(G, 0)], 0.0)
+        ue = rigid_free(np.where(G >= 0, u[np.maximum(G, 0)], 0.0), key[0])
+        le = rigid_free(np.where(G >= 0, lam[np.maximum(G, 0)], 0.0), key[0])
         out[off[e]:off[e + 1]] = -dE[off[e]:off[e + 1]] * np.einsum("i,sij,j->s", le, cache[key], ue)
     return out
 

@@ -15,8 +15,23 @@ numpy.longdouble, until the correction is below 1e-15 of u.  (With modulus
 contrast E_min/E0 = 1e-9 the condition number of K is large, so a single
 FP64 factor solve alone is not trusted to 1e-8.)
 
+The residual applies K by its definition, element by element:
+K u = sum_e P_e^T K_e (u_e - r_e), where r_e is the rigid motion that takes
+the element's values at three vertex DOFs (vertex (0,0) x and y, vertex
+(1,0) y).  K_e annihilates rigid motions, so this is K u exactly; it matters
+in floating point.  Where a region of solid material is joined to the
+supports only through void material (E = E_min), the region moves almost
+rigidly by 1e9 times its deformation.  The FP64 cell matrices annihilate
+rigid motions only to their rounding (K_s r ~ 1e-16 |K_s| |r|), and the
+assembled FP64 matrix only to the rounding of its sums, so applying them to
+the whole of u_e puts spurious forces of 1e-7 relative size on such a
+region, which move u by up to 1e-3.  Applied to u_e - r_e they act on the
+deformation alone.  The assembled FP64 matrix serves only as the
+preconditioner of the refinement (its LU factors).
+
 Sensitivity: for the self-adjoint compliance the adjoint is lambda = -u, so
-dc/drho_{e,s} = -u^T (dK/drho_{e,s}) u = -E'(rho_{e,s}) u_e^T K_s u_e.
+dc/drho_{e,s} = -u^T (dK/drho_{e,s}) u = -E'(rho_{e,s}) u_e^T K_s u_e,
+evaluated as (u_e - r_e)^T K_s (u_e - r_e) for the same reason.
 """
 
 import numpy as np
@@ -105,19 +120,65 @@ def free_mask(space, supports):
     return free
 
 
-def refined_solve(Kff, lu, b, max_rounds=8):
-    """Factor solve plus iterative refinement with a longdouble residual."""
-    Kl = Kff.astype(np.longdouble)
+def rigid_free(ue, p):
+    """u_e minus the rigid motion (a - th y, b + th x) through its DOFs 0, 1
+    (vertex (0,0) x, y) and 3 (vertex (1,0) y), for element vectors [..., n_e]
+    of order p (the rigid motion lives on the four vertex functions)."""
+    n1 = p + 1
+    a, b = ue[..., 0], ue[..., 1]
+    th = ue[..., 3] - ue[..., 1]
+    out = ue.copy()
+    for j in range(2):
+        for i in range(2):
+            k = j * n1 + i
+            out[..., 2 * k] -= a - th * j
+            out[..., 2 * k + 1] -= b + th * i
+    return out
+
+
+class ElementOperator:
+    """K u = sum_e P_e^T K_e (u_e - r_e) in numpy.longdouble, element group
+    by element group, with K_e = sum_s E(rho_{e,s}) K_s (Sec. 2.2, Appendix
+    B) and r_e the element's rigid motion (rigid_free)."""
+
+    def __init__(self, p, d, E, edofs, off, ks, nu, n_dof):
+        p = np.asarray(p, dtype=np.int64).ravel()
+        d = np.asarray(d, dtype=np.int64).ravel()
+        self.n_dof = n_dof
+        self.groups = []
+        for (pe, de) in sorted(set(zip(p.tolist(), d.tolist()))):
+            els = np.nonzero((p == pe) & (d == de))[0]
+            G = np.stack([edofs[e] for e in els])
+            Eg = np.stack([E[off[e]:off[e + 1]] for e in els]).astype(np.longdouble)
+            self.groups.append((pe, G, Eg, ks[(pe, de, nu)].astype(np.longdouble)))
+
+    def apply(self, u):
+        """K u for a full-length vector u (zeros at supported DOFs)."""
+        u = np.asarray(u, dtype=np.longdouble)
+        y = np.zeros(self.n_dof, dtype=np.longdouble)
+        for pe, G, Eg, Ks in self.groups:
+            ue = rigid_free(np.where(G >= 0, u[np.maximum(G, 0)], 0), pe)
+            ye = np.einsum("ns,nsi->ni", Eg, np.einsum("sij,nj->nsi", Ks, ue))
+            m = G >= 0
+            np.add.at(y, G[m], ye[m])
+        return y
+
+
+def refined_solve(op, fi, lu, b, max_rounds=30):
+    """Factor solve plus iterative refinement with a longdouble residual
+    b - (K u)[fi] from the element operator; stops when the correction is
+    below 1e-15 of u."""
     bl = b.astype(np.longdouble)
-    u = lu.solve(b).astype(np.longdouble)
+    u = np.zeros(op.n_dof, dtype=np.longdouble)
+    u[fi] = lu.solve(b)
     for _ in range(max_rounds):
-        r = bl - Kl @ u
+        r = bl - op.apply(u)[fi]
         du = lu.solve(np.asarray(r, dtype=np.float64))
-        u = u + du.astype(np.longdouble)
+        u[fi] += du.astype(np.longdouble)
         nu = float(np.sqrt(np.sum(u * u)))
         if nu == 0.0 or float(np.linalg.norm(du)) <= 1e-15 * nu:
             break
-    return u
+    return u[fi]
 
 
 def spring_matrix(space, springs):
@@ -131,13 +192,15 @@ def spring_matrix(space, springs):
 
 
 def oracle_solve(nelx, nely, p, d, rho, supports, loads, n_load_cases=1,
-                 E0=1.0, Emin=1e-9, nu=0.3, q=3.0, want_K=False, springs=()):
+                 E0=1.0, Emin=1e-9, nu=0.3, q=3.0, want_K=False, springs=(), tables=None):
     """Full reference step: returns dict with
     u [L, n_dof] (zero at supported DOFs), c [L], g [L, n_cells] (dc/drho),
     w [L, n_cells] (u_e^T K_s u_e), plus bookkeeping.  Ground springs
     (vx, vy, comp, k) are added to K; they do not depend on rho, so g keeps
-    its form."""
-    K, space, edofs, off, ks = assemble(nelx, nely, p, d, rho, E0, Emin, q, nu)
+    its form.  tables: optional dict (p, d, nu) -> K_s to use instead of
+    computing them (for perturbation tests)."""
+    K, space, edofs, off, ks = assemble(nelx, nely, p, d, rho, E0, Emin, q, nu,
+                                        ks_cache=dict(tables) if tables else None)
     if len(springs):
         S = spring_matrix(space, springs)
         if np.any(S.diagonal()[~free_mask(space, supports)] != 0.0):
@@ -155,8 +218,14 @@ def oracle_solve(nelx, nely, p, d, rho, supports, loads, n_load_cases=1,
     L = n_load_cases
     u = np.zeros((L, space.n_dof))
     c = np.zeros(L)
+    E_all = simp_modulus(np.asarray(rho, dtype=np.float64).ravel(), E0, Emin, q)
+    op = ElementOperator(p, d, E_all, edofs, off, ks, nu, space.n_dof)
+    if len(springs):  # the springs' diagonal joins the element operator
+        sdiag = spring_matrix(space, springs).diagonal().astype(np.longdouble)
+        base = op.apply
+        op.apply = lambda v, base=base, sdiag=sdiag: base(v) + sdiag * np.asarray(v, dtype=np.longdouble)
     for lc in range(L):
-        ul = refined_solve(Kff, lu, f[lc, fi])
+        ul = refined_solve(op, fi, lu, f[lc, fi])
         u[lc, fi] = np.asarray(ul, dtype=np.float64)
         c[lc] = float(np.dot(f[lc, fi].astype(np.longdouble), ul))
     # sensitivities: g_{e,s} = -E'(rho_{e,s}) u_e^T K_s u_e
@@ -169,7 +238,7 @@ def oracle_solve(nelx, nely, p, d, rho, supports, loads, n_load_cases=1,
         Ks = ks[(int(p_arr[e]), int(d_arr[e]), nu)]
         G = edofs[e]
         for lc in range(L):
-            ue = np.where(G >= 0, u[lc, np.maximum(G, 0)], 0.0)
+            ue = rigid_free(np.where(G >= 0, u[lc, np.maximum(G, 0)], 0.0), int(p_arr[e]))
             w[lc, off[e]:off[e + 1]] = np.einsum("i,sij,j->s", ue, Ks, ue)
     g = -dE[None, :] * w
     out = dict(u=u, c=c, g=g, w=w, n_dof=space.n_dof, n_free=int(free.sum()), free=free,
