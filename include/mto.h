@@ -10,8 +10,12 @@
  *     form of Appendix B: K_e = sum_s E(rho_{e,s}) K_s, with K_s the exact
  *     integral of B^T D0 B (plane stress) over density cell s;
  *   - the displacement u solving K u = f (Eq. eq_comp_1) with supported DOFs
- *     eliminated, by matrix-free Jacobi-preconditioned conjugate gradients
- *     (K is never assembled);
+ *     eliminated, by matrix-free preconditioned conjugate gradients (K is
+ *     never assembled); the preconditioner is chosen per plan
+ *     (mto_params.precond): a multigrid V-cycle with element-block Schwarz
+ *     smoothing, the same V-cycle with l1-Jacobi smoothing, or Jacobi.  The
+ *     paper names no solver; any SPD preconditioner reaches the same u to
+ *     the tolerance;
  *   - the compliance c = f^T u (the objective z^T u with z = f, Sec. 4.1);
  *   - the sensitivity dc/drho_{e,s} = -E'(rho_{e,s}) u_e^T K_s u_e.  The paper
  *     names the sensitivity analysis (Sec. 1, Sec. 2.1) without printing it;
@@ -63,7 +67,8 @@ enum {
   MTO_OK = 0,
   MTO_EINVAL = -1,      /* bad argument: shape, range, NULL pointer, load on a support */
   MTO_ESINGULAR = -2,   /* supports leave a rigid-body mode free */
-  MTO_ENOCONV = -3,     /* PCG hit max_iter before reaching rtol (outputs still written) */
+  MTO_ENOCONV = -3,     /* the true residual misses rtol: PCG hit max_iter, or the residual
+                           stalled above rtol after the restarts (outputs still written) */
   MTO_EBREAKDOWN = -4,  /* p^T K p <= 0 or non-finite value in PCG */
   MTO_EHIP = -5,        /* HIP runtime error */
   MTO_ENOMEM = -6       /* device allocation failed */
@@ -82,8 +87,10 @@ enum { /* element contraction kernels */
   MTO_PATH_PLAIN = 1  /* one thread per element column, FP64 VALU (comparison path) */
 };
 
-enum { /* PCG preconditioners */
-  MTO_PRECOND_JACOBI = 0, /* diagonal of K (default) */
+enum { /* PCG preconditioners (the caller sets one in mto_params; the Python
+          binding's default is MTO_PRECOND_MG_ASM, the fastest on every
+          workload measured) */
+  MTO_PRECOND_JACOBI = 0, /* diagonal of K */
   MTO_PRECOND_MG = 1,     /* one multigrid V-cycle: hierarchic-order injection to the bilinear
                              vertex grid, then geometric coarsening with Galerkin operators,
                              l1-Jacobi smoothing, dense coarsest solve */
@@ -209,13 +216,32 @@ int mto_instance_info(const mto_plan* plan, int32_t inst, int64_t* cell_off, int
                       int64_t* u_off, int64_t* n_dof, int64_t* g_off, int64_t* c_off,
                       int64_t* n_free, int32_t* n_load_cases);
 
-/* One FEA + sensitivity step.  rho [n_cells] in; u [n_u], c [n_load total] out;
- * g [n_g] out (dc/drho per load case) or NULL to skip the sensitivity; u0 [n_u]
- * initial guess or NULL (zero).  Blocks the calling thread until the PCG
- * convergence of every system is known (it polls device flags once per
- * graph launch).  stats (host, may be NULL) receives iteration counts.
- * Returns MTO_OK, MTO_ENOCONV or MTO_EBREAKDOWN (outputs are written in all
- * three cases), or an argument / HIP error. */
+/* One FEA + sensitivity step (Sec. 2.2: the state equation K u = f of
+ * Eq. eq_comp_1 with the SIMP stiffness, the objective c = f^T u of Sec. 4.1,
+ * and its design sensitivities, Sec. 1 and 2.1; the sensitivity formula is
+ * the adjoint result for the self-adjoint compliance, derived, since the
+ * paper does not print it).
+ *   rho  device [n_cells]: densities, each finite and in [0, 1] (Eq. eq_comp_1
+ *        constrains 0 <= rho <= 1); otherwise MTO_EINVAL (outputs undefined)
+ *   u    device [n_u] out; c device [total load cases] out
+ *   g    device [n_g] out (dc/drho per load case) or NULL to skip it
+ *   u0   device [n_u] initial guess or NULL (zero)
+ *   stats host, may be NULL: iteration counts and true residuals
+ * Stop test: ||f - K u||_2 <= rtol ||f||_2 per system, with f - K u evaluated
+ * in double-double at the end of each PCG cycle; restarts from that residual
+ * (at most max_restarts) continue while it misses rtol and still improves.
+ * Returns MTO_OK, MTO_ENOCONV (the residual of some system misses rtol) or
+ * MTO_EBREAKDOWN (outputs are written in these three cases), MTO_EINVAL, or
+ * a HIP error.
+ * The call blocks the calling thread until the convergence of every system
+ * is known.  Convergence is decided on the device, per system, and the host
+ * decides how many captured chunks of iterations to launch: it keeps two
+ * chunks queued past the last progress report it has read (a 16-byte copy
+ * to pinned memory per chunk), so the GPU never waits for the host; only the
+ * host thread waits.  Returning before convergence would need either a
+ * fixed, over-provisioned number of chunks (each costs its launches even
+ * when every system has stopped) or device-side control of the loop.  The
+ * work is enqueued on `stream`, so other streams keep running meanwhile. */
 int mto_solve(mto_plan* plan, const double* rho, double* u, double* c, double* g, const double* u0,
               void* stream, mto_solve_stats* stats);
 
@@ -228,11 +254,18 @@ int mto_batch_capture(mto_plan* plan, const double* rho, double* u, double* c, d
  * the bound rho: same results and return codes as mto_solve. */
 int mto_batch_replay(mto_plan* plan, void* stream, mto_solve_stats* stats);
 
-/* y = K x for every system of the plan (x, y in the u layout).  Supported
- * DOFs of x are ignored and those of y are set to 0, i.e. y = K_ff x_f. */
+/* y = K x for every system of the plan (x, y device arrays in the u layout),
+ * with K assembled from the element matrices of Sec. 2.2 in the composite
+ * per-cell form of Appendix B; the product of each PCG iteration.
+ * Supported DOFs of x are ignored and those of y are set to 0, i.e.
+ * y = K_ff x_f.  rho is not checked (mto_solve checks it).  Asynchronous on
+ * stream. */
 int mto_apply_stiffness(mto_plan* plan, const double* rho, const double* x, double* y, void* stream);
 
-/* g = -E'(rho) u_e^T K_s u_e for given displacements u (u layout). */
+/* g = -E'(rho) u_e^T K_s u_e for given displacements u (device, u layout)
+ * into g (device, g layout): the compliance sensitivity (Sec. 1 and 2.1 name
+ * the sensitivity analysis; the formula is the adjoint result for the
+ * self-adjoint compliance, lambda = -u).  Asynchronous on stream. */
 int mto_sensitivity(mto_plan* plan, const double* rho, const double* u, double* g, void* stream);
 
 /* Adjoint sensitivity of a linear objective J = z^T u (Eq. (1)): for every
@@ -259,9 +292,15 @@ int mto_jacobi_diagonal(mto_plan* plan, const double* rho, double* diag, void* s
 
 /* Times the element contraction of every (p, d) group of the plan for each
  * tile shape (ncol x ks, see mto_set_tile) and keeps the fastest per group.  rho is a
- * representative density field.  report (host, may be NULL) receives a text
- * summary of at most report_len bytes. */
-int mto_autotune(mto_plan* plan, const double* rho, void* stream, char* report, int32_t report_len);
+ * representative density field.  cache_path (host string, may be NULL): a
+ * text file of tile shapes keyed by (GPU architecture, p, d, floor(log2 of
+ * the group's element columns)); a group found there takes the cached
+ * shape without timing, and the shapes timed in this call are added to the
+ * file (a missing file is created; MTO_EINVAL if it cannot be parsed).
+ * report (host, may be NULL) receives a text summary of at most report_len
+ * bytes.  Blocks until the timing is done. */
+int mto_autotune(mto_plan* plan, const double* rho, const char* cache_path, void* stream, char* report,
+                 int32_t report_len);
 
 /* Sets the tile shape of the element contraction for the group with order p
  * and cell grid d (all groups if p <= 0): ncol blocks of 16 element columns

@@ -21,6 +21,15 @@ constexpr int mb_of(int p) { return (ne_of(p) + 15) / 16; }
 // ks[s*ne*ne + i*ne + j] for density cell s of a d x d grid.
 std::vector<double> subcell_tables(int p, int d, double nu);
 
+// Load transfer of the QR-error indicator (Sec. 3.2.3): the order-(p+1)
+// element load integrates the order-p load field against the refined
+// functions.  In 1D, with the hierarchic functions phi_0..phi_p of order p
+// also the first p + 1 of order p + 1, the field with moments g (integrals
+// against phi_0..phi_p) has moment t . g against the new function phi_{p+1},
+// t = m_p^{-1} m[0..p][p+1] (m the unit-interval mass matrix).  The 2D
+// transfer is the tensor product of the 1D one.  Returns t (p + 1 values).
+std::vector<double> qr_load_transfer(int p);
+
 // Rearranges K_s into the MFMA A-operand order: for k-step t (4 consecutive
 // reduction indices k = s*NEP + j) and row block mb, lane l holds
 // Kcat[mb*16 + l%16][4t + l/16], with Kcat[row][s*NEP + j] = K_s[row][j]
@@ -56,7 +65,8 @@ void clear_error();
 int build_instance(const mto_problem& prob, InstanceHost& out, std::string& err);
 
 // Per-iteration scalar state lives in partial-sum arrays; see the kernels.
-enum SysStatus : int32_t { SYS_RUNNING = 0, SYS_CONVERGED = 1, SYS_BREAKDOWN = 2 };
+// SYS_BADINPUT: a density of the solve was not finite or outside [0, 1].
+enum SysStatus : int32_t { SYS_RUNNING = 0, SYS_CONVERGED = 1, SYS_BREAKDOWN = 2, SYS_BADINPUT = 3 };
 
 // Descriptor of one tile of element columns: elements
 // [elem_begin, elem_begin + count) of group `group`, all for system `sys`.

@@ -181,6 +181,13 @@ __device__ __forceinline__ dd_t dd_scale(double a, dd_t y) {
 // only for the true residual.  One block per 16 element columns of a tile
 // (blockIdx.y picks the part), one thread per (row, column); x_e (high and
 // low parts) is gathered once into LDS.
+// The rigid motion r_e through x_e's DOFs 0, 1 (vertex (0,0)) and 3 (vertex
+// (1,0) y) is removed from x_e first: K_s r_e = 0 exactly, so the result is
+// the same operator, but the FP64 tables annihilate rigid motions only to
+// their rounding, and a region joined to the supports through void material
+// moves rigidly by ~1e9 times its deformation; applied to that motion the
+// tables' rounding would put spurious forces of ~1e-7 relative size into
+// the residual.
 template <int P>
 constexpr int dd_rows() { return (ne_of(P) + 3) / 4 * 4; }
 
@@ -205,6 +212,20 @@ __global__ __launch_bounds__(16 * dd_rows<P>()) void k_elem_dd(GroupDev g, const
     ul[row][c] = gi >= 0 ? xlo[t.dof_off + gi] : 0.0;
   }
   __syncthreads();
+  {
+    // rigid motion (a - th y, b + th x): a = x_0, b = x_1, th = x_3 - x_1
+    const dd_t a{uh[0][c], ul[0][c]}, b{uh[1][c], ul[1][c]};
+    const dd_t th = dd_add(dd_t{uh[3][c], ul[3][c]}, dd_t{-b.hi, -b.lo});
+    __syncthreads();
+    if (row < 8) {  // vertex k = row / 2 at (i, j) = (k & 1, k >> 1), component row & 1
+      const int k = row >> 1, i = k & 1, j = k >> 1, dof = 2 * (j * (P + 1) + i) + (row & 1);
+      const dd_t r = (row & 1) ? (i ? dd_add(b, th) : b) : (j ? dd_add(a, dd_t{-th.hi, -th.lo}) : a);
+      const dd_t v = dd_add(dd_t{uh[dof][c], ul[dof][c]}, dd_t{-r.hi, -r.lo});
+      uh[dof][c] = v.hi;
+      ul[dof][c] = v.lo;
+    }
+    __syncthreads();
+  }
   if (row >= NE || !valid) return;
   const int si = g.sidx[row * g.npad + el];
   if (si < 0) return;
@@ -240,6 +261,24 @@ __device__ __forceinline__ int xcd_tile(int i, int T, int run) {
   }
   if (i >= T / (8 * run) * (8 * run)) return i;  // the tail, in order
   return ((k / run) * 8 + x) * run + k % run;
+}
+
+// Removing an element's rigid motion (exact for the products: K_s annihilates
+// rigid motions, its FP64 rounding does not, and a region joined to the
+// supports through void material moves rigidly by ~1e9 times its
+// deformation).  The rigid motion (a - th y, b + th x) takes the element
+// vector's values at DOF 0 (vertex (0,0) x), 1 (its y) and 3 (vertex (1,0)
+// y); only the four vertex functions carry it.  For local DOF `row` of an
+// order-P element with value xv, x0 = value of DOF 0, x1 = of DOF 1,
+// th = x3 - x1: the deformation part, formed as the difference of nearby
+// values first ((xv - x0) and x3 - x1 are exact when the values are within a
+// factor 2 of each other), so its rounding is relative to the deformation,
+// not to the rigid motion.  Non-vertex DOFs are returned unchanged.
+template <int P>
+__device__ __forceinline__ double rigid_free(double xv, int row, double x0, double x1, double th) {
+  const int a = row >> 1, i = a % (P + 1), j = a / (P + 1);
+  if (i > 1 || j > 1) return xv;
+  return (row & 1) ? (xv - x1) - th * i : (xv - x0) + th * j;
 }
 
 // ---------------------------------------------------------------------------
@@ -354,11 +393,14 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int col = c * 16 + n;
+    // the element vector (p = z + beta p_old formed exactly as k_dof1 stores it), rigid motion removed
+    auto val = [&](int row) {
+      const int k = row * TC + col;
+      return pcg ? fma(beta, ush[k], ush[NEP * TC + k]) : ush[k];
+    };
+    const double x0 = val(0), x1 = val(1), th = val(3) - x1;
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-      const int k = (4 * jj + kq) * TC + col;
-      u[c][jj] = pcg ? fma(beta, ush[k], ush[NEP * TC + k]) : ush[k];
-    }
+    for (int jj = 0; jj < NJ; ++jj) u[c][jj] = rigid_free<P>(val(4 * jj + kq), 4 * jj + kq, x0, x1, th);
   }
   d4 acc[MB][NC];
 #pragma unroll
@@ -456,6 +498,11 @@ __global__ __launch_bounds__(64) void k_elem_plain(GroupDev g, const Tile* __res
     if (gi >= 0) v = (mode == ELEM_PCG) ? fma(beta, xs[gi], zs[gi]) : xs[gi];
     u[j] = v;
   }
+  {  // rigid motion removed (see rigid_free)
+    const double x0 = u[0], x1 = u[1], th = u[3] - u[1];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) u[j] = rigid_free<P>(u[j], j, x0, x1, th);
+  }
   const int cb = g.cell[el];
   double* __restrict__ sl = s.slots + t.slot_off;
   for (int row = 0; row < NE; ++row) {
@@ -475,7 +522,9 @@ __global__ __launch_bounds__(64) void k_elem_plain(GroupDev g, const Tile* __res
 // ---------------------------------------------------------------------------
 // Sensitivity: w_{e,s} = lam_e^T K_s u_e (lam = u for compliance) with K_s u_e on MFMA (same A fragments
 // as the matvec), then a segmented dot over the rows each lane holds and a
-// 4-lane butterfly; g = -E'(rho) w.
+// 4-lane butterfly; g = -E'(rho) w.  Both element vectors have their rigid
+// motions (through DOFs 0, 1 and 3) removed first, as in k_elem_dd: K_s
+// annihilates them exactly, its FP64 rounding does not.
 template <int P, int NC>
 __global__ __launch_bounds__(BLOCK) void k_sens_mfma(GroupDev g, const Tile* __restrict__ tiles,
                                                     const double* __restrict__ dE, const double* __restrict__ x,
@@ -504,6 +553,14 @@ __global__ __launch_bounds__(BLOCK) void k_sens_mfma(GroupDev g, const Tile* __r
       const int gi = valid[c] ? g.gidx[(4 * jj + kq) * g.npad + el] : -1;
       u[c][jj] = gi >= 0 ? xs[gi] : 0.0;
       lm[c][jj] = gi >= 0 ? ys[gi] : 0.0;
+    }
+    // rows 0, 1, 3 of column n sit in lanes n, 16 + n, 48 + n (k-step 0)
+    const double ua = __shfl(u[c][0], n), ub = __shfl(u[c][0], 16 + n), uth = __shfl(u[c][0], 48 + n) - ub;
+    const double la = __shfl(lm[c][0], n), lb = __shfl(lm[c][0], 16 + n), lth = __shfl(lm[c][0], 48 + n) - lb;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      u[c][jj] = rigid_free<P>(u[c][jj], 4 * jj + kq, ua, ub, uth);
+      lm[c][jj] = rigid_free<P>(lm[c][jj], 4 * jj + kq, la, lb, lth);
     }
   }
   const double* __restrict__ kf = g.kfrag + lane;
@@ -570,11 +627,21 @@ __global__ __launch_bounds__(64) void k_diag_elem(GroupDev g, const Tile* __rest
 }
 
 // ---------------------------------------------------------------------------
+// SIMP moduli (Sec. 2.2).  A density that is not finite or lies outside
+// [0, 1] sets *bad (when given; every writer stores the same 1) and gets the
+// modulus E0 and derivative 0, so the kernels that follow still see valid
+// numbers while the solve reports the input as invalid.
 __global__ void k_simp(const double* __restrict__ rho, double* __restrict__ E, double* __restrict__ dE, int64_t n,
-                       double E0, double Emin, double q) {
+                       double E0, double Emin, double q, int32_t* __restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double r = rho[i];
+  if (!(r >= 0.0 && r <= 1.0)) {  // NaN fails both tests
+    if (bad) *bad = 1;
+    E[i] = E0;
+    dE[i] = 0.0;
+    return;
+  }
   const double rq1 = pow(r, q - 1.0);
   E[i] = Emin + r * rq1 * (E0 - Emin);
   dE[i] = q * rq1 * (E0 - Emin);
@@ -631,12 +698,14 @@ __global__ __launch_bounds__(VBLOCK) void k_init(PcgDev s, int use_slots) {
 
 __global__ __launch_bounds__(BLOCK) void k_sys_setup(PcgDev s, double rtol2) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // invalid densities (flagged by k_simp): no system runs
+  const bool bad = s.bad_rho && *s.bad_rho != 0;
   for (int sys = wave; sys < s.n_sys; sys += WAVES) {
     const SysDesc& sd = s.sys[sys];
     const double ff = wave_sum(s.part_aux, sd.chunk_begin, sd.chunk_end);
     if (lane == 0) {
       s.tol2[sys] = rtol2 * ff;
-      s.status[sys] = SYS_RUNNING;
+      s.status[sys] = bad ? SYS_BADINPUT : SYS_RUNNING;
       s.iters[sys] = 0;
     }
   }
@@ -979,9 +1048,9 @@ void launch_diag_elem(const GroupDev& g, const Tile* tiles, const double* E, dou
 }
 
 void launch_simp(const double* rho, double* E, double* dE, int64_t n, double E0, double Emin, double q,
-                 hipStream_t st) {
+                 hipStream_t st, int32_t* bad) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_simp, dim3(nblocks(n, BLOCK)), dim3(BLOCK), 0, st, rho, E, dE, n, E0, Emin, q);
+  hipLaunchKernelGGL(k_simp, dim3(nblocks(n, BLOCK)), dim3(BLOCK), 0, st, rho, E, dE, n, E0, Emin, q, bad);
 }
 
 void launch_fill(double* a, double v, int64_t n, hipStream_t st) {

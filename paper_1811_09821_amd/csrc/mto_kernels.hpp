@@ -34,6 +34,7 @@ struct QrGroupDev {
   const int32_t* cell;    // as GroupDev::cell
   const int32_t* eid;     // [n_elems] element index within its instance
   const int32_t* einst;   // [n_elems] instance
+  double t[MTO_MAX_P + 1];  // 1D load transfer to the new order-(p+1) function (qr_load_transfer)
 };
 
 // Element lookup for the refinement indicators: element e of instance i is
@@ -122,6 +123,7 @@ struct PcgDev {
   double* sys_out;         // [n_sys][4]: f.f, f.x, |f-Kx|^2, spare
   int32_t* it_base;        // [1]
   double* progress;        // [2]: systems still running, largest rr / tol2 among them
+  const int32_t* bad_rho;  // [1] or NULL: set by k_simp for an invalid density
 };
 
 // ELEM_APPLY_RUNNING: as ELEM_APPLY, skipping systems whose PCG has stopped.
@@ -152,8 +154,10 @@ void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const d
 void launch_diag_elem(const GroupDev& g, const Tile* tiles, const double* E, double* slots, const SysDesc* sys,
                       const double* table, hipStream_t st);
 
+// E, E' of every cell (Sec. 2.2); bad (device int, may be NULL) is set to 1 if a
+// density is not finite or outside [0, 1] (it is never cleared here)
 void launch_simp(const double* rho, double* E, double* dE, int64_t n, double E0, double Emin, double q,
-                 hipStream_t st);
+                 hipStream_t st, int32_t* bad = nullptr);
 void launch_fill(double* a, double v, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t* a, int32_t v, int64_t n, hipStream_t st);
 // dinv = scale / (sum of slots) on the first system of each instance

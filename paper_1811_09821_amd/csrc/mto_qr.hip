@@ -15,8 +15,10 @@
 //   3. the pinned rows and columns of K' are replaced by identity rows and
 //      K' is factored in place (right-looking Cholesky, two barriers per
 //      column);
-//   4. one wave per load case solves K' u' = f' (f on the embedded DOFs, zero
-//      on the new ones and on the pinned ones) with the rows held in lanes,
+//   4. one wave per load case solves K' u' = f' (f on the embedded DOFs; on
+//      the new ones the integrals of the order-p load field against the new
+//      functions, by the tensor product of the 1D transfer t; zero on the
+//      pinned ones) with the rows held in lanes,
 //      then refines u' twice against a double-double residual computed from
 //      an unfactored copy of K', J^(p+1) = f' . u' / 2 (the load is
 //      self-equilibrated, so the pinned DOFs carry no reaction and the rigid
@@ -194,6 +196,32 @@ __global__ __launch_bounds__(QR_BLOCK) void k_qr(QrGroupDev g, const double* __r
         const bool on = o >= 0 && !pinned(r);
         rh[h] = on ? F[l][o] : 0.0;
         rl[h] = on ? Fl[l][o] : 0.0;
+        if (r < NQ && o < 0) {  // a new function: phi_i(x) phi_j(y) with i or j = P + 1
+          const int a = r >> 1, c = r & 1, i = a % (P + 2), j = a / (P + 2);
+          double hi = 0.0, lo = 0.0;
+          if (i == P + 1 && j == P + 1) {
+            for (int jj = 0; jj <= P; ++jj) {
+              double gh = 0.0, gl = 0.0;
+              for (int ii = 0; ii <= P; ++ii) {
+                const int q = 2 * (jj * (P + 1) + ii) + c;
+                dd_fma(g.t[ii], F[l][q], gh, gl);
+                gl = fma(g.t[ii], Fl[l][q], gl);
+              }
+              dd_fma(g.t[jj], gh, hi, lo);
+              lo = fma(g.t[jj], gl, lo);
+            }
+          } else {
+            const bool alongx = i == P + 1;  // the transfer acts in x (j <= P) or in y (i <= P)
+            for (int k = 0; k <= P; ++k) {
+              const int q = alongx ? 2 * (j * (P + 1) + k) + c : 2 * (k * (P + 1) + i) + c;
+              dd_fma(g.t[k], F[l][q], hi, lo);
+              lo = fma(g.t[k], Fl[l][q], lo);
+            }
+          }
+          const double sh = hi + lo;
+          rh[h] = sh;
+          rl[h] = lo - (sh - hi);
+        }
         b[h] = rh[h];
         xv[h] = 0.0;
       }

@@ -137,6 +137,7 @@ struct mto_plan {
   // sys_out [n_sys][4]
   double* sysblk = nullptr;
   int32_t *status = nullptr, *iters = nullptr, *it_base = nullptr;
+  int32_t* bad_rho = nullptr;  // [1]: set by the moduli kernel for an invalid density
   double* progress = nullptr;  // [2], written by each chunk's last kernel
   double *tol2 = nullptr, *sys_out = nullptr;
   double* h_sysblk = nullptr;  // host pinned copy of sysblk
@@ -201,6 +202,7 @@ struct mto_plan {
     s.sys_out = sys_out;
     s.it_base = it_base;
     s.progress = progress;
+    s.bad_rho = bad_rho;
     return s;
   }
   GroupDev gdev(const GroupHost& g) const {
@@ -303,6 +305,71 @@ int rebuild_tiles(mto_plan* P) {
     HIP_TRY(hipMemcpy(P->d_tiles, P->tiles.data(), P->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
   destroy_graphs(P);
   return MTO_OK;
+}
+
+// ---- autotune cache: one text line per (arch, p, d, size class) ----
+// "arch p d size_class ncol ks us"; size class = floor(log2(element columns
+// of the group)), since the best tile shape of a group of a few elements and
+// of a full mesh differ.
+struct TileKey {
+  std::string arch;
+  int p, d, size_class;
+  bool operator<(const TileKey& o) const {
+    if (arch != o.arch) return arch < o.arch;
+    if (p != o.p) return p < o.p;
+    if (d != o.d) return d < o.d;
+    return size_class < o.size_class;
+  }
+};
+struct TileChoice {
+  int ncol, ks;
+  double us;
+};
+
+int size_class(double columns) {
+  int c = 0;
+  while (columns >= 2.0 && c < 40) {
+    columns *= 0.5;
+    ++c;
+  }
+  return c;
+}
+
+// Reads the cache if the file exists (a missing file is an empty cache);
+// false on a malformed line.
+bool read_tile_cache(const char* path, std::map<TileKey, TileChoice>& out) {
+  FILE* fh = fopen(path, "r");
+  if (!fh) return true;
+  char line[256];
+  bool ok = true;
+  while (fgets(line, sizeof line, fh)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    char arch[64];
+    TileKey k;
+    TileChoice v;
+    if (sscanf(line, "%63s %d %d %d %d %d %lf", arch, &k.p, &k.d, &k.size_class, &v.ncol, &v.ks, &v.us) != 7 ||
+        (v.ncol != 1 && v.ncol != 2 && v.ncol != 4) || v.ks < 1 || v.ks > 8 || k.p < 1 || k.p > MTO_MAX_P ||
+        k.d < 1 || k.d > MTO_MAX_D) {
+      ok = false;
+      break;
+    }
+    k.arch = arch;
+    out[k] = v;
+  }
+  fclose(fh);
+  return ok;
+}
+
+bool write_tile_cache(const char* path, const std::map<TileKey, TileChoice>& c) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* fh = fopen(tmp.c_str(), "w");
+  if (!fh) return false;
+  fprintf(fh, "# element-contraction tile shapes: arch p d size_class(log2 columns) ncol ks us_per_launch\n");
+  for (auto& kv : c)
+    fprintf(fh, "%s %d %d %d %d %d %.3f\n", kv.first.arch.c_str(), kv.first.p, kv.first.d, kv.first.size_class,
+            kv.second.ncol, kv.second.ks, kv.second.us);
+  const bool ok = fclose(fh) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
 }
 
 int check_launch(const char* what) {
@@ -739,6 +806,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_alloc(P, &P->part_rr, 2 * nch)) || (rc = dev_alloc(P, &P->part_aux, 3 * nch)) ||
       (rc = dev_alloc(P, &P->sysblk, 5 * (size_t)P->n_sys)) ||
       (rc = dev_alloc(P, &P->it_base, 1)) || (rc = dev_alloc(P, &P->progress, 2)) ||
+      (rc = dev_alloc(P, &P->bad_rho, 1)) ||
       (rc = dev_alloc(P, &P->tol2, P->n_sys)) ||
       (rc = dev_upload(P, &P->f2f, f2f)))
     return cleanup(rc);
@@ -865,7 +933,9 @@ void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
 
 void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st) {
   const PcgDev s = P->pcg();
-  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  // the densities are checked here; k_sys_setup then stops every system if one is invalid
+  launch_fill_i32(P->bad_rho, 0, 1, st);
+  launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st, P->bad_rho);
   const bool mg = P->prm.precond != MTO_PRECOND_JACOBI;
   // l1-Jacobi level-0 smoother of MTO_PRECOND_MG unless a damping factor is set
   const bool l1 = P->prm.precond == MTO_PRECOND_MG && !(P->prm.mg_omega > 0.0);
@@ -1108,11 +1178,12 @@ int run_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, c
       if ((rc = check_launch("residual"))) return rc;
     }
     if ((rc = fetch(P, st, R))) return rc;
-    bool any_breakdown = false, any_running = false, need_restart = false;
+    bool any_breakdown = false, any_running = false, need_restart = false, any_bad = false;
     for (int s = 0; s < P->n_sys; ++s) {
       iters_total[s] += R.iters[s];
       if (R.status[s] == SYS_BREAKDOWN) any_breakdown = true;
       else if (R.status[s] == SYS_RUNNING) any_running = true;
+      else if (R.status[s] == SYS_BADINPUT) any_bad = true;
       const double ff = R.out[4 * s + 0], res = R.out[4 * s + 2];
       // Restart from the true residual while it misses rtol and the last
       // restart still halved it; once it stalls it sits at the FP64 rounding
@@ -1124,6 +1195,10 @@ int run_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, c
       if (s == 0) r0 = 0.0;
       if (ff > 0.0) r0 = std::max(r0, res / (rtol2 * ff));
     }
+    if (any_bad) {
+      final_status = MTO_EINVAL;
+      break;
+    }
     if (any_breakdown) {
       final_status = MTO_EBREAKDOWN;
       break;
@@ -1132,7 +1207,14 @@ int run_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, c
       final_status = MTO_ENOCONV;
       break;
     }
-    if (!need_restart || restarts >= P->prm.max_restarts) break;
+    if (!need_restart || restarts >= P->prm.max_restarts) {
+      // The stop test is the true residual: a system whose residual still
+      // misses rtol (stalled at the rounding floor, or out of restarts) has
+      // not converged, whatever its PCG recurrence reported.
+      for (int s = 0; s < P->n_sys; ++s)
+        if (!(R.out[4 * s + 2] <= rtol2 * R.out[4 * s + 0])) final_status = MTO_ENOCONV;  // NaN fails too
+      break;
+    }
     ++restarts;
     if (graphs) {
       HIP_TRY(hipGraphLaunch(P->restart_exec, st));
@@ -1163,8 +1245,11 @@ int run_solve(mto_plan* P, const double* rho, double* u, double* c, double* g, c
     }
     stats->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
+  if (final_status == MTO_EINVAL) return fail(MTO_EINVAL, "rho: a density is not finite or lies outside [0, 1]");
   if (final_status == MTO_EBREAKDOWN) return fail(MTO_EBREAKDOWN, "PCG breakdown (p^T K p <= 0 or non-finite)");
-  if (final_status == MTO_ENOCONV) return fail(MTO_ENOCONV, "PCG reached max_iter before rtol");
+  if (final_status == MTO_ENOCONV)
+    return fail(MTO_ENOCONV, "the true residual of a system misses rtol (PCG reached max_iter, or the "
+                             "residual stalled above rtol after its restarts)");
   return MTO_OK;
 }
 
@@ -1402,6 +1487,8 @@ int mto_qr_error(mto_plan* P, const double* rho, const double* u, double* eps, v
     qd.cell = g.cell;
     qd.eid = g.d_eid;
     qd.einst = g.d_einst;
+    const std::vector<double> t = qr_load_transfer(g.p);
+    for (int k = 0; k <= MTO_MAX_P; ++k) qd.t[k] = k < (int)t.size() ? t[k] : 0.0;
     launch_qr(qd, P->E, P->q, P->d_sys, P->d_qr_sys0, P->d_qr_L, P->d_qr_eoff, P->d_qr_nel, eps, st);
   }
   return check_launch("qr_error");
@@ -1456,20 +1543,45 @@ int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol, int32_t ks) {
   return rebuild_tiles(P);
 }
 
-int mto_autotune(mto_plan* P, const double* rho, void* stream, char* report, int32_t report_len) {
+int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* stream, char* report,
+                 int32_t report_len) {
   g_err.clear();
   if (!P || !rho) return fail(MTO_EINVAL, "NULL argument");
   if (P->prm.kernel_path != MTO_PATH_MFMA) return MTO_OK;
   hipStream_t st = (hipStream_t)stream;
+  std::string arch = "unknown";
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) {
+      arch = prop.gcnArchName;
+      const size_t colon = arch.find(':');
+      if (colon != std::string::npos) arch.resize(colon);
+    }
+  }
+  std::map<TileKey, TileChoice> cache;
+  if (cache_path && !read_tile_cache(cache_path, cache))
+    return fail(MTO_EINVAL, std::string("autotune cache: cannot parse ") + cache_path);
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
   launch_fill(P->q, 1.0, P->n_vec, st);
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   std::string rep;
+  bool changed = false;
   const int cand_nc[3] = {1, 2, 4};
   const int cand_ks[4] = {1, 2, 4, 8};
   for (auto& g : P->groups) {
+    const TileKey key{arch, g.p, g.d, size_class(g.flops / (2.0 * g.S * g.ne * g.ne))};
+    auto hit = cache.find(key);
+    if (hit != cache.end() && elem_lds_bytes(g.p, hit->second.ncol, std::min(hit->second.ks, g.S)) <= ELEM_LDS_LIMIT) {
+      g.ncol = hit->second.ncol;
+      g.waves = std::min(hit->second.ks, g.S);
+      char line[200];
+      snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=%d: cached (%s, %d columns class, %.3f us when tuned)\n", g.p,
+               g.d, g.ncol, g.waves, arch.c_str(), key.size_class, hit->second.us);
+      rep += line;
+      continue;
+    }
     double best = 1e30;
     int best_nc = g.ncol, best_ks = g.waves;
     for (int nc : cand_nc)
@@ -1503,11 +1615,20 @@ int mto_autotune(mto_plan* P, const double* rho, void* stream, char* report, int
       }
     g.ncol = best_nc;
     g.waves = best_ks;
+    cache[key] = TileChoice{best_nc, best_ks, 1e3 * best};
+    changed = true;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  for (auto& g : P->groups) {
+    char line[96];
+    snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=%d: chosen\n", g.p, g.d, g.ncol, g.waves);
+    rep += line;
+  }
   int rc = rebuild_tiles(P);
   if (rc) return rc;
+  if (cache_path && changed && !write_tile_cache(cache_path, cache))
+    return fail(MTO_EHIP, std::string("autotune cache: cannot write ") + cache_path);
   if (report && report_len > 0) {
     snprintf(report, (size_t)report_len, "%s", rep.c_str());
   }

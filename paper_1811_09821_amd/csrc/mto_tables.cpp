@@ -12,6 +12,7 @@
 // Accumulation in long double, rounded once to double.
 
 #include <cmath>
+#include <utility>
 #include <vector>
 
 #include "mto_internal.hpp"
@@ -117,6 +118,43 @@ std::vector<double> subcell_tables(int p, int d, double nu) {
     for (int i = 0; i < ne; ++i)
       for (int j = 0; j < i; ++j) out[(size_t)s * ne * ne + i * ne + j] = out[(size_t)s * ne * ne + j * ne + i];
   return out;
+}
+
+std::vector<double> qr_load_transfer(int p) {
+  // 1D mass matrix of the order-(p+1) functions on the unit interval
+  // (dx = dxi / 2), exact with p + 2 Gauss points (degree 2p + 2)
+  const int n = p + 2;
+  ld gx[16], gw[16];
+  gauss_legendre(n, gx, gw);
+  std::vector<ld> m((size_t)n * n, 0);
+  for (int q = 0; q < n; ++q) {
+    ld phi[16], dphi[16];
+    shape_1d(p + 1, gx[q], phi, dphi);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) m[(size_t)i * n + k] += gw[q] * phi[i] * phi[k] / 2;
+  }
+  // t solves m_p t = m[0..p][p+1] (m_p: the leading (p+1) x (p+1) block, the
+  // order-p mass matrix), by Gaussian elimination with partial pivoting
+  const int k1 = p + 1;
+  std::vector<ld> A((size_t)k1 * (k1 + 1));
+  for (int i = 0; i < k1; ++i) {
+    for (int k = 0; k < k1; ++k) A[(size_t)i * (k1 + 1) + k] = m[(size_t)i * n + k];
+    A[(size_t)i * (k1 + 1) + k1] = m[(size_t)i * n + (p + 1)];
+  }
+  for (int c = 0; c < k1; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k1; ++r)
+      if (std::fabs(A[(size_t)r * (k1 + 1) + c]) > std::fabs(A[(size_t)piv * (k1 + 1) + c])) piv = r;
+    for (int k = 0; k <= k1; ++k) std::swap(A[(size_t)c * (k1 + 1) + k], A[(size_t)piv * (k1 + 1) + k]);
+    for (int r = 0; r < k1; ++r) {
+      if (r == c) continue;
+      const ld fac = A[(size_t)r * (k1 + 1) + c] / A[(size_t)c * (k1 + 1) + c];
+      for (int k = c; k <= k1; ++k) A[(size_t)r * (k1 + 1) + k] -= fac * A[(size_t)c * (k1 + 1) + k];
+    }
+  }
+  std::vector<double> t(k1);
+  for (int i = 0; i < k1; ++i) t[i] = (double)(A[(size_t)i * (k1 + 1) + k1] / A[(size_t)i * (k1 + 1) + i]);
+  return t;
 }
 
 std::vector<double> mfma_fragments(const std::vector<double>& ks, int p, int d) {

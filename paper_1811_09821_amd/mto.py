@@ -108,7 +108,7 @@ def _load():
         "mto_sensitivity": ([vp, vp, vp, vp, vp], i32),
         "mto_jacobi_diagonal": ([vp, vp, vp, vp], i32),
         "mto_weighted_sensitivity": ([vp, vp, vp, vp, vp], i32),
-        "mto_autotune": ([vp, vp, vp, ctypes.c_char_p, i32], i32),
+        "mto_autotune": ([vp, vp, ctypes.c_char_p, vp, ctypes.c_char_p, i32], i32),
         "mto_set_tile": ([vp, i32, i32, i32, i32], i32),
         "mto_time_contraction": ([vp, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "mto_plan_destroy": ([vp], None),
@@ -390,10 +390,13 @@ class Plan:
         _check(_lib.mto_jacobi_diagonal(self.handle, _ptr(rho), _ptr(dg), _stream(stream)))
         return dg
 
-    def autotune(self, rho, stream=None):
+    def autotune(self, rho, cache=None, stream=None):
+        """Tile shape per (p, d) group; `cache` is an optional path of the
+        tile-shape cache file (see mto.h).  Returns the text report."""
         _f64_cuda(rho, self.info["n_cells"], "rho")
         buf = ctypes.create_string_buffer(8192)
-        _check(_lib.mto_autotune(self.handle, _ptr(rho), _stream(stream), buf, len(buf)))
+        path = None if cache is None else os.fsencode(cache)
+        _check(_lib.mto_autotune(self.handle, _ptr(rho), path, _stream(stream), buf, len(buf)))
         self._bound = None
         return buf.value.decode()
 

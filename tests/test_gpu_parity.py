@@ -1,9 +1,9 @@
 """GPU parity: the HIP library (through the C ABI) against the CPU oracle on
 the same seeded inputs.
 
-Tolerances (relative, norm-wise, written here): u and c within 1e-8, dc/drho
-within 1e-7 (both the 2-norm and the max-norm ratios), with PCG run to a
-relative residual of 1e-11.  The element contraction itself (no solve) is
+Tolerances (relative, norm-wise, written here): u and c within 1e-8 (u in
+both the 2-norm and the max-norm ratios), dc/drho within 1e-7 (both ratios),
+with PCG run to a relative residual of 1e-11.  The element contraction itself (no solve) is
 compared at 1e-13: it is one FP64 product with a different summation order.
 """
 
@@ -63,6 +63,8 @@ def check_solution(plan, prs, u, c, g, stats):
         o = oracle_solve(**pr.oracle_args())
         uu = us[i].cpu().numpy()
         assert rel(uu, o["u"]) < U_TOL, (pr.name, rel(uu, o["u"]))
+        for lc in range(pr.n_load_cases):  # small edge and interior modes must not hide errors
+            assert rel_max(uu[lc], o["u"][lc]) < U_TOL, (pr.name, lc, rel_max(uu[lc], o["u"][lc]))
         cc = cs[i].cpu().numpy()
         assert np.all(np.abs(cc - o["c"]) <= C_TOL * np.abs(o["c"])), (pr.name, cc, o["c"])
         gg = gs[i].cpu().numpy()
@@ -374,3 +376,90 @@ def test_time_contraction_modes_leave_solve_exact(cuda):
     b = plan.solve(rho)
     for x, y in zip(a[:3], b[:3]):
         assert torch.equal(x, y)
+
+
+def test_stalled_true_residual_is_noconv(cuda):
+    """A true residual that misses rtol is MTO_ENOCONV, with finite outputs
+    written: rtol 1e-20 with no restarts (the PCG recurrence meets it, but one
+    FP64 correction cannot bring the double-double true residual there), and
+    rtol 1e-40 with three restarts (below what double-double refinement can
+    reach, so the restarts stall).  The same plan at the default tolerance is
+    MTO_OK."""
+    m = mto()
+    pr = P.small_mixed(10, 5, seed=43)
+    rho = torch.tensor(pr.rho, device=cuda)
+    for rtol, restarts in ((1e-20, 0), (1e-40, 3)):
+        plan = m.Plan(pr, rtol=rtol, max_restarts=restarts, max_iter=3000)
+        with pytest.raises(m.MtoError) as ei:
+            plan.solve(rho)
+        assert ei.value.code == m.MTO_ENOCONV
+        u, c, g, st = plan.solve(rho, allow_noconv=True)
+        assert st["status"] == m.MTO_ENOCONV and torch.isfinite(u).all() and torch.isfinite(g).all()
+        assert max(st["true_rel_residual"]) > rtol
+        plan.capture(rho)
+        with pytest.raises(m.MtoError) as ei:
+            plan.replay()
+        assert ei.value.code == m.MTO_ENOCONV
+    u, c, g, st = m.Plan(pr).solve(rho)
+    assert st["status"] == m.MTO_OK and max(st["true_rel_residual"]) <= 1e-11
+
+
+@pytest.mark.parametrize("bad", [float("nan"), -0.25, 1.5, float("inf")])
+def test_invalid_density_rejected(cuda, bad):
+    """A density that is not finite or outside [0, 1] (Eq. (1) bounds it to
+    [0, 1]): mto_solve and the graph replay return MTO_EINVAL without
+    iterating, and the next solve of the same plan with valid densities is
+    bit-identical to a fresh plan's."""
+    m = mto()
+    pr = P.small_mixed(9, 5, seed=44, n_loads=2)
+    plan = m.Plan(pr)
+    good = torch.tensor(pr.rho, device=cuda)
+    rho = good.clone()
+    rho[pr.n_cells // 3] = bad
+    with pytest.raises(m.MtoError) as ei:
+        plan.solve(rho)
+    assert ei.value.code == m.MTO_EINVAL and "density" in str(ei.value)
+    ub, cb, gb = plan.capture(rho)
+    with pytest.raises(m.MtoError) as ei:
+        plan.replay()
+    assert ei.value.code == m.MTO_EINVAL
+    rho.copy_(good)
+    st = plan.replay()
+    assert st["status"] == m.MTO_OK
+    u, c, g, st2 = m.Plan(pr).solve(good)
+    assert torch.equal(ub, u) and torch.equal(cb, c) and torch.equal(gb, g)
+    u2, c2, g2, _ = plan.solve(good)
+    assert torch.equal(u2, u) and torch.equal(c2, c)
+    # the bounds themselves are valid densities
+    edge = good.clone()
+    edge[0], edge[1] = 0.0, 1.0
+    plan.solve(edge)
+
+
+def test_autotune_cache(cuda, tmp_path):
+    """The tile-shape cache: a first autotune times every group and writes one
+    line per (arch, p, d, size class); a second plan of the same mesh takes
+    every shape from the file without timing and solves to the same bits as
+    the first; a malformed file is MTO_EINVAL."""
+    m = mto()
+    pr = P.small_mixed(16, 8, seed=45)
+    rho = torch.tensor(pr.rho, device=cuda)
+    path = tmp_path / "tiles.txt"
+    a = m.Plan(pr)
+    rep_a = a.autotune(rho, cache=str(path))
+    lines = [ln for ln in path.read_text().splitlines() if not ln.startswith("#")]
+    assert len(lines) == a.info["n_groups"], (lines, rep_a)
+    assert "cached" not in rep_a
+    b = m.Plan(pr)
+    rep_b = b.autotune(rho, cache=str(path))
+    assert rep_b.count("cached") == a.info["n_groups"], rep_b
+    assert sorted(l for l in rep_a.splitlines() if l.endswith("chosen")) == \
+        sorted(l for l in rep_b.splitlines() if l.endswith("chosen"))
+    ua, ca, ga, _ = a.solve(rho)
+    ub, cb, gb, _ = b.solve(rho)
+    assert torch.equal(ua, ub) and torch.equal(ca, cb) and torch.equal(ga, gb)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 3 4 nonsense\n")
+    with pytest.raises(m.MtoError) as ei:
+        m.Plan(pr).autotune(rho, cache=str(bad))
+    assert ei.value.code == m.MTO_EINVAL
