@@ -17,13 +17,18 @@ cell centres, so it does not depend on d.
 
 Density map: rho = clip(0.5 + 0.5 z - t, rho_min, 1) with the shift t found
 by bisection so that the area-weighted mean density equals the volume
-fraction; cells on the load paths are solid (rho = 1): a pad of radius
-LOAD_PAD around each point load and a beam of half-width BEAM_HALF_WIDTH from
-the clamped edge to it, as the paper's optimised designs carry every load
-through material to the supports.
+fraction.  This plain field is the default of the five workload
+configurations.  With ``solid_paths=True`` the cells on the load paths are
+also made solid (rho = 1): a pad of radius LOAD_PAD around each point load
+and a beam of half-width BEAM_HALF_WIDTH from the clamped edge to it, as the
+paper's optimised designs carry every load through material to the
+supports.  That eased field conditions K better; the small parity meshes and
+the force inverter use it, so that a tiny mesh does not leave its load on
+void material.
 
 dp rule for mixed meshes (an element is 'solid' when z at its centre >= 0,
-i.e. the [0, 1]-mapped field is >= 0.5, or it lies on a load path): elements whose centre lies within 3
+i.e. the [0, 1]-mapped field is >= 0.5, or, with solid_paths, it lies on a
+load path): elements whose centre lies within 3
 element widths of an element on the solid/void contour (one with a
 4-neighbour of the other class) get p = 4, d = 5; other solid elements get
 p = 2, d = 2 and other void elements p = 1, d = 1.  Then neighbouring orders
@@ -189,7 +194,7 @@ def smooth_orders(p, nelx, nely, max_jump=2):
 
 def dp_rule(nelx, nely, fieldfn, band=3.0, loads=()):
     """Per-element (p, d) of the mixed-mesh configs (see the module docstring);
-    elements on the load paths count as solid."""
+    elements on the load paths of `loads` (empty: none) count as solid."""
     from scipy import ndimage
 
     ex, ey = np.meshgrid(np.arange(nelx) + 0.5, np.arange(nely) + 0.5)
@@ -229,30 +234,34 @@ def mbb_20x10(seed=1):
     return Problem("mbb20x10_p1d2", nelx, nely, p, d, rho, sup, loads, 1)
 
 
-def cantilever_uniform(nelx=160, nely=80, p=3, d=4, sigma=8.0, volfrac=0.4, seed=2):
+def cantilever_uniform(nelx=160, nely=80, p=3, d=4, sigma=8.0, volfrac=0.4, seed=2, solid_paths=False):
     """Clamped-left cantilever with uniform (p, d), density from the random
     field (length scale sigma) mapped to [0.001, 1] at mean volfrac, unit
-    downward load at the mid-right vertex."""
+    downward load at the mid-right vertex (solid_paths: see the module
+    docstring)."""
     pa = np.full(nelx * nely, p, np.int8)
     da = np.full(nelx * nely, d, np.int8)
     fld = RandomField(seed, sigma, nelx, nely)
     x, y, w = cell_centres(nelx, nely, da)
     loads = [(nelx, nely // 2, 0.0, -1.0, 0)]
-    rho = map_density(fld(x, y), w, volfrac, solid=load_paths(x, y, loads))
+    rho = map_density(fld(x, y), w, volfrac, solid=load_paths(x, y, loads) if solid_paths else None)
     return Problem(f"cantilever{nelx}x{nely}_p{p}d{d}", nelx, nely, pa, da, rho,
                    cantilever_supports(), loads, 1)
 
 
-def mixed_cantilever(nelx=200, nely=100, volfrac=0.5, seed=3, load_vy=None, sigma=MIXED_SIGMA):
+def mixed_cantilever(nelx=200, nely=100, volfrac=0.5, seed=3, load_vy=None, sigma=MIXED_SIGMA,
+                     solid_paths=False):
     """Clamped-left cantilever on a dp-mixed mesh from the dp rule; point loads
-    f_y = -1 at the given right-edge vertices (one load case each)."""
+    f_y = -1 at the given right-edge vertices (one load case each);
+    solid_paths: see the module docstring."""
     fld = RandomField(seed, sigma, nelx, nely)
     if load_vy is None:
         load_vy = [nely // 2]
     loads = [(nelx, int(vy), 0.0, -1.0, lc) for lc, vy in enumerate(load_vy)]
-    p, d = dp_rule(nelx, nely, fld, loads=loads)
+    paths = loads if solid_paths else ()
+    p, d = dp_rule(nelx, nely, fld, loads=paths)
     x, y, w = cell_centres(nelx, nely, d)
-    rho = map_density(fld(x, y), w, volfrac, solid=load_paths(x, y, loads))
+    rho = map_density(fld(x, y), w, volfrac, solid=load_paths(x, y, paths) if solid_paths else None)
     return Problem(f"mixed{nelx}x{nely}", nelx, nely, p, d, rho, cantilever_supports(), loads,
                    len(load_vy))
 
@@ -283,13 +292,14 @@ def force_inverter(nelx=40, nely=20, p=2, d=4, volfrac=0.45, seed=7, sigma=4.0):
     return pr
 
 
-def mixed_200x100(seed=3):
-    return mixed_cantilever(200, 100, 0.5, seed)
+def mixed_200x100(seed=3, solid_paths=False):
+    return mixed_cantilever(200, 100, 0.5, seed, solid_paths=solid_paths)
 
 
-def batch_instances(n=64, first_seed=100, lo=20, hi=160):
+def batch_instances(n=64, first_seed=100, lo=20, hi=160, solid_paths=False):
     """Uneven batch: nelx = 2 round(exp(U[ln lo, ln hi])), nely = nelx / 2,
-    dp rule, mean density 0.5, 1-3 load cases at distinct right-edge vertices."""
+    dp rule, mean density 0.5, 1-3 load cases at distinct right-edge vertices
+    (solid_paths: see the module docstring)."""
     out = []
     for k in range(n):
         seed = first_seed + k
@@ -298,25 +308,28 @@ def batch_instances(n=64, first_seed=100, lo=20, hi=160):
         nely = nelx // 2
         nl = int(rng.integers(1, 4))
         vys = rng.choice(np.arange(1, nely), size=nl, replace=False)
-        prob = mixed_cantilever(nelx, nely, 0.5, seed, load_vy=sorted(int(v) for v in vys))
+        prob = mixed_cantilever(nelx, nely, 0.5, seed, load_vy=sorted(int(v) for v in vys),
+                                solid_paths=solid_paths)
         prob.name = f"batch{k}_{nelx}x{nely}"
         out.append(prob)
     return out
 
 
-def autograd_400x200(seed=5):
+def autograd_400x200(seed=5, solid_paths=False):
     """400 x 200 mixed mesh, mean density 0.2, three load cases at right-edge
     vertices nely/4, nely/2, 3 nely/4."""
     nelx, nely = 400, 200
-    return mixed_cantilever(nelx, nely, 0.2, seed, load_vy=[nely // 4, nely // 2, 3 * nely // 4])
+    return mixed_cantilever(nelx, nely, 0.2, seed, load_vy=[nely // 4, nely // 2, 3 * nely // 4],
+                            solid_paths=solid_paths)
 
 
-def small_mixed(nelx, nely, seed, volfrac=0.5, sigma=3.0, n_loads=1):
+def small_mixed(nelx, nely, seed, volfrac=0.5, sigma=3.0, n_loads=1, solid_paths=True):
     """Small mixed-mesh cantilever for parity tests (same dp rule, shorter
-    field length so a small mesh still has all four (p, d) groups)."""
+    field length so a small mesh still has all four (p, d) groups; solid load
+    paths by default, so that a load is not left on void)."""
     nl = n_loads
     vys = [max(1, (k + 1) * nely // (nl + 1)) for k in range(nl)]
-    return mixed_cantilever(nelx, nely, volfrac, seed, load_vy=vys, sigma=sigma)
+    return mixed_cantilever(nelx, nely, volfrac, seed, load_vy=vys, sigma=sigma, solid_paths=solid_paths)
 
 
 def uniform_random(nelx, nely, p, d, seed, supports=None, loads=None, n_load_cases=1,
@@ -334,16 +347,18 @@ def uniform_random(nelx, nely, p, d, seed, supports=None, loads=None, n_load_cas
     return Problem(f"uniform{nelx}x{nely}", nelx, nely, pa, da, rho, supports, loads, n_load_cases)
 
 
-def config(k):
-    """The five workload configurations, by number 1..5 (4 returns a list)."""
+def config(k, solid_paths=False):
+    """The five workload configurations, by number 1..5 (4 returns a list).
+    Default: the plain random density field; solid_paths=True gives the eased
+    field with solid load paths (configs 2-5; config 1 has i.i.d. densities)."""
     if k == 1:
         return mbb_20x10()
     if k == 2:
-        return cantilever_uniform()
+        return cantilever_uniform(solid_paths=solid_paths)
     if k == 3:
-        return mixed_200x100()
+        return mixed_200x100(solid_paths=solid_paths)
     if k == 4:
-        return batch_instances()
+        return batch_instances(solid_paths=solid_paths)
     if k == 5:
-        return autograd_400x200()
+        return autograd_400x200(solid_paths=solid_paths)
     raise ValueError(k)
