@@ -262,6 +262,25 @@ int mto_batch_replay(mto_plan* plan, void* stream, mto_solve_stats* stats);
  * stream. */
 int mto_apply_stiffness(mto_plan* plan, const double* rho, const double* x, double* y, void* stream);
 
+/* Size of the device scratch array of mto_apply_stiffness_noalloc (per GPU,
+ * held from the library's first use on that GPU until the process ends). */
+#define MTO_NOALLOC_SCRATCH_BYTES (32 * 1024 * 1024)
+
+/* mto_apply_stiffness for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and result (y = K x, u layout, supported DOFs
+ * of y set to 0); it calls no hipMalloc/hipFree.  Its scratch (cell moduli,
+ * gathered x, element slots: 8 (2 n_cells + n_free_total + slots) bytes,
+ * slots being 4 per free vertex DOF, 2 per free edge DOF and 1 per free
+ * interior DOF of every system) lives in one static device array of
+ * MTO_NOALLOC_SCRATCH_BYTES per GPU, shared by every call on that GPU: calls
+ * that overlap on one GPU (other streams, other threads, other plans) race
+ * and must be serialised by the caller.  The current device must be the
+ * plan's device.  The first call on a device looks the array's address up
+ * (no allocation).  MTO_EINVAL if the plan needs more scratch than the
+ * array holds, or on NULL arguments.  Asynchronous on stream. */
+int mto_apply_stiffness_noalloc(mto_plan* plan, const double* rho, const double* x, double* y, void* stream);
+
 /* g = -E'(rho) u_e^T K_s u_e for given displacements u (device, u layout)
  * into g (device, g layout): the compliance sensitivity (Sec. 1 and 2.1 name
  * the sensitivity analysis; the formula is the adjoint result for the

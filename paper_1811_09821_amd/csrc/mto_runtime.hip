@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1348,6 +1349,72 @@ int mto_apply_stiffness(mto_plan* P, const double* rho, const double* x, double*
   launch_fill(y, 0.0, P->n_u, st);
   launch_assemble_to_full(s, P->f2f, y, 0, st);
   return check_launch("apply_stiffness");
+}
+
+}  // extern "C"
+
+// ---- allocation-free stiffness product --------------------------------------
+// Scratch of mto_apply_stiffness_noalloc: the cell moduli and their
+// derivatives, the gathered x and the element slots, in one file-scope device
+// array that every call on a device shares.  Host code uses the array only
+// through the device address hipGetSymbolAddress gives for it on each device.
+namespace {
+constexpr int64_t NOALLOC_DOUBLES = MTO_NOALLOC_SCRATCH_BYTES / 8;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+std::mutex g_scratch_mu;
+double* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of `scratch` on device dev (the current device), looked
+// up once per device.
+int scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(MTO_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(MTO_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return MTO_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mto_apply_stiffness_noalloc(mto_plan* P, const double* rho, const double* x, double* y, void* stream) {
+  g_err.clear();
+  if (!P || !rho || !x || !y) return fail(MTO_EINVAL, "NULL argument");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != P->device) return fail(MTO_EINVAL, "the current device is not the plan's device");
+  const int64_t need = 2 * P->n_cells_tot + P->n_vec + P->n_slots_tot;
+  if (need > NOALLOC_DOUBLES)
+    return fail(MTO_EINVAL, "mto_apply_stiffness_noalloc: the plan needs " + std::to_string(8 * need) +
+                                " bytes of scratch, more than the " + std::to_string(MTO_NOALLOC_SCRATCH_BYTES) +
+                                " the library holds");
+  double* base = nullptr;
+  int rc = scratch_address(dev, &base);
+  if (rc) return rc;
+  double* E = base;
+  double* dE = E + P->n_cells_tot;
+  double* q = dE + P->n_cells_tot;
+  double* slots = q + P->n_vec;
+  hipStream_t st = (hipStream_t)stream;
+  PcgDev s = P->pcg();
+  s.q = q;
+  s.slots = slots;
+  launch_simp(rho, E, dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  launch_gather_free(s, P->f2f, x, q, st);
+  // slots that no element writes (missing neighbours) must read as zero; the
+  // array keeps the previous call's contents
+  launch_fill(slots, 0.0, P->n_slots_tot, st);
+  for (auto& g : P->groups) launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, E, q, s, ELEM_APPLY, 0, st);
+  launch_fill(y, 0.0, P->n_u, st);
+  launch_assemble_to_full(s, P->f2f, y, 0, st);
+  return check_launch("apply_stiffness_noalloc");
 }
 
 int mto_sensitivity(mto_plan* P, const double* rho, const double* u, double* g, void* stream) {

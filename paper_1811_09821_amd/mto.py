@@ -105,6 +105,7 @@ def _load():
         "mto_batch_capture": ([vp, vp, vp, vp, vp, vp], i32),
         "mto_batch_replay": ([vp, vp, ctypes.POINTER(_Stats)], i32),
         "mto_apply_stiffness": ([vp, vp, vp, vp, vp], i32),
+        "mto_apply_stiffness_noalloc": ([vp, vp, vp, vp, vp], i32),
         "mto_sensitivity": ([vp, vp, vp, vp, vp], i32),
         "mto_jacobi_diagonal": ([vp, vp, vp, vp], i32),
         "mto_weighted_sensitivity": ([vp, vp, vp, vp, vp], i32),
@@ -135,6 +136,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("mto_last_error", "mto_version", "mto_plan_create", "mto_batch_plan_create", "mto_plan_info",
             "mto_instance_info", "mto_solve", "mto_batch_capture", "mto_batch_replay", "mto_apply_stiffness",
+            "mto_apply_stiffness_noalloc",
             "mto_sensitivity", "mto_jacobi_diagonal", "mto_weighted_sensitivity", "mto_autotune", "mto_set_tile",
             "mto_time_contraction", "mto_plan_destroy", "mto_qr_error", "mto_adjoint_sensitivity", "mto_kelly_indicator",
             "mto_density_indicator", "mto_dp_update", "mto_qr_update", "mto_filter_create", "mto_filter_apply", "mto_filter_grad",
@@ -325,6 +327,15 @@ class Plan:
         _f64_cuda(x, self.info["n_u"], "x")
         y = self._empty(self.info["n_u"], rho)
         _check(_lib.mto_apply_stiffness(self.handle, _ptr(rho), _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def apply_stiffness_noalloc(self, rho, x, y, stream=None):
+        """y = K x into the caller's y, with the library's static scratch (no
+        device allocation in the library; see mto.h)."""
+        _f64_cuda(rho, self.info["n_cells"], "rho")
+        _f64_cuda(x, self.info["n_u"], "x")
+        _f64_cuda(y, self.info["n_u"], "y")
+        _check(_lib.mto_apply_stiffness_noalloc(self.handle, _ptr(rho), _ptr(x), _ptr(y), _stream(stream)))
         return y
 
     def sensitivity(self, rho, u, stream=None):
