@@ -324,8 +324,11 @@ int mto_autotune(mto_plan* plan, const double* rho, const char* cache_path, void
 /* Sets the tile shape of the element contraction for the group with order p
  * and cell grid d (all groups if p <= 0): ncol blocks of 16 element columns
  * per tile (1, 2 or 4) and ks waves per tile splitting the density cells
- * (1..8, clamped to d*d).  MTO_EINVAL if the shape needs more than 64 KB of
- * LDS.  Invalidates captured graphs. */
+ * (1..8, clamped to d*d); or, with ks = 0 (p >= 3 only, ncol 1 or 2), the
+ * LDS-staged contraction: 4 waves of 16 ncol columns each share the cell
+ * tables, staged in LDS one cell ahead (with p <= 0 the groups of p < 3 keep
+ * their shape).  MTO_EINVAL if the shape needs more LDS than the kernel
+ * takes (64 KB; 160 KB for ks = 0).  Invalidates captured graphs. */
 int mto_set_tile(mto_plan* plan, int32_t p, int32_t d, int32_t ncol, int32_t ks);
 
 /* Average time (ms, from HIP events on `stream`) of one PCG search-direction

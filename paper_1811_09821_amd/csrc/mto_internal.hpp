@@ -36,6 +36,12 @@ std::vector<double> qr_load_transfer(int p);
 // (zero outside n_e).  Result length T*MB*64 with T = d*d*NEP/4.
 std::vector<double> mfma_fragments(const std::vector<double>& ks, int p, int d);
 
+// The columns of K_s at the element's 8 vertex DOFs (local DOFs 0..3 and
+// 2(p+1)..2(p+1)+3, k = 0..7 in that order) as MFMA A operands: for k-step jj
+// (k = 4 jj .. 4 jj + 3) and row block mb, lane l holds
+// K_s[mb*16 + l%16][vertex DOF 4 jj + l/16] (zero past n_e).  Length S*2*MB*64.
+std::vector<double> vertex_fragments(const std::vector<double>& ks, int p, int d);
+
 // One design instance after numbering.
 struct InstanceHost {
   int nelx = 0, nely = 0, L = 1;
@@ -79,8 +85,8 @@ struct Tile {
   int32_t sys;
   int32_t elem_begin;
   int32_t count;
-  int32_t pc_begin;   // the system's chunk (partial-sum) range
-  int32_t pc_end;
+  int32_t pc_begin;   // the system's chunk (partial-sum) range; in the tiles of the Schwarz
+  int32_t pc_end;     //   application (GroupDev::ms_*) pc_begin is the instance's number of systems
 };
 
 // A chunk of the free DOFs of one system for the vector kernels, with the

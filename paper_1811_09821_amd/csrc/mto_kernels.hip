@@ -300,7 +300,8 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
   const int ks = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Tile t = tiles[g.tile_begin + xcd_tile(blockIdx.x, g.n_tiles, g.xcd_run)];
-  if (mode == ELEM_APPLY_RUNNING && s.status[t.sys] != SYS_RUNNING) return;
+  // a stopped system has nothing to do (PCG mode also checks this iteration's residual below)
+  if (mode != ELEM_APPLY && s.status[t.sys] != SYS_RUNNING) return;
   const bool pcg = mode == ELEM_PCG;
   const int n = lane & 15, kq = lane >> 4;
   // Everything that depends only on the tile is requested before the gather
@@ -465,6 +466,245 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (sidx[c][b][r] >= 0) sl[sidx[c][b][r]] = acc[b][c][r];
+}
+
+// ---------------------------------------------------------------------------
+// Element contraction with the cell tables staged in LDS, for the groups whose
+// tables are large (p >= 3): one block of 4 waves per tile of 64 NC element
+// columns, wave w taking columns [16 NC w, 16 NC (w + 1)).  Every wave runs all
+// density cells.  The A fragments of the next cell are loaded from L2 by the
+// whole block into the other half of an LDS double buffer while the current
+// cell's MFMAs run, so each fragment is read from L2 once per 64 NC columns
+// (instead of once per 16 NC in k_elem_mfma) and from LDS by the four waves.
+// The gathered element vectors (p = z + beta p_old formed once, rigid motion
+// removed as in k_elem_mfma) sit in LDS as well; each wave writes its own
+// columns' slots.  Results are the same sums as k_elem_mfma with ks = 1.
+template <int P, int NC>
+__global__ __launch_bounds__(256) void k_elem_mfma_lds(GroupDev g, const Tile* __restrict__ tiles,
+                                                      const double* __restrict__ E, const double* __restrict__ xin,
+                                                      PcgDev s, int mode, int it_k) {
+  constexpr int NE = ne_of(P), NEP = nep_of(P), MB = mb_of(P), NJ = NEP / 4, WC = 16 * NC, TC = 4 * WC;
+  constexpr int FR = NJ * MB * 64;         // doubles of one cell's A fragments
+  constexpr int FPT = (FR + 255) / 256;    // of those, per thread
+  constexpr int NT = NEP * TC, GPT = (NT + 255) / 256;  // gathered entries, per thread
+  extern __shared__ double lds[];
+  double* afr = lds;                // [2][FR]
+  double* ush = lds + 2 * FR;       // [NEP][TC] element vectors
+  double* scal = ush + NT;          // [2] beta, active
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Tile t = tiles[g.lds_tile_begin + xcd_tile(blockIdx.x, g.lds_n_tiles, g.xcd_run)];
+  // a stopped system has nothing to do (PCG mode also checks this iteration's residual below)
+  if (mode != ELEM_APPLY && s.status[t.sys] != SYS_RUNNING) return;
+  const bool pcg = mode == ELEM_PCG;
+  const int n = lane & 15, kq = lane >> 4;
+  // this wave's columns: cell offsets and scatter slots, requested first
+  int cellb[NC];
+  bool valid[NC];
+  int sidx[NC][MB][4];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int col = wave * WC + c * 16 + n;
+    valid[c] = col < t.count;
+    cellb[c] = valid[c] ? g.cell[t.elem_begin + col] : 0;
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = b * 16 + kq + 4 * r;
+        sidx[c][b][r] = (valid[c] && row < NE) ? g.sidx[row * g.npad + t.elem_begin + col] : -1;
+      }
+  }
+  // cell 0's fragments: global loads now, LDS stores after the gather loads are issued
+  const double* __restrict__ kf = g.kfrag;
+  double stg[FPT];
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) {
+    const int i = tid + 256 * k;
+    stg[k] = kf[i < FR ? i : FR - 1];
+  }
+  // the element vectors: clamped, unconditional loads (column to the tile's
+  // last element, DOF to the system's first), zeroed where absent
+  double gv[GPT], gz[GPT];
+  const double* __restrict__ xs = xin + t.dof_off;
+  const double* __restrict__ zs = s.z + t.dof_off;
+  {
+    int gi[GPT];
+#pragma unroll
+    for (int k = 0; k < GPT; ++k) {
+      const int e = tid + 256 * k;
+      const int ec = e < NT ? e : NT - 1;
+      const int row = ec / TC, col = ec - row * TC;
+      const int gl = g.gidx[row * g.npad + t.elem_begin + (col < t.count ? col : t.count - 1)];
+      gi[k] = (e < NT && col < t.count) ? gl : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < GPT; ++k) {
+      const int gc = gi[k] >= 0 ? gi[k] : 0;
+      const double xv = xs[gc];
+      gv[k] = gi[k] >= 0 ? xv : 0.0;
+      gz[k] = 0.0;
+      if (pcg) {
+        const double zz = zs[gc];
+        gz[k] = gi[k] >= 0 ? zz : 0.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) {
+    const int i = tid + 256 * k;
+    if (i < FR) afr[i] = stg[k];
+  }
+  if (pcg && wave == 0) {
+    const Scal sc = pcg_state(s, t.sys, t.pc_begin, t.pc_end, *s.it_base + it_k, true);
+    if (lane == 0) {
+      scal[0] = sc.beta;
+      scal[1] = sc.active ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  if (pcg && scal[1] == 0.0) return;  // system stopped: uniform over the block
+  const double beta = pcg ? scal[0] : 0.0;
+#pragma unroll
+  for (int k = 0; k < GPT; ++k) {  // p = z + beta p_old, formed as k_dof1 stores it
+    const int e = tid + 256 * k;
+    if (e < NT) ush[e] = pcg ? fma(beta, gv[k], gz[k]) : gv[k];
+  }
+  __syncthreads();
+  double u[NC][NJ];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int col = wave * WC + c * 16 + n;
+    const double x0 = ush[col], x1 = ush[TC + col], th = ush[3 * TC + col] - x1;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) u[c][jj] = rigid_free<P>(ush[(4 * jj + kq) * TC + col], 4 * jj + kq, x0, x1, th);
+  }
+  d4 acc[MB][NC];
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[b][c] = d4{0.0, 0.0, 0.0, 0.0};
+  double e[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) e[c] = valid[c] ? E[cellb[c]] : 0.0;
+  for (int sc = 0; sc < g.S; ++sc) {
+    const double* __restrict__ cur = afr + (sc & 1) * FR;
+    double* __restrict__ nxt = afr + ((sc + 1) & 1) * FR;
+    const bool more = sc + 1 < g.S;
+    double en[NC];
+    if (more) {  // next cell: fragments and moduli in flight during this cell's MFMAs
+      const double* __restrict__ kn = kf + (size_t)(sc + 1) * FR;
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) {
+        const int i = tid + 256 * k;
+        stg[k] = kn[i < FR ? i : FR - 1];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) en[c] = valid[c] ? E[cellb[c] + sc + 1] : 0.0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      double a[MB];
+#pragma unroll
+      for (int b = 0; b < MB; ++b) a[b] = cur[(jj * MB + b) * 64 + lane];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double bv = e[c] * u[c][jj];
+#pragma unroll
+        for (int b = 0; b < MB; ++b) acc[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b], bv, acc[b][c], 0, 0, 0);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) {
+        const int i = tid + 256 * k;
+        if (i < FR) nxt[i] = stg[k];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) e[c] = en[c];
+    }
+    __syncthreads();  // the next cell's fragments are in; this cell's buffer may be overwritten
+  }
+  double* __restrict__ sl = s.slots + t.slot_off;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (sidx[c][b][r] >= 0) sl[sidx[c][b][r]] = acc[b][c][r];
+}
+
+// ---------------------------------------------------------------------------
+// Vertex-column product: slots += sum_s E_s K_s[:, V] dz_V for a correction dz
+// that is nonzero only at vertex DOFs (V: the element's 8 vertex DOFs), which
+// is what the coarse-grid correction of the V-cycle adds to z.  With the
+// slots holding K z from before the correction this gives K z after it,
+// without the full product: the reduction runs over S * 8 instead of
+// S * NEP entries (two MFMA k-steps per cell, A = the vertex columns of K_s,
+// kfragv [S][2][MB][64]).  One wave per 16 element columns (blockIdx.y picks
+// the part of the tile); running systems only; dz's rigid motion removed as
+// in the other products.
+template <int P>
+__device__ __forceinline__ int vertex_dof(int v) {  // v = 0..7: vertices (0,0), (1,0), (0,1), (1,1), x and y
+  return v < 4 ? v : 2 * (P + 1) + (v - 4);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_elem_vertex(GroupDev g, const Tile* __restrict__ tiles,
+                                                   const double* __restrict__ E, const double* __restrict__ dz,
+                                                   PcgDev s) {
+  constexpr int NE = ne_of(P), MB = mb_of(P);
+  const Tile t = tiles[g.tile_begin + blockIdx.x];
+  const int c0 = blockIdx.y * 16;
+  if (c0 >= t.count || s.status[t.sys] != SYS_RUNNING) return;  // uniform over the wave
+  const int lane = threadIdx.x, n = lane & 15, kq = lane >> 4;
+  const bool valid = c0 + n < t.count;
+  const int el = t.elem_begin + c0 + (valid ? n : 0);
+  // dz at vertex DOFs kq and 4 + kq of this lane's column
+  double v[2];
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj) {
+    const int gi = valid ? g.gidx[vertex_dof<P>(4 * jj + kq) * g.npad + el] : -1;
+    const double x = dz[t.dof_off + (gi >= 0 ? gi : 0)];
+    v[jj] = gi >= 0 ? x : 0.0;
+  }
+  {  // rigid motion through DOFs 0, 1 (vertex (0,0)) and 3 (vertex (1,0) y): lanes n, 16 + n, 48 + n
+    const double x0 = __shfl(v[0], n), x1 = __shfl(v[0], 16 + n), th = __shfl(v[0], 48 + n) - x1;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) v[jj] = rigid_free<P>(v[jj], vertex_dof<P>(4 * jj + kq), x0, x1, th);
+  }
+  int sidx[MB][4];
+  double old[MB][4];
+  double* __restrict__ sl = s.slots + t.slot_off;
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = b * 16 + kq + 4 * r;
+      sidx[b][r] = (valid && row < NE) ? g.sidx[row * g.npad + el] : -1;
+      const double o = sl[sidx[b][r] >= 0 ? sidx[b][r] : 0];
+      old[b][r] = sidx[b][r] >= 0 ? o : 0.0;
+    }
+  const int cb = valid ? g.cell[el] : 0;
+  const double* __restrict__ kf = g.kfragv + lane;
+  d4 acc[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) acc[b] = d4{old[b][0], old[b][1], old[b][2], old[b][3]};
+  for (int sc = 0; sc < g.S; ++sc) {
+    const double e = valid ? E[cb + sc] : 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const double bv = e * v[jj];
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kf[(((size_t)sc * 2 + jj) * MB + b) * 64], bv, acc[b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (sidx[b][r] >= 0) sl[sidx[b][r]] = acc[b][r];
 }
 
 // ---------------------------------------------------------------------------
@@ -991,6 +1231,19 @@ void launch_elem_p(const GroupDev& g, int path, int ncol, const Tile* tiles, con
     launch_timed(k_elem_plain<P>, dim3(g.n_tiles), dim3(64), 0u, st, ev0, ev1, g, tiles, E, xin, s, mode, it_k);
     return;
   }
+  if constexpr (P >= 3) {
+    if (g.lds_nc > 0) {
+      if (g.lds_n_tiles == 0) return;
+      const uint32_t lds = (uint32_t)elem_lds_staged_bytes(P, g.lds_nc);
+      if (g.lds_nc == 1)
+        launch_timed(k_elem_mfma_lds<P, 1>, dim3(g.lds_n_tiles), dim3(256), lds, st, ev0, ev1, g, tiles, E, xin, s,
+                     mode, it_k);
+      else
+        launch_timed(k_elem_mfma_lds<P, 2>, dim3(g.lds_n_tiles), dim3(256), lds, st, ev0, ev1, g, tiles, E, xin, s,
+                     mode, it_k);
+      return;
+    }
+  }
   const dim3 grid(g.n_tiles), block(64 * g.waves);
   const uint32_t lds = (uint32_t)elem_lds_bytes(P, ncol, g.waves);
   switch (ncol) {
@@ -1021,6 +1274,18 @@ void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E
     case 2: launch_elem_p<2>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
     case 3: launch_elem_p<3>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
     default: launch_elem_p<4>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
+  }
+}
+
+void launch_elem_vertex(const GroupDev& g, const Tile* tiles, const double* E, const double* dz, const PcgDev& s,
+                        hipStream_t st) {
+  if (g.n_tiles == 0) return;
+  const dim3 grid(g.n_tiles, g.ncol), block(64);
+  switch (g.p) {
+    case 1: hipLaunchKernelGGL(k_elem_vertex<1>, grid, block, 0, st, g, tiles, E, dz, s); break;
+    case 2: hipLaunchKernelGGL(k_elem_vertex<2>, grid, block, 0, st, g, tiles, E, dz, s); break;
+    case 3: hipLaunchKernelGGL(k_elem_vertex<3>, grid, block, 0, st, g, tiles, E, dz, s); break;
+    default: hipLaunchKernelGGL(k_elem_vertex<4>, grid, block, 0, st, g, tiles, E, dz, s); break;
   }
 }
 

@@ -15,7 +15,13 @@ struct GroupDev {
   int32_t tile_begin, n_tiles, ncol;  // tiles of this group in the tile array
   int32_t waves;           // waves per tile (density-cell split of the reduction)
   int32_t xcd_run;         // tile order over the XCDs of the contraction (see xcd_tile)
+  int32_t lds_nc;          // > 0: the contraction runs k_elem_mfma_lds<P, lds_nc> (p >= 3) on the
+  int32_t lds_tile_begin;  //   tiles of 64 lds_nc columns [lds_tile_begin, + lds_n_tiles)
+  int32_t lds_n_tiles;
+  int32_t ms_tile_begin;   // tiles of the first system of every instance (16 ncol columns), on which the
+  int32_t ms_n_tiles;      //   Schwarz application serves all systems of the instance
   const double* kfrag;     // MFMA A fragments [S*NEP/4][MB][64]
+  const double* kfragv;    // the vertex columns of K_s as A fragments [S][2][MB][64] (vertex_fragments)
   const double* ks;        // plain K_s [S][ne][ne]
   const double* kdiag;     // diag(K_s) [S][ne]
   const double* kabs;      // row sums of |K_s| [S][ne] (l1 smoother)
@@ -139,12 +145,24 @@ inline size_t elem_lds_bytes(int p, int ncol, int ks) {
 }
 constexpr size_t ELEM_LDS_LIMIT = 64 * 1024;
 
+// Dynamic LDS of the LDS-staged contraction k_elem_mfma_lds<P, nc>: the A
+// fragments of two cells, the tile's 64 nc element vectors and two scalars.
+inline size_t elem_lds_staged_bytes(int p, int nc) {
+  const size_t fr = (size_t)(nep_of(p) / 4) * mb_of(p) * 64;
+  return 8 * (2 * fr + (size_t)nep_of(p) * 64 * nc + 2);
+}
+constexpr size_t ELEM_LDS_STAGED_LIMIT = 160 * 1024;
+
 // y-slots of K applied to the vector `xin` (ELEM_APPLY) or to the PCG search
 // direction p = z + beta p formed on the fly (ELEM_PCG), for the tiles of one group.
 // Optional events ev0/ev1 record the start and end of this kernel itself.
 void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E, const double* xin,
                  const PcgDev& s, int mode, int it_k, hipStream_t st, hipEvent_t ev0 = nullptr,
                  hipEvent_t ev1 = nullptr);
+// slots += K[:, vertex DOFs] dz for the running systems (dz in the free-DOF
+// layout, read at vertex DOFs only; the slots hold K z before the call)
+void launch_elem_vertex(const GroupDev& g, const Tile* tiles, const double* E, const double* dz, const PcgDev& s,
+                        hipStream_t st);
 // g = -E' lam_e^T K_s u_e per system, u from x and lam from y (free-DOF
 // layout of the systems; y = x gives the compliance sensitivity)
 void launch_sens(const GroupDev& g, const Tile* tiles, const double* dE, const double* x, const double* y,

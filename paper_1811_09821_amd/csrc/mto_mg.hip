@@ -755,7 +755,9 @@ __global__ __launch_bounds__(256) void k_mg_coarse_solve(const MgChunk* __restri
 }
 
 // vfree != NULL (level 1): also z += e2 at the node's free vertex DOFs
-// (the injection back to the hierarchic level).  MG_RR_NODES nodes per
+// (the injection back to the hierarchic level), and the same correction into
+// q at those DOFs (q is free between k_dof2 and the next k_dof1), from which
+// the vertex-column product updates the slots.  MG_RR_NODES nodes per
 // 256-thread block, 16 lanes each.
 __global__ __launch_bounds__(256) void k_mg_prolong_smooth(const MgChunk* __restrict__ chunks, PcgDev s,
                                                            const double* __restrict__ A,
@@ -773,12 +775,19 @@ __global__ __launch_bounds__(256) void k_mg_prolong_smooth(const MgChunk* __rest
   if (vfree && node_ok && sub == 4) {
     const int64_t node = ch.op + n;
     const int f0 = vfree[node * 2], f1 = vfree[node * 2 + 1];
-    if (f0 >= 0) s.z[ch.dof_off + f0] += o0;
-    if (f1 >= 0) s.z[ch.dof_off + f1] += o1;
+    if (f0 >= 0) {
+      s.z[ch.dof_off + f0] += o0;
+      s.q[ch.dof_off + f0] = o0;
+    }
+    if (f1 >= 0) {
+      s.z[ch.dof_off + f1] += o1;
+      s.q[ch.dof_off + f1] = o1;
+    }
   }
 }
 
-// Level 1 -> 0: z += injection^T e2_1 at the free vertex DOFs.
+// Level 1 -> 0: z += injection^T e2_1 at the free vertex DOFs (and into q, as
+// in k_mg_prolong_smooth).
 __global__ __launch_bounds__(MGB) void k_mg_prolong0(const MgChunk* __restrict__ chunks, PcgDev s,
                                                      const int32_t* __restrict__ vfree, const double* __restrict__ e2) {
   const MgChunk ch = chunks[blockIdx.x];
@@ -788,7 +797,10 @@ __global__ __launch_bounds__(MGB) void k_mg_prolong0(const MgChunk* __restrict__
   const int64_t node = ch.op + n, v = ch.vec + n;
   for (int c = 0; c < 2; ++c) {
     const int f = vfree[node * 2 + c];
-    if (f >= 0) s.z[ch.dof_off + f] += e2[v * 2 + c];
+    if (f >= 0) {
+      s.z[ch.dof_off + f] += e2[v * 2 + c];
+      s.q[ch.dof_off + f] = e2[v * 2 + c];
+    }
   }
 }
 
@@ -1061,6 +1073,11 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
 template <int P>
 constexpr int asm_rows() { return (ne_of(P) + 3) / 4 * 4; }
 
+// Up to ASM_SYS systems of one instance per pass over a tile: the element
+// blocks B_e are shared by the load cases of an instance, so one read of a
+// block's row serves all of them.
+constexpr int ASM_SYS = 4;
+
 template <int P>
 __global__ __launch_bounds__(16 * asm_rows<P>()) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
                                                                   const double* __restrict__ binv,
@@ -1068,14 +1085,22 @@ __global__ __launch_bounds__(16 * asm_rows<P>()) void k_asm_apply(GroupDev g, co
                                                                   double* __restrict__ out_slots, double omega,
                                                                   int resid) {
   constexpr int NE = ne_of(P);
-  __shared__ double vs[NE][17];
-  const Tile t = tiles[g.tile_begin + blockIdx.x];
+  __shared__ double vs[ASM_SYS][NE][17];
+  // a tile of the first system of its instance; the instance's other systems
+  // follow it (instance-major numbering), their count is in pc_begin
+  const Tile t = tiles[g.ms_tile_begin + blockIdx.x];
   const int c0 = blockIdx.y * 16;
-  if (c0 >= t.count || s.status[t.sys] != SYS_RUNNING) return;  // uniform over the block
+  if (c0 >= t.count) return;  // uniform over the block
   const int c = threadIdx.x & 15, a = threadIdx.x >> 4;
   const bool valid = c0 + c < t.count;
   const int col = t.elem_begin + c0 + (valid ? c : 0);
   const int64_t np = g.npad;
+  const int nsys = t.pc_begin;
+  {  // nothing to do once every system of the instance has stopped (no block read)
+    bool any = false;
+    for (int l = 0; l < nsys; ++l) any |= s.status[t.sys + l] == SYS_RUNNING;
+    if (!any) return;  // uniform over the block
+  }
   // the 16 elements of this block (tile-major storage) read one contiguous run
   const double* __restrict__ bp = binv + (int64_t)(col >> 4) * (NE * (NE + 1) / 2) * 16 + (col & 15);
   // the first H entries of the row are requested before the gather, the rest
@@ -1087,31 +1112,46 @@ __global__ __launch_bounds__(16 * asm_rows<P>()) void k_asm_apply(GroupDev g, co
   double brow[H];
 #pragma unroll
   for (int b = 0; b < H; ++b) brow[b] = entry(b);
-  if (a < NE) {
-    const int id = valid ? g.gidx[a * np + col] : -1;
-    double x = 0.0;
-    if (id >= 0) {
-      const double* __restrict__ vsys = v + t.dof_off;
-      if (resid) {
-        const SysDesc& sd = s.sys[t.sys];
-        x = vsys[id] - slot_sum(s.slots + t.slot_off, id, sd.nfv, sd.nfe);
-      } else {
-        x = vsys[id];
+  const int id = (a < NE && valid) ? g.gidx[a * np + col] : -1;
+  const int si = (a < NE && valid) ? g.sidx[a * np + col] : -1;
+  for (int l0 = 0; l0 < nsys; l0 += ASM_SYS) {
+    bool run[ASM_SYS];
+#pragma unroll
+    for (int l = 0; l < ASM_SYS; ++l) {  // the same addresses in every lane: one load each
+      const int sys = t.sys + l0 + (l0 + l < nsys ? l : 0);
+      const bool st = s.status[sys] == SYS_RUNNING;
+      run[l] = l0 + l < nsys && st;
+    }
+    if (a < NE) {
+#pragma unroll
+      for (int l = 0; l < ASM_SYS; ++l) {
+        if (!run[l]) continue;
+        const SysDesc& sd = s.sys[t.sys + l0 + l];
+        double x = 0.0;
+        if (id >= 0) {
+          const double* __restrict__ vsys = v + sd.dof_off;
+          x = resid ? vsys[id] - slot_sum(s.slots + sd.slot_off, id, sd.nfv, sd.nfe) : vsys[id];
+        }
+        vs[l][a][c] = x;
       }
     }
-    vs[a][c] = x;
-  }
-  __syncthreads();
-  if (a >= NE) return;
-  double acc = 0.0;
+    __syncthreads();
+    if (a < NE) {
 #pragma unroll
-  for (int b = 0; b < H; ++b) acc = fma(brow[b], vs[b][c], acc);
-  if constexpr (H < NE) {
+      for (int l = 0; l < ASM_SYS; ++l) {
+        if (!run[l]) continue;
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < H; ++b) acc = fma(brow[b], vs[l][b][c], acc);
+        if constexpr (H < NE) {
 #pragma unroll 5
-    for (int b = H; b < NE; ++b) acc = fma(entry(b), vs[b][c], acc);
+          for (int b = H; b < NE; ++b) acc = fma(entry(b), vs[l][b][c], acc);
+        }
+        if (si >= 0) out_slots[s.sys[t.sys + l0 + l].slot_off + si] = omega * acc;
+      }
+    }
+    if (l0 + ASM_SYS < nsys) __syncthreads();  // vs is rewritten by the next pass
   }
-  const int si = valid ? g.sidx[a * np + col] : -1;
-  if (si >= 0) out_slots[t.slot_off + si] = omega * acc;
 }
 
 // z = assembled slots2 (the Schwarz products)
@@ -1216,8 +1256,8 @@ void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const i
 }
 void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, int resid,
                       const PcgDev& s, double* slots2, double omega, hipStream_t st) {
-  if (g.n_tiles == 0) return;
-  const dim3 grid(g.n_tiles, g.ncol);  // tiles hold at most 16 ncol columns
+  if (g.ms_n_tiles == 0) return;
+  const dim3 grid(g.ms_n_tiles, g.ncol);  // tiles hold at most 16 ncol columns
   switch (g.p) {
     case 1:
       hipLaunchKernelGGL(k_asm_apply<1>, grid, dim3(16 * asm_rows<1>()), 0, st, g, tiles, binv, v, s, slots2, omega,

@@ -59,9 +59,14 @@ struct DevBuf {
 struct GroupHost {
   int p = 0, d = 0, S = 0, ne = 0, nep = 0, mb = 0;
   int n_elems = 0, npad = 0, ncol = 1, waves = 1;
+  // LDS-staged contraction (p >= 3): 0 = off, else 64 lds_nc columns per tile, on their own tiles
+  int lds_nc = 0, lds_tile_begin = 0, lds_n_tiles = 0;
+  // tiles of the first system of each instance (the Schwarz application serves all its systems)
+  int ms_tile_begin = 0, ms_n_tiles = 0;
   // per instance: element range [inst_begin[i], inst_begin[i+1]) in the group arrays
   std::vector<int32_t> inst_begin;
   double* kfrag = nullptr;
+  double* kfragv = nullptr;
   double* ks = nullptr;
   double* kdiag = nullptr;
   double* kabs = nullptr;
@@ -218,7 +223,13 @@ struct mto_plan {
     o.ncol = g.ncol;
     o.waves = g.waves;
     o.xcd_run = n_sys > 1 ? 8 : 0;  // several systems may stop at different iterations
+    o.lds_nc = g.lds_nc;
+    o.lds_tile_begin = g.lds_tile_begin;
+    o.lds_n_tiles = g.lds_n_tiles;
+    o.ms_tile_begin = g.ms_tile_begin;
+    o.ms_n_tiles = g.ms_n_tiles;
     o.kfrag = g.kfrag;
+    o.kfragv = g.kfragv;
     o.ks = g.ks;
     o.kdiag = g.kdiag;
     o.kabs = g.kabs;
@@ -260,18 +271,30 @@ void destroy_graphs(mto_plan* P) {
   P->bound = false;
 }
 
-// Tiles for every group with its current ncol; uploads them.
+// Tiles for every group with its current ncol, then the tiles of the
+// LDS-staged contraction (64 lds_nc columns) for the groups that use it, then
+// the tiles of the first system of every instance (16 ncol columns) for the
+// Schwarz application; uploads them.
 int rebuild_tiles(mto_plan* P) {
   P->tiles.clear();
+  for (int pass = 0; pass < 3; ++pass)
   for (size_t gi = 0; gi < P->groups.size(); ++gi) {
     GroupHost& g = P->groups[gi];
-    if (P->prm.kernel_path == MTO_PATH_PLAIN) g.ncol = 4;  // one 64-thread block per 64-column tile
-    const int tile_cols = 16 * g.ncol;
-    g.tile_begin = (int)P->tiles.size();
+    if (P->prm.kernel_path == MTO_PATH_PLAIN) {
+      g.ncol = 4;  // one 64-thread block per 64-column tile
+      g.lds_nc = 0;
+    }
+    if (pass == 1 && g.lds_nc == 0) {
+      g.lds_tile_begin = (int)P->tiles.size();
+      g.lds_n_tiles = 0;
+      continue;
+    }
+    const int tile_cols = pass == 1 ? 64 * g.lds_nc : 16 * g.ncol;
+    (pass == 0 ? g.tile_begin : pass == 1 ? g.lds_tile_begin : g.ms_tile_begin) = (int)P->tiles.size();
     for (int i = 0; i < P->n_inst; ++i) {
       const int a = g.inst_begin[i], b = g.inst_begin[i + 1];
       if (a == b) continue;
-      for (int l = 0; l < P->L[i]; ++l) {
+      for (int l = 0; l < (pass == 2 ? 1 : P->L[i]); ++l) {
         int sysi = 0;
         for (int k = 0; k < i; ++k) sysi += P->L[k];
         sysi += l;
@@ -284,13 +307,18 @@ int rebuild_tiles(mto_plan* P) {
           t.sys = sysi;
           t.elem_begin = e;
           t.count = std::min(tile_cols, b - e);
-          t.pc_begin = sd.chunk_begin;
+          t.pc_begin = pass == 2 ? P->L[i] : sd.chunk_begin;  // Schwarz tiles: the instance's system count
           t.pc_end = sd.chunk_end;
           P->tiles.push_back(t);
         }
       }
     }
-    g.n_tiles = (int)P->tiles.size() - g.tile_begin;
+    if (pass == 0)
+      g.n_tiles = (int)P->tiles.size() - g.tile_begin;
+    else if (pass == 1)
+      g.lds_n_tiles = (int)P->tiles.size() - g.lds_tile_begin;
+    else
+      g.ms_n_tiles = (int)P->tiles.size() - g.ms_tile_begin;
   }
   if (P->tiles.size() > P->tiles_cap) {
     if (P->d_tiles) {
@@ -349,8 +377,8 @@ bool read_tile_cache(const char* path, std::map<TileKey, TileChoice>& out) {
     TileKey k;
     TileChoice v;
     if (sscanf(line, "%63s %d %d %d %d %d %lf", arch, &k.p, &k.d, &k.size_class, &v.ncol, &v.ks, &v.us) != 7 ||
-        (v.ncol != 1 && v.ncol != 2 && v.ncol != 4) || v.ks < 1 || v.ks > 8 || k.p < 1 || k.p > MTO_MAX_P ||
-        k.d < 1 || k.d > MTO_MAX_D) {
+        (v.ncol != 1 && v.ncol != 2 && v.ncol != 4) || v.ks < 0 || v.ks > 8 || k.p < 1 || k.p > MTO_MAX_P ||
+        k.d < 1 || k.d > MTO_MAX_D || (v.ks == 0 && (k.p < 3 || v.ncol == 4))) {
       ok = false;
       break;
     }
@@ -365,7 +393,8 @@ bool write_tile_cache(const char* path, const std::map<TileKey, TileChoice>& c) 
   const std::string tmp = std::string(path) + ".tmp";
   FILE* fh = fopen(tmp.c_str(), "w");
   if (!fh) return false;
-  fprintf(fh, "# element-contraction tile shapes: arch p d size_class(log2 columns) ncol ks us_per_launch\n");
+  fprintf(fh, "# element-contraction tile shapes: arch p d size_class(log2 columns) ncol ks us_per_launch"
+              " (ks 0: LDS-staged tables, 64 ncol columns per tile)\n");
   for (auto& kv : c)
     fprintf(fh, "%s %d %d %d %d %d %.3f\n", kv.first.arch.c_str(), kv.first.p, kv.first.d, kv.first.size_class,
             kv.second.ncol, kv.second.ks, kv.second.us);
@@ -755,6 +784,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     }
     std::vector<double> ks = subcell_tables(g.p, g.d, P->prm.nu);
     std::vector<double> kfr = mfma_fragments(ks, g.p, g.d);
+    std::vector<double> kfv = vertex_fragments(ks, g.p, g.d);
     std::vector<double> kdiag((size_t)g.S * g.ne), kabs((size_t)g.S * g.ne, 0.0);
     for (int s = 0; s < g.S; ++s)
       for (int j = 0; j < g.ne; ++j) {
@@ -775,6 +805,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     int rc;
     if ((rc = dev_upload(P, &g.gidx, gidx)) || (rc = dev_upload(P, &g.sidx, sidx)) ||
         (rc = dev_upload(P, &g.cell, cell)) || (rc = dev_upload(P, &g.ks, ks)) || (rc = dev_upload(P, &g.kfrag, kfr)) ||
+        (rc = dev_upload(P, &g.kfragv, kfv)) ||
         (rc = dev_upload(P, &g.kdiag, kdiag)) || (rc = dev_upload(P, &g.kabs, kabs)))
       return cleanup(rc);
     double per_col = 2.0 * g.S * g.ne * g.ne;
@@ -909,6 +940,18 @@ void enq_coarse_correction(mto_plan* P, hipStream_t st) {
   if (M.L == 1) launch_mg_prolong0(M.sysc(1), M.sys_count[0], s, M.vfree, M.e2, st);
 }
 
+// The slots hold K z from before the coarse-grid correction, which changed z
+// at vertex DOFs only (by the values also left in q): add K[:, vertex] of
+// that change, so the slots hold K z after it.
+void enq_vertex_update(mto_plan* P, hipStream_t st) {
+  const PcgDev s = P->pcg();
+  if (P->prm.kernel_path == MTO_PATH_PLAIN) {  // the comparison path keeps its full product
+    enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
+    return;
+  }
+  for (auto& g : P->groups) launch_elem_vertex(P->gdev(g), P->d_tiles, P->E, P->q, s, st);
+}
+
 // z = M r: one V-cycle.  Level-0 smoothing is Jacobi-type (z = D0^-1 r is
 // already in z; l1 or damped post-sweep) or the element-block Schwarz
 // smoother (pre: z = w B r; post: z += w B (r - A0 z)).  The last kernel also
@@ -920,7 +963,7 @@ void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
     launch_asm_z(s, P->slots2, st);
     enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
     enq_coarse_correction(P, st);
-    enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
+    enq_vertex_update(P, st);
     // post-smoothing: the residual r - A0 z is formed in the gather
     for (auto& g : P->groups) launch_asm_apply(P->gdev(g), P->d_tiles, g.binv, P->r, 1, s, P->slots2, P->asm_omega, st);
     launch_asm_post(s, P->slots2, it_k, init, st);
@@ -928,7 +971,7 @@ void enq_vcycle(mto_plan* P, int it_k, int init, hipStream_t st) {
   }
   enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
   enq_coarse_correction(P, st);
-  enq_elem_all(P, P->z, ELEM_APPLY_RUNNING, 0, st);
+  enq_vertex_update(P, st);
   launch_mg_post0(s, it_k, init, st);
 }
 
@@ -1598,14 +1641,26 @@ int mto_weighted_sensitivity(mto_plan* P, const double* g, const double* w, doub
 
 int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol, int32_t ks) {
   g_err.clear();
-  if (!P || (ncol != 1 && ncol != 2 && ncol != 4) || ks < 1 || ks > 8)
-    return fail(MTO_EINVAL, "ncol must be 1, 2 or 4 and ks 1..8");
+  if (!P || (ncol != 1 && ncol != 2 && ncol != 4) || ks < 0 || ks > 8)
+    return fail(MTO_EINVAL, "ncol must be 1, 2 or 4 and ks 0..8");
+  if (ks == 0 && ncol == 4) return fail(MTO_EINVAL, "the LDS-staged contraction takes ncol 1 or 2");
   for (auto& g : P->groups)
     if (p <= 0 || (g.p == p && g.d == d)) {
+      if (ks == 0) {
+        if (g.p < 3) {
+          if (p > 0) return fail(MTO_EINVAL, "the LDS-staged contraction needs p >= 3");
+          continue;  // all groups: the others keep their shape
+        }
+        if (elem_lds_staged_bytes(g.p, ncol) > ELEM_LDS_STAGED_LIMIT)
+          return fail(MTO_EINVAL, "tile shape exceeds the LDS limit");
+        g.lds_nc = ncol;
+        continue;
+      }
       const int k = std::min<int>(ks, g.S);
       if (elem_lds_bytes(g.p, ncol, k) > ELEM_LDS_LIMIT) return fail(MTO_EINVAL, "tile shape exceeds the LDS limit");
       g.ncol = ncol;
       g.waves = k;
+      g.lds_nc = 0;
     }
   return rebuild_tiles(P);
 }
@@ -1636,11 +1691,22 @@ int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* s
   std::string rep;
   bool changed = false;
   const int cand_nc[3] = {1, 2, 4};
-  const int cand_ks[4] = {1, 2, 4, 8};
+  const int cand_ks[5] = {0, 1, 2, 4, 8};  // 0: the LDS-staged contraction
   for (auto& g : P->groups) {
     const TileKey key{arch, g.p, g.d, size_class(g.flops / (2.0 * g.S * g.ne * g.ne))};
     auto hit = cache.find(key);
-    if (hit != cache.end() && elem_lds_bytes(g.p, hit->second.ncol, std::min(hit->second.ks, g.S)) <= ELEM_LDS_LIMIT) {
+    if (hit != cache.end() && hit->second.ks == 0 && g.p >= 3 &&
+        elem_lds_staged_bytes(g.p, hit->second.ncol) <= ELEM_LDS_STAGED_LIMIT) {
+      g.lds_nc = hit->second.ncol;
+      char line[200];
+      snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=0: cached (%s, %d columns class, %.3f us when tuned)\n", g.p,
+               g.d, g.lds_nc, arch.c_str(), key.size_class, hit->second.us);
+      rep += line;
+      continue;
+    }
+    if (hit != cache.end() && hit->second.ks > 0 &&
+        elem_lds_bytes(g.p, hit->second.ncol, std::min(hit->second.ks, g.S)) <= ELEM_LDS_LIMIT) {
+      g.lds_nc = 0;
       g.ncol = hit->second.ncol;
       g.waves = std::min(hit->second.ks, g.S);
       char line[200];
@@ -1653,10 +1719,12 @@ int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* s
     int best_nc = g.ncol, best_ks = g.waves;
     for (int nc : cand_nc)
       for (int ks : cand_ks) {
-        if (ks > g.S || elem_lds_bytes(g.p, nc, ks) > ELEM_LDS_LIMIT) continue;
-        if ((nc == 4 && g.p >= 2) || (nc == 2 && g.p == 4)) continue;  // register spills
-        g.ncol = nc;
-        g.waves = ks;
+        if (ks > 0 && (ks > g.S || elem_lds_bytes(g.p, nc, ks) > ELEM_LDS_LIMIT)) continue;
+        if (ks > 0 && ((nc == 4 && g.p >= 2) || (nc == 2 && g.p == 4))) continue;  // register spills
+        if (ks == 0 && (g.p < 3 || nc == 4 || elem_lds_staged_bytes(g.p, nc) > ELEM_LDS_STAGED_LIMIT)) continue;
+        g.lds_nc = ks == 0 ? nc : 0;
+        g.ncol = ks == 0 ? 1 : nc;
+        g.waves = ks == 0 ? 1 : ks;
         int rc = rebuild_tiles(P);
         if (rc) return rc;
         const GroupDev gd = P->gdev(g);
@@ -1680,8 +1748,9 @@ int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* s
           best_ks = ks;
         }
       }
-    g.ncol = best_nc;
-    g.waves = best_ks;
+    g.lds_nc = best_ks == 0 ? best_nc : 0;
+    g.ncol = best_ks == 0 ? 1 : best_nc;
+    g.waves = best_ks == 0 ? 1 : best_ks;
     cache[key] = TileChoice{best_nc, best_ks, 1e3 * best};
     changed = true;
   }
@@ -1689,7 +1758,8 @@ int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* s
   (void)hipEventDestroy(e1);
   for (auto& g : P->groups) {
     char line[96];
-    snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=%d: chosen\n", g.p, g.d, g.ncol, g.waves);
+    snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=%d: chosen\n", g.p, g.d, g.lds_nc ? g.lds_nc : g.ncol,
+             g.lds_nc ? 0 : g.waves);
     rep += line;
   }
   int rc = rebuild_tiles(P);

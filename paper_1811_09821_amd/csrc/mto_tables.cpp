@@ -174,4 +174,18 @@ std::vector<double> mfma_fragments(const std::vector<double>& ks, int p, int d) 
   return fr;
 }
 
+std::vector<double> vertex_fragments(const std::vector<double>& ks, int p, int d) {
+  const int ne = ne_of(p), mb = mb_of(p), S = d * d;
+  std::vector<double> fr((size_t)S * 2 * mb * 64, 0.0);
+  for (int s = 0; s < S; ++s)
+    for (int jj = 0; jj < 2; ++jj)
+      for (int b = 0; b < mb; ++b)
+        for (int l = 0; l < 64; ++l) {
+          const int row = b * 16 + (l % 16), v = 4 * jj + l / 16;
+          const int col = v < 4 ? v : 2 * (p + 1) + (v - 4);
+          fr[(((size_t)s * 2 + jj) * mb + b) * 64 + l] = row < ne ? ks[(size_t)s * ne * ne + row * ne + col] : 0.0;
+        }
+  return fr;
+}
+
 }  // namespace mto

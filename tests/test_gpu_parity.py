@@ -81,7 +81,9 @@ GROUPS = [(p, d) for p in (1, 2, 3, 4) for d in range(1, 9)]  # every (p, d) the
 def test_matvec_every_group(cuda, p, d):
     """y = K x (element contraction + slot assembly) for all 32 (p, d) groups,
     on a 7 x 5 mesh (35 elements: several 16-column tiles and a ragged tail)
-    with several tile widths and density-cell splits across waves."""
+    with several tile widths and density-cell splits across waves, and for
+    p >= 3 the LDS-staged contraction (ks = 0: one 64- or 128-column tile,
+    ragged)."""
     pr = P.uniform_random(7, 5, p, d, seed=100 + 10 * p + d)
     K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
     free = free_mask(space, pr.supports)
@@ -92,7 +94,8 @@ def test_matvec_every_group(cuda, p, d):
     plan = mto().Plan(pr)
     rho = torch.tensor(pr.rho, device=cuda)
     xt = torch.tensor(x, device=cuda)
-    for ncol, ks in ((1, 1), (2, 2), (1, 4), (4, 1), (1, 8)):
+    shapes = [(1, 1), (2, 2), (1, 4), (4, 1), (1, 8)] + ([(1, 0), (2, 0)] if p >= 3 else [])
+    for ncol, ks in shapes:
         plan.set_tile(ncol, ks)
         y = plan.apply_stiffness(rho, xt).cpu().numpy()
         assert rel(y, yref) < 1e-13, (p, d, ncol, ks, rel(y, yref))
@@ -463,3 +466,39 @@ def test_autotune_cache(cuda, tmp_path):
     with pytest.raises(m.MtoError) as ei:
         m.Plan(pr).autotune(rho, cache=str(bad))
     assert ei.value.code == m.MTO_EINVAL
+
+
+@pytest.mark.parametrize("ncol", [1, 2])
+@pytest.mark.parametrize("name", ["uniform_p3d4", "uniform_p4d5", "uniform_p4d8_max", "mixed_3loads"])
+def test_solve_parity_lds_staged(cuda, name, ncol):
+    """Solves with the LDS-staged contraction (cell tables shared by four
+    waves through LDS) on every p >= 3 group, against the oracle."""
+    prs = CASES[name]()
+    plan = mto().Plan(prs)
+    plan.set_tile(ncol, 0)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
+
+
+def test_lds_staged_product_many_tiles(cuda):
+    """The LDS-staged product on a 40 x 23 p = 4, d = 5 mesh with two load
+    cases (30 tiles of 64 columns, the last ragged; tiles of both systems)
+    equals the register-fragment product to 1e-14 and the oracle's K x."""
+    pr = P.uniform_random(40, 23, 4, 5, seed=91, loads=[(40, 11, 0.0, -1.0, 0), (40, 3, 1.0, 0.0, 1)], n_load_cases=2)
+    K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
+    free = free_mask(space, pr.supports)
+    x = np.random.default_rng(5).standard_normal((2, space.n_dof))
+    x[:, ~free] = 0.0
+    yref = (K @ x.T).T
+    yref[:, ~free] = 0.0
+    plan = mto().Plan(pr)
+    rho = torch.tensor(pr.rho, device=cuda)
+    xt = torch.tensor(x.ravel(), device=cuda)
+    plan.set_tile(1, 1)
+    y1 = plan.apply_stiffness(rho, xt).cpu().numpy()
+    for nc in (1, 2):
+        plan.set_tile(nc, 0)
+        y = plan.apply_stiffness(rho, xt).cpu().numpy()
+        assert rel(y, yref.ravel()) < 1e-13, (nc, rel(y, yref.ravel()))
+        assert rel(y, y1) < 1e-14
