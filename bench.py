@@ -290,6 +290,32 @@ def contraction_roofline(plan, rho, stats, config, path_name, shapes):
             "tile_shapes": shapes}
 
 
+def contraction_only(args, prs, desc):
+    """Plan, cached tile shapes, then 100 back-to-back launches of the element
+    contraction (after the solve set-up), optionally followed by one device
+    copy of known size: the command that hardware counters are taken of."""
+    import numpy as np
+    import torch
+
+    from paper_1811_09821_amd import mto
+
+    plan = mto.Plan(prs)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device="cuda:0")
+    report = plan.autotune(rho, cache=args.tile_cache or None)
+    ms = plan.time_contraction(rho, reps=100)
+    out = {"workload": desc, "ms_per_launch": ms, "tile_shapes": tile_shapes(report),
+           "flops_per_launch": plan.info["flops_per_matvec"]}
+    if args.calibrate_copy_mb > 0:
+        n = args.calibrate_copy_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 2 * n * 8
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +342,8 @@ def main():
     ap.add_argument("--no-qr", action="store_true", help="skip the QR-error indicator timing")
     ap.add_argument("--no-mechanism", action="store_true",
                     help="skip the force inverter (compliant mechanism) timing on a 160x80 p=3 d=4 mesh")
+    ap.add_argument("--contraction-only", action="store_true",
+                    help="only plan, tile shapes and 100 back-to-back contraction launches (for counter runs)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -326,6 +354,9 @@ def main():
         sys.exit(2)
 
     prs, desc = workload(args.config, args.eased_field)
+    if args.contraction_only:
+        contraction_only(args, prs, desc)
+        return
     # The CPU baseline first, before anything initialises the GPU, so that its
     # workers are forks of a CPU-only process.
     cpu = None
