@@ -327,8 +327,12 @@ int mto_autotune(mto_plan* plan, const double* rho, const char* cache_path, void
  * (1..8, clamped to d*d); or, with ks = 0 (p >= 3 only, ncol 1 or 2), the
  * LDS-staged contraction: 4 waves of 16 ncol columns each share the cell
  * tables, staged in LDS one cell ahead (with p <= 0 the groups of p < 3 keep
- * their shape).  MTO_EINVAL if the shape needs more LDS than the kernel
- * takes (64 KB; 160 KB for ks = 0).  Invalidates captured graphs. */
+ * their shape).  ks = -1 (p, d, ncol ignored): the product of every group in
+ * one launch (the LDS-staged contraction of 64-column tiles from all groups,
+ * the long ones first); any other call returns to one launch per group.
+ * mto_autotune picks between the two by timing.  MTO_EINVAL if the shape
+ * needs more LDS than the kernel takes (64 KB; 160 KB for ks = 0).
+ * Invalidates captured graphs. */
 int mto_set_tile(mto_plan* plan, int32_t p, int32_t d, int32_t ncol, int32_t ks);
 
 /* Average time (ms, from HIP events on `stream`) of one PCG search-direction

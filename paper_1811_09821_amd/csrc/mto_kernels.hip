@@ -480,19 +480,17 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
 // removed as in k_elem_mfma) sit in LDS as well; each wave writes its own
 // columns' slots.  Results are the same sums as k_elem_mfma with ks = 1.
 template <int P, int NC>
-__global__ __launch_bounds__(256) void k_elem_mfma_lds(GroupDev g, const Tile* __restrict__ tiles,
-                                                      const double* __restrict__ E, const double* __restrict__ xin,
-                                                      PcgDev s, int mode, int it_k) {
+__device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, const double* __restrict__ E,
+                                              const double* __restrict__ xin, const PcgDev& s, int mode, int it_k,
+                                              double* lds) {
   constexpr int NE = ne_of(P), NEP = nep_of(P), MB = mb_of(P), NJ = NEP / 4, WC = 16 * NC, TC = 4 * WC;
   constexpr int FR = NJ * MB * 64;         // doubles of one cell's A fragments
   constexpr int FPT = (FR + 255) / 256;    // of those, per thread
   constexpr int NT = NEP * TC, GPT = (NT + 255) / 256;  // gathered entries, per thread
-  extern __shared__ double lds[];
   double* afr = lds;                // [2][FR]
   double* ush = lds + 2 * FR;       // [NEP][TC] element vectors
   double* scal = ush + NT;          // [2] beta, active
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const Tile t = tiles[g.lds_tile_begin + xcd_tile(blockIdx.x, g.lds_n_tiles, g.xcd_run)];
   // a stopped system has nothing to do (PCG mode also checks this iteration's residual below)
   if (mode != ELEM_APPLY && s.status[t.sys] != SYS_RUNNING) return;
   const bool pcg = mode == ELEM_PCG;
@@ -632,6 +630,35 @@ __global__ __launch_bounds__(256) void k_elem_mfma_lds(GroupDev g, const Tile* _
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (sidx[c][b][r] >= 0) sl[sidx[c][b][r]] = acc[b][c][r];
+}
+
+template <int P, int NC>
+__global__ __launch_bounds__(256) void k_elem_mfma_lds(GroupDev g, const Tile* __restrict__ tiles,
+                                                      const double* __restrict__ E, const double* __restrict__ xin,
+                                                      PcgDev s, int mode, int it_k) {
+  extern __shared__ double lds[];
+  const Tile t = tiles[g.lds_tile_begin + xcd_tile(blockIdx.x, g.lds_n_tiles, g.xcd_run)];
+  elem_lds_tile<P, NC>(g, t, E, xin, s, mode, it_k, lds);
+}
+
+// The product of every (p, d) group in one launch: one block of 4 waves per
+// tile of 64 element columns of the combined tile list (the groups ordered
+// by decreasing work per tile, so the long tiles start first and the short
+// ones fill in), each block running the LDS-staged contraction of its
+// tile's group.
+__global__ __launch_bounds__(256) void k_elem_fused(const GroupDev* __restrict__ groups,
+                                                   const Tile* __restrict__ tiles, int tile_begin, int n_tiles,
+                                                   int xcd_run, const double* __restrict__ E,
+                                                   const double* __restrict__ xin, PcgDev s, int mode, int it_k) {
+  extern __shared__ double lds[];
+  const Tile t = tiles[tile_begin + xcd_tile(blockIdx.x, n_tiles, xcd_run)];
+  const GroupDev g = groups[t.group];
+  switch (g.p) {  // uniform over the block
+    case 1: elem_lds_tile<1, 1>(g, t, E, xin, s, mode, it_k, lds); break;
+    case 2: elem_lds_tile<2, 1>(g, t, E, xin, s, mode, it_k, lds); break;
+    case 3: elem_lds_tile<3, 1>(g, t, E, xin, s, mode, it_k, lds); break;
+    default: elem_lds_tile<4, 1>(g, t, E, xin, s, mode, it_k, lds); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1275,6 +1302,14 @@ void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E
     case 3: launch_elem_p<3>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
     default: launch_elem_p<4>(g, path, g.ncol, tiles, E, xin, s, mode, it_k, st, ev0, ev1); break;
   }
+}
+
+void launch_elem_fused(const GroupDev* groups, const Tile* tiles, int tile_begin, int n_tiles, int xcd_run,
+                       size_t lds_bytes, const double* E, const double* xin, const PcgDev& s, int mode, int it_k,
+                       hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (n_tiles == 0) return;
+  launch_timed(k_elem_fused, dim3(n_tiles), dim3(256), (uint32_t)lds_bytes, st, ev0, ev1, groups, tiles, tile_begin,
+               n_tiles, xcd_run, E, xin, s, mode, it_k);
 }
 
 void launch_elem_vertex(const GroupDev& g, const Tile* tiles, const double* E, const double* dz, const PcgDev& s,

@@ -159,6 +159,13 @@ constexpr size_t ELEM_LDS_STAGED_LIMIT = 160 * 1024;
 void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E, const double* xin,
                  const PcgDev& s, int mode, int it_k, hipStream_t st, hipEvent_t ev0 = nullptr,
                  hipEvent_t ev1 = nullptr);
+// The product of every group in one launch (k_elem_fused): tiles
+// [tile_begin, + n_tiles) of 64 columns from any group (Tile::group indexes
+// the device array `groups`); lds_bytes: the largest elem_lds_staged_bytes(p, 1)
+// of the groups.
+void launch_elem_fused(const GroupDev* groups, const Tile* tiles, int tile_begin, int n_tiles, int xcd_run,
+                       size_t lds_bytes, const double* E, const double* xin, const PcgDev& s, int mode, int it_k,
+                       hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // slots += K[:, vertex DOFs] dz for the running systems (dz in the free-DOF
 // layout, read at vertex DOFs only; the slots hold K z before the call)
 void launch_elem_vertex(const GroupDev& g, const Tile* tiles, const double* E, const double* dz, const PcgDev& s,

@@ -169,6 +169,12 @@ struct mto_plan {
   double *b_u = nullptr, *b_c = nullptr, *b_g = nullptr;
   hipGraphExec_t setup_exec = nullptr, resid_exec = nullptr, restart_exec = nullptr, out_exec = nullptr;
   MgHost mg;
+  // the product of all groups in one launch (k_elem_fused): on when the
+  // autotuner measured it faster than one launch per group
+  bool fused = false;
+  int fused_tile_begin = 0, fused_n_tiles = 0;
+  size_t fused_lds = 0;
+  GroupDev* d_groups_cur = nullptr;  // the groups' current device views (after the last rebuild_tiles)
   // element-block Schwarz smoother (MTO_PRECOND_MG_ASM)
   GroupDev* d_groups = nullptr;
   int32_t *d_el_group = nullptr, *d_el_col = nullptr;
@@ -320,6 +326,43 @@ int rebuild_tiles(mto_plan* P) {
     else
       g.ms_n_tiles = (int)P->tiles.size() - g.ms_tile_begin;
   }
+  // the combined tiles of the fused product: 64 columns, groups by decreasing work per column
+  {
+    std::vector<int> order(P->groups.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      const GroupHost &a = P->groups[x], &b = P->groups[y];
+      return (double)a.S * a.ne * a.ne > (double)b.S * b.ne * b.ne;
+    });
+    P->fused_tile_begin = (int)P->tiles.size();
+    P->fused_lds = 0;
+    for (int gi : order) {
+      const GroupHost& g = P->groups[gi];
+      P->fused_lds = std::max(P->fused_lds, elem_lds_staged_bytes(g.p, 1));
+      for (int i = 0; i < P->n_inst; ++i) {
+        const int a = g.inst_begin[i], b = g.inst_begin[i + 1];
+        if (a == b) continue;
+        int sysi = 0;
+        for (int k = 0; k < i; ++k) sysi += P->L[k];
+        for (int l = 0; l < P->L[i]; ++l) {
+          const SysDesc& sd = P->sys[sysi + l];
+          for (int e = a; e < b; e += 64) {
+            Tile t{};
+            t.dof_off = sd.dof_off;
+            t.slot_off = sd.slot_off;
+            t.group = (int32_t)gi;
+            t.sys = sysi + l;
+            t.elem_begin = e;
+            t.count = std::min(64, b - e);
+            t.pc_begin = sd.chunk_begin;
+            t.pc_end = sd.chunk_end;
+            P->tiles.push_back(t);
+          }
+        }
+      }
+    }
+    P->fused_n_tiles = (int)P->tiles.size() - P->fused_tile_begin;
+  }
   if (P->tiles.size() > P->tiles_cap) {
     if (P->d_tiles) {
       (void)hipFree(P->d_tiles);
@@ -332,6 +375,15 @@ int rebuild_tiles(mto_plan* P) {
   }
   if (!P->tiles.empty())
     HIP_TRY(hipMemcpy(P->d_tiles, P->tiles.data(), P->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  {
+    std::vector<GroupDev> gd;
+    for (auto& g : P->groups) gd.push_back(P->gdev(g));
+    if (!P->d_groups_cur) {
+      int rc = dev_alloc(P, &P->d_groups_cur, gd.size());
+      if (rc) return rc;
+    }
+    if (!gd.empty()) HIP_TRY(hipMemcpy(P->d_groups_cur, gd.data(), gd.size() * sizeof(GroupDev), hipMemcpyHostToDevice));
+  }
   destroy_graphs(P);
   return MTO_OK;
 }
@@ -377,8 +429,9 @@ bool read_tile_cache(const char* path, std::map<TileKey, TileChoice>& out) {
     TileKey k;
     TileChoice v;
     if (sscanf(line, "%63s %d %d %d %d %d %lf", arch, &k.p, &k.d, &k.size_class, &v.ncol, &v.ks, &v.us) != 7 ||
-        (v.ncol != 1 && v.ncol != 2 && v.ncol != 4) || v.ks < 0 || v.ks > 8 || k.p < 1 || k.p > MTO_MAX_P ||
-        k.d < 1 || k.d > MTO_MAX_D || (v.ks == 0 && (k.p < 3 || v.ncol == 4))) {
+        (v.ncol != 1 && v.ncol != 2 && v.ncol != 4) || v.ks < 0 || v.ks > 8 || k.p < 0 || k.p > MTO_MAX_P ||
+        k.d < 0 || k.d > MTO_MAX_D * MTO_MAX_P || (k.p > 0 && k.d < 1) || (k.p > 0 && k.d > MTO_MAX_D) ||
+        (k.p > 0 && v.ks == 0 && (k.p < 3 || v.ncol == 4)) || (k.p == 0 && (v.ks != 0 || v.ncol == 4))) {
       ok = false;
       break;
     }
@@ -394,7 +447,8 @@ bool write_tile_cache(const char* path, const std::map<TileKey, TileChoice>& c) 
   FILE* fh = fopen(tmp.c_str(), "w");
   if (!fh) return false;
   fprintf(fh, "# element-contraction tile shapes: arch p d size_class(log2 columns) ncol ks us_per_launch"
-              " (ks 0: LDS-staged tables, 64 ncol columns per tile)\n");
+              " (ks 0: LDS-staged tables, 64 ncol columns per tile; p 0: the plan's choice between one launch"
+              " for all its d groups (ncol 1) and one per group (ncol 2))\n");
   for (auto& kv : c)
     fprintf(fh, "%s %d %d %d %d %d %.3f\n", kv.first.arch.c_str(), kv.first.p, kv.first.d, kv.first.size_class,
             kv.second.ncol, kv.second.ks, kv.second.us);
@@ -894,6 +948,11 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
 
 void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_t st) {
   const PcgDev s = P->pcg();
+  if (P->fused && P->prm.kernel_path == MTO_PATH_MFMA) {
+    launch_elem_fused(P->d_groups_cur, P->d_tiles, P->fused_tile_begin, P->fused_n_tiles, P->n_sys > 1 ? 8 : 0,
+                      P->fused_lds, P->E, xin, s, mode, it_k, st);
+    return;
+  }
   for (auto& g : P->groups) launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, xin, s, mode, it_k, st);
 }
 
@@ -1641,8 +1700,13 @@ int mto_weighted_sensitivity(mto_plan* P, const double* g, const double* w, doub
 
 int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol, int32_t ks) {
   g_err.clear();
+  if (P && ks == -1) {  // the fused product: one launch over every group
+    P->fused = true;
+    return rebuild_tiles(P);
+  }
   if (!P || (ncol != 1 && ncol != 2 && ncol != 4) || ks < 0 || ks > 8)
-    return fail(MTO_EINVAL, "ncol must be 1, 2 or 4 and ks 0..8");
+    return fail(MTO_EINVAL, "ncol must be 1, 2 or 4 and ks -1..8");
+  P->fused = false;
   if (ks == 0 && ncol == 4) return fail(MTO_EINVAL, "the LDS-staged contraction takes ncol 1 or 2");
   for (auto& g : P->groups)
     if (p <= 0 || (g.p == p && g.d == d)) {
@@ -1754,8 +1818,46 @@ int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* s
     cache[key] = TileChoice{best_nc, best_ks, 1e3 * best};
     changed = true;
   }
+  // one launch for all groups (the fused product) or one per group
+  {
+    int64_t cols = 0;
+    for (auto& g : P->groups) cols += (int64_t)(g.flops / (2.0 * g.S * g.ne * g.ne));
+    const TileKey key{arch, 0, (int)P->groups.size(), size_class((double)cols)};
+    auto hit = cache.find(key);
+    if (hit != cache.end()) {
+      P->fused = hit->second.ncol == 1;
+    } else {
+      double tm[2] = {0.0, 0.0};
+      for (int f = 0; f < 2; ++f) {
+        P->fused = f == 1;
+        int rc = rebuild_tiles(P);
+        if (rc) return rc;
+        for (int w = 0; w < 3; ++w) enq_elem_all(P, P->q, ELEM_APPLY, 0, st);
+        const int reps = 20;
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int w = 0; w < reps; ++w) enq_elem_all(P, P->q, ELEM_APPLY, 0, st);
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        tm[f] = ms / reps;
+      }
+      P->fused = tm[1] < tm[0];
+      char line[160];
+      snprintf(line, sizeof line, "all groups: one launch per group %.3f us, one fused launch %.3f us\n", 1e3 * tm[0],
+               1e3 * tm[1]);
+      rep += line;
+      cache[key] = TileChoice{P->fused ? 1 : 2, 0, 1e3 * std::min(tm[0], tm[1])};
+      changed = true;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  {
+    char line[96];
+    snprintf(line, sizeof line, "product: %s\n", P->fused ? "fused (one launch for all groups)" : "one launch per group");
+    rep += line;
+  }
   for (auto& g : P->groups) {
     char line[96];
     snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=%d: chosen\n", g.p, g.d, g.lds_nc ? g.lds_nc : g.ncol,
@@ -1808,12 +1910,19 @@ int mto_time_contraction(mto_plan* P, const double* rho, int32_t reps, int32_t i
   const size_t ng = P->groups.size();
   std::vector<hipEvent_t> ev(2 * ng * (size_t)reps, nullptr);
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  const bool fused = P->fused && P->prm.kernel_path == MTO_PATH_MFMA;
   for (int i = 0; i < reps; ++i) {
     const int k = i % G;
-    for (size_t gi = 0; gi < ng; ++gi) {
-      auto& g = P->groups[gi];
-      hipEvent_t* e = &ev[2 * (ng * i + gi)];
-      launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, P->p, s, ELEM_PCG, k, st, e[0], e[1]);
+    if (fused) {
+      hipEvent_t* e = &ev[2 * (ng * i)];
+      launch_elem_fused(P->d_groups_cur, P->d_tiles, P->fused_tile_begin, P->fused_n_tiles, P->n_sys > 1 ? 8 : 0,
+                        P->fused_lds, P->E, P->p, s, ELEM_PCG, k, st, e[0], e[1]);
+    } else {
+      for (size_t gi = 0; gi < ng; ++gi) {
+        auto& g = P->groups[gi];
+        hipEvent_t* e = &ev[2 * (ng * i + gi)];
+        launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, P->p, s, ELEM_PCG, k, st, e[0], e[1]);
+      }
     }
     launch_dof1(s, k, st);
     launch_dof2(s, k, st);
@@ -1823,7 +1932,8 @@ int mto_time_contraction(mto_plan* P, const double* rho, int32_t reps, int32_t i
   HIP_TRY(hipStreamSynchronize(st));
   double total = 0.0;
   for (size_t j = 0; j < ng * (size_t)reps; ++j) {
-    if (P->groups[j % ng].n_tiles == 0) continue;  // nothing launched, events never recorded
+    if (fused ? (j % ng != 0 || P->fused_n_tiles == 0) : P->groups[j % ng].n_tiles == 0)
+      continue;  // nothing launched, events never recorded
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
     total += ms;

@@ -83,7 +83,7 @@ def test_matvec_every_group(cuda, p, d):
     on a 7 x 5 mesh (35 elements: several 16-column tiles and a ragged tail)
     with several tile widths and density-cell splits across waves, and for
     p >= 3 the LDS-staged contraction (ks = 0: one 64- or 128-column tile,
-    ragged)."""
+    ragged); ks = -1 is the fused one-launch product."""
     pr = P.uniform_random(7, 5, p, d, seed=100 + 10 * p + d)
     K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
     free = free_mask(space, pr.supports)
@@ -94,7 +94,7 @@ def test_matvec_every_group(cuda, p, d):
     plan = mto().Plan(pr)
     rho = torch.tensor(pr.rho, device=cuda)
     xt = torch.tensor(x, device=cuda)
-    shapes = [(1, 1), (2, 2), (1, 4), (4, 1), (1, 8)] + ([(1, 0), (2, 0)] if p >= 3 else [])
+    shapes = [(1, 1), (2, 2), (1, 4), (4, 1), (1, 8), (1, -1)] + ([(1, 0), (2, 0)] if p >= 3 else [])
     for ncol, ks in shapes:
         plan.set_tile(ncol, ks)
         y = plan.apply_stiffness(rho, xt).cpu().numpy()
@@ -130,8 +130,10 @@ def random_orders_mesh():
     return P.uniform_random(8, 5, rng.integers(1, 5, 40), rng.integers(1, 9, 40), 61)
 
 
-@pytest.mark.parametrize("path", [0, 1])
-def test_matvec_random_orders(cuda, path):
+@pytest.mark.parametrize("path,fused", [(0, False), (0, True), (1, False)])
+def test_matvec_random_orders(cuda, path, fused):
+    """26 (p, d) groups of one to four elements: per-group launches, the fused
+    one-launch product (tiles of all groups in one grid) and the plain path."""
     pr = random_orders_mesh()
     K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
     free = free_mask(space, pr.supports)
@@ -140,6 +142,8 @@ def test_matvec_random_orders(cuda, path):
     yref = K @ x
     yref[~free] = 0.0
     plan = mto().Plan(pr, kernel_path=path)
+    if fused:
+        plan.set_tile(1, -1)
     y = plan.apply_stiffness(torch.tensor(pr.rho, device=cuda), torch.tensor(x, device=cuda)).cpu().numpy()
     assert rel(y, yref) < 1e-13
 
@@ -441,9 +445,11 @@ def test_invalid_density_rejected(cuda, bad):
 
 def test_autotune_cache(cuda, tmp_path):
     """The tile-shape cache: a first autotune times every group and writes one
-    line per (arch, p, d, size class); a second plan of the same mesh takes
-    every shape from the file without timing and solves to the same bits as
-    the first; a malformed file is MTO_EINVAL."""
+    line per (arch, p, d, size class), plus one line (p = 0) for the choice
+    between one launch per group and the fused launch; a second plan of the
+    same mesh takes every shape and that choice from the file without timing
+    and solves to the same bits as the first; a malformed file is
+    MTO_EINVAL."""
     m = mto()
     pr = P.small_mixed(16, 8, seed=45)
     rho = torch.tensor(pr.rho, device=cuda)
@@ -451,13 +457,16 @@ def test_autotune_cache(cuda, tmp_path):
     a = m.Plan(pr)
     rep_a = a.autotune(rho, cache=str(path))
     lines = [ln for ln in path.read_text().splitlines() if not ln.startswith("#")]
-    assert len(lines) == a.info["n_groups"], (lines, rep_a)
+    assert len(lines) == a.info["n_groups"] + 1, (lines, rep_a)
+    assert sum(ln.split()[1] == "0" for ln in lines) == 1
     assert "cached" not in rep_a
+    product = [ln for ln in rep_a.splitlines() if ln.startswith("product:")]
     b = m.Plan(pr)
     rep_b = b.autotune(rho, cache=str(path))
     assert rep_b.count("cached") == a.info["n_groups"], rep_b
     assert sorted(l for l in rep_a.splitlines() if l.endswith("chosen")) == \
         sorted(l for l in rep_b.splitlines() if l.endswith("chosen"))
+    assert product == [ln for ln in rep_b.splitlines() if ln.startswith("product:")]
     ua, ca, ga, _ = a.solve(rho)
     ub, cb, gb, _ = b.solve(rho)
     assert torch.equal(ua, ub) and torch.equal(ca, cb) and torch.equal(ga, gb)
@@ -502,3 +511,15 @@ def test_lds_staged_product_many_tiles(cuda):
         y = plan.apply_stiffness(rho, xt).cpu().numpy()
         assert rel(y, yref.ravel()) < 1e-13, (nc, rel(y, yref.ravel()))
         assert rel(y, y1) < 1e-14
+
+
+@pytest.mark.parametrize("name", ["mixed16x8", "mixed_3loads", "uniform_p4d5"])
+def test_solve_parity_fused_product(cuda, name):
+    """Solves with the fused product (one launch over the tiles of every
+    (p, d) group and system) against the oracle."""
+    prs = CASES[name]()
+    plan = mto().Plan(prs)
+    plan.set_tile(1, -1)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
