@@ -16,6 +16,22 @@ namespace mto {
 constexpr int ne_of(int p) { return 2 * (p + 1) * (p + 1); }
 constexpr int nep_of(int p) { return (ne_of(p) + 3) / 4 * 4; }
 constexpr int mb_of(int p) { return (ne_of(p) + 15) / 16; }
+// Orders whose last row block would hold only 2 of its 16 rows (p = 2: 18
+// rows, p = 4: 50 rows): the LDS-staged contraction runs the full 16-row
+// blocks on MFMA and those last rows as FP64 FMAs on the vector ALU, which
+// runs at the same FP64 rate as MFMA on gfx950 and overlaps it.
+constexpr bool valu_tail(int p) { return ne_of(p) % 16 == 2 && ne_of(p) > 16; }
+constexpr int mbm_of(int p) { return valu_tail(p) ? ne_of(p) / 16 : mb_of(p); }  // MFMA row blocks
+constexpr int tr_of(int p) { return valu_tail(p) ? ne_of(p) % 16 : 0; }           // rows on the vector ALU
+// Doubles per k-step of the LDS-staged contraction's tables (staged_fragments).
+constexpr int frj_of(int p) { return mbm_of(p) * 64 + 4 * tr_of(p); }
+
+// Element-block Schwarz smoother: the packed upper triangle of an element's
+// block inverse, padded to an even count (so every element's triangle starts
+// on 16 bytes), and the element columns per block of its application
+// (NE rows each, at most 256 threads, the blocks' triangles staged in LDS).
+constexpr int asm_ntp_of(int p) { return (ne_of(p) * (ne_of(p) + 1) / 2 + 1) / 2 * 2; }
+constexpr int asm_cols_of(int p) { return p == 1 ? 32 : p == 2 ? 14 : p == 3 ? 8 : 4; }
 
 // Host-side K_s tables of Appendix B's composite integration:
 // ks[s*ne*ne + i*ne + j] for density cell s of a d x d grid.
@@ -35,6 +51,13 @@ std::vector<double> qr_load_transfer(int p);
 // Kcat[mb*16 + l%16][4t + l/16], with Kcat[row][s*NEP + j] = K_s[row][j]
 // (zero outside n_e).  Result length T*MB*64 with T = d*d*NEP/4.
 std::vector<double> mfma_fragments(const std::vector<double>& ks, int p, int d);
+
+// The tables of the LDS-staged contraction, [S][NEP/4][frj_of(p)]: for k-step
+// jj of cell s, the A fragments of the mbm_of(p) MFMA row blocks as in
+// mfma_fragments, then (valu_tail orders) the last tr_of(p) rows at the
+// step's 4 reduction indices, [kq][r] = K_s[16 mbm + r][4 jj + kq] (zero
+// beyond n_e).  Without a vector-ALU tail it equals mfma_fragments.
+std::vector<double> staged_fragments(const std::vector<double>& ks, int p, int d);
 
 // The columns of K_s at the element's 8 vertex DOFs (local DOFs 0..3 and
 // 2(p+1)..2(p+1)+3, k = 0..7 in that order) as MFMA A operands: for k-step jj

@@ -470,21 +470,26 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
 
 // ---------------------------------------------------------------------------
 // Element contraction with the cell tables staged in LDS, for the groups whose
-// tables are large (p >= 3): one block of 4 waves per tile of 64 NC element
-// columns, wave w taking columns [16 NC w, 16 NC (w + 1)).  Every wave runs all
-// density cells.  The A fragments of the next cell are loaded from L2 by the
-// whole block into the other half of an LDS double buffer while the current
-// cell's MFMAs run, so each fragment is read from L2 once per 64 NC columns
-// (instead of once per 16 NC in k_elem_mfma) and from LDS by the four waves.
-// The gathered element vectors (p = z + beta p_old formed once, rigid motion
-// removed as in k_elem_mfma) sit in LDS as well; each wave writes its own
-// columns' slots.  Results are the same sums as k_elem_mfma with ks = 1.
+// tables are large (p >= 3, and every group in the fused launch): one block of
+// 4 waves per tile of 64 NC element columns, wave w taking columns
+// [16 NC w, 16 NC (w + 1)).  Every wave runs all density cells.  The tables of
+// the next cell are loaded from L2 by the whole block into the other half of
+// an LDS double buffer while the current cell's MFMAs run, so each table is
+// read from L2 once per 64 NC columns (instead of once per 16 NC in
+// k_elem_mfma) and from LDS by the four waves.  The gathered element vectors
+// (p = z + beta p_old formed once, rigid motion removed as in k_elem_mfma) sit
+// in LDS as well; each wave writes its own columns' slots.  For the orders
+// with a vector-ALU tail (valu_tail: p = 2, 4) the last 2 rows are FMAs of
+// each lane's B value with the 2 table entries of its reduction index,
+// summed over the 4 lanes that share a column at the end, instead of a
+// 16-row MFMA block of which 14 rows are padding.
 template <int P, int NC>
 __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, const double* __restrict__ E,
                                               const double* __restrict__ xin, const PcgDev& s, int mode, int it_k,
                                               double* lds) {
-  constexpr int NE = ne_of(P), NEP = nep_of(P), MB = mb_of(P), NJ = NEP / 4, WC = 16 * NC, TC = 4 * WC;
-  constexpr int FR = NJ * MB * 64;         // doubles of one cell's A fragments
+  constexpr int NE = ne_of(P), NEP = nep_of(P), NJ = NEP / 4, WC = 16 * NC, TC = 4 * WC;
+  constexpr int MB = mbm_of(P), TR = tr_of(P), FRJ = frj_of(P);
+  constexpr int FR = NJ * FRJ;             // doubles of one cell's tables
   constexpr int FPT = (FR + 255) / 256;    // of those, per thread
   constexpr int NT = NEP * TC, GPT = (NT + 255) / 256;  // gathered entries, per thread
   double* afr = lds;                // [2][FR]
@@ -499,6 +504,7 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
   int cellb[NC];
   bool valid[NC];
   int sidx[NC][MB][4];
+  int sidt[NC];  // the tail row 16 MB + kq (kq < TR)
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int col = wave * WC + c * 16 + n;
@@ -511,9 +517,10 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
         const int row = b * 16 + kq + 4 * r;
         sidx[c][b][r] = (valid[c] && row < NE) ? g.sidx[row * g.npad + t.elem_begin + col] : -1;
       }
+    sidt[c] = (TR > 0 && valid[c] && kq < TR) ? g.sidx[(16 * MB + kq) * g.npad + t.elem_begin + col] : -1;
   }
-  // cell 0's fragments: global loads now, LDS stores after the gather loads are issued
-  const double* __restrict__ kf = g.kfrag;
+  // cell 0's tables: global loads now, LDS stores after the gather loads are issued
+  const double* __restrict__ kf = g.kfrags;
   double stg[FPT];
 #pragma unroll
   for (int k = 0; k < FPT; ++k) {
@@ -581,6 +588,11 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
   for (int b = 0; b < MB; ++b)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[b][c] = d4{0.0, 0.0, 0.0, 0.0};
+  double tacc[NC][TR > 0 ? TR : 1];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < TR; ++r) tacc[c][r] = 0.0;
   double e[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) e[c] = valid[c] ? E[cellb[c]] : 0.0;
@@ -589,7 +601,7 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
     double* __restrict__ nxt = afr + ((sc + 1) & 1) * FR;
     const bool more = sc + 1 < g.S;
     double en[NC];
-    if (more) {  // next cell: fragments and moduli in flight during this cell's MFMAs
+    if (more) {  // next cell: tables and moduli in flight during this cell's MFMAs
       const double* __restrict__ kn = kf + (size_t)(sc + 1) * FR;
 #pragma unroll
       for (int k = 0; k < FPT; ++k) {
@@ -603,12 +615,17 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
     for (int jj = 0; jj < NJ; ++jj) {
       double a[MB];
 #pragma unroll
-      for (int b = 0; b < MB; ++b) a[b] = cur[(jj * MB + b) * 64 + lane];
+      for (int b = 0; b < MB; ++b) a[b] = cur[jj * FRJ + b * 64 + lane];
+      double ta[TR > 0 ? TR : 1];
+#pragma unroll
+      for (int r = 0; r < TR; ++r) ta[r] = cur[jj * FRJ + MB * 64 + kq * TR + r];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double bv = e[c] * u[c][jj];
 #pragma unroll
         for (int b = 0; b < MB; ++b) acc[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b], bv, acc[b][c], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < TR; ++r) tacc[c][r] = fma(ta[r], bv, tacc[c][r]);
       }
     }
     if (more) {
@@ -620,7 +637,7 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
 #pragma unroll
       for (int c = 0; c < NC; ++c) e[c] = en[c];
     }
-    __syncthreads();  // the next cell's fragments are in; this cell's buffer may be overwritten
+    __syncthreads();  // the next cell's tables are in; this cell's buffer may be overwritten
   }
   double* __restrict__ sl = s.slots + t.slot_off;
 #pragma unroll
@@ -630,6 +647,22 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (sidx[c][b][r] >= 0) sl[sidx[c][b][r]] = acc[b][c][r];
+  if constexpr (TR > 0) {
+    // tail rows: sum over the 4 lanes of each column ((a + b) + (c + d), the
+    // same value in all four), lane kq writes row 16 MB + kq
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double mine = 0.0;
+#pragma unroll
+      for (int r = 0; r < TR; ++r) {
+        double v = tacc[c][r];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (kq == r) mine = v;
+      }
+      if (sidt[c] >= 0) sl[sidt[c]] = mine;
+    }
+  }
 }
 
 template <int P, int NC>

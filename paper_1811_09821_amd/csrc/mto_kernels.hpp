@@ -18,9 +18,10 @@ struct GroupDev {
   int32_t lds_nc;          // > 0: the contraction runs k_elem_mfma_lds<P, lds_nc> (p >= 3) on the
   int32_t lds_tile_begin;  //   tiles of 64 lds_nc columns [lds_tile_begin, + lds_n_tiles)
   int32_t lds_n_tiles;
-  int32_t ms_tile_begin;   // tiles of the first system of every instance (16 ncol columns), on which the
-  int32_t ms_n_tiles;      //   Schwarz application serves all systems of the instance
+  int32_t ms_tile_begin;   // tiles of the first system of every instance (asm_cols_of(p) columns), on
+  int32_t ms_n_tiles;      //   which the Schwarz application serves all systems of the instance
   const double* kfrag;     // MFMA A fragments [S*NEP/4][MB][64]
+  const double* kfrags;    // the LDS-staged contraction's tables [S][NEP/4][frj_of(p)] (staged_fragments)
   const double* kfragv;    // the vertex columns of K_s as A fragments [S][2][MB][64] (vertex_fragments)
   const double* ks;        // plain K_s [S][ne][ne]
   const double* kdiag;     // diag(K_s) [S][ne]
@@ -148,7 +149,7 @@ constexpr size_t ELEM_LDS_LIMIT = 64 * 1024;
 // Dynamic LDS of the LDS-staged contraction k_elem_mfma_lds<P, nc>: the A
 // fragments of two cells, the tile's 64 nc element vectors and two scalars.
 inline size_t elem_lds_staged_bytes(int p, int nc) {
-  const size_t fr = (size_t)(nep_of(p) / 4) * mb_of(p) * 64;
+  const size_t fr = (size_t)(nep_of(p) / 4) * frj_of(p);
   return 8 * (2 * fr + (size_t)nep_of(p) * 64 * nc + 2);
 }
 constexpr size_t ELEM_LDS_STAGED_LIMIT = 160 * 1024;
@@ -257,8 +258,8 @@ void launch_mg_post0(const PcgDev& s, int it_k, int init, hipStream_t st);
 // Per element column of group `gi`: the assembled operator restricted to the
 // element's free DOFs (own sum_s E_s K_s plus the shared-DOF entries of the
 // eight neighbours), inverted; binv holds its upper triangle packed by rows,
-// tile-major: [npad / 16][ne (ne + 1) / 2][16] (16 consecutive element
-// columns entry by entry), zero rows/columns at absent or supported DOFs.  groups: device array of all group views;
+// element-major: [npad][asm_ntp_of(p)] (the last entry of an odd count is
+// padding), zero rows/columns at absent or supported DOFs.  groups: device array of all group views;
 // nbr [8][npad]: global element index of each neighbour (-1: none);
 // el_group / el_col: group and column of every global element.
 void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const int32_t* nbr, const int32_t* el_group,

@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mto_kernels.hpp"
 
 namespace mto {
@@ -1060,95 +1062,112 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
     if (b < a) continue;
     double v = 0.5 * (A[a][b] + A[b][a]) * sc[a] * sc[b];
     if (gid[a] < 0 || gid[b] < 0) v = 0.0;
-    // tile-major: 16 consecutive elements' packed triangles, entry by entry
-    binv[((int64_t)(k >> 4) * (NE * (NE + 1) / 2) + packed_index<NE>(a, b)) * 16 + (k & 15)] = v;
+    binv[(int64_t)k * asm_ntp_of(P) + packed_index<NE>(a, b)] = v;
   }
 }
 
-// slots2 = omega * B_e v_e.  One block per 16 element columns of a tile
-// (blockIdx.y picks the 16-column part); thread = (row, column), one row of
-// B_e per thread.  Each thread first loads its whole row from the packed
-// upper triangle (row a takes entry (min(a, b), max(a, b))), so the loads
-// overlap the gather, then contracts it with the gathered v_e in LDS.
-template <int P>
-constexpr int asm_rows() { return (ne_of(P) + 3) / 4 * 4; }
-
-// Up to ASM_SYS systems of one instance per pass over a tile: the element
-// blocks B_e are shared by the load cases of an instance, so one read of a
-// block's row serves all of them.
+// slots2 = omega * B_e v_e.  One block of 256 threads per tile of
+// EB = asm_cols_of(P) element columns of an instance's first system; thread
+// (column c, row a) for the first NE EB threads.  The tile's packed
+// triangles are one contiguous range of binv, read once from HBM with 16-byte
+// loads by all threads and staged in LDS (each entry serves rows a and b);
+// the loads are issued before the element vectors are gathered, so the two
+// overlap.  Row a then sums B(a, b) v_b in order of b from LDS.  Up to
+// ASM_SYS systems of the instance per pass: the element blocks are shared by
+// its load cases, so one read of a block serves all of them.
 constexpr int ASM_SYS = 4;
+constexpr int ASM_THREADS = 256;
 
 template <int P>
-__global__ __launch_bounds__(16 * asm_rows<P>()) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
-                                                                  const double* __restrict__ binv,
-                                                                  const double* __restrict__ v, PcgDev s,
-                                                                  double* __restrict__ out_slots, double omega,
-                                                                  int resid) {
-  constexpr int NE = ne_of(P);
-  __shared__ double vs[ASM_SYS][NE][17];
+__global__ __launch_bounds__(ASM_THREADS) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
+                                                           const double* __restrict__ binv,
+                                                           const double* __restrict__ v, PcgDev s,
+                                                           double* __restrict__ out_slots, double omega, int resid) {
+  constexpr int NE = ne_of(P), NTP = asm_ntp_of(P), EB = asm_cols_of(P);
+  static_assert(NE * EB <= ASM_THREADS, "one thread per row and column");
+  constexpr int NB2 = EB * NTP / 2;                          // 16-byte words of the tile's triangles
+  constexpr int LPT = (NB2 + ASM_THREADS - 1) / ASM_THREADS;  // of those, per thread
+  __shared__ double2 bs2[NB2];
+  __shared__ double vs[ASM_SYS][EB][NE];
+  const double* bs = (const double*)bs2;
   // a tile of the first system of its instance; the instance's other systems
   // follow it (instance-major numbering), their count is in pc_begin
   const Tile t = tiles[g.ms_tile_begin + blockIdx.x];
-  const int c0 = blockIdx.y * 16;
-  if (c0 >= t.count) return;  // uniform over the block
-  const int c = threadIdx.x & 15, a = threadIdx.x >> 4;
-  const bool valid = c0 + c < t.count;
-  const int col = t.elem_begin + c0 + (valid ? c : 0);
-  const int64_t np = g.npad;
   const int nsys = t.pc_begin;
   {  // nothing to do once every system of the instance has stopped (no block read)
     bool any = false;
     for (int l = 0; l < nsys; ++l) any |= s.status[t.sys + l] == SYS_RUNNING;
     if (!any) return;  // uniform over the block
   }
-  // the 16 elements of this block (tile-major storage) read one contiguous run
-  const double* __restrict__ bp = binv + (int64_t)(col >> 4) * (NE * (NE + 1) / 2) * 16 + (col & 15);
-  // the first H entries of the row are requested before the gather, the rest
-  // (p = 4 only, to stay within the registers of 13 waves) after it
-  constexpr int H = NE <= 32 ? NE : NE / 2;
-  auto entry = [&](int b) -> double {
-    return a < NE ? bp[(b < a ? packed_index<NE>(b, a) : packed_index<NE>(a, b)) * 16] : 0.0;
-  };
-  double brow[H];
+  const int tid = threadIdx.x;
+  // the triangles of columns [elem_begin, elem_begin + count): the words of
+  // absent columns (a partial last tile) are not read
+  const double2* __restrict__ src = (const double2*)(binv + (int64_t)t.elem_begin * NTP);
+  const int nw = t.count * (NTP / 2);
+  double2 stg[LPT];
 #pragma unroll
-  for (int b = 0; b < H; ++b) brow[b] = entry(b);
-  const int id = (a < NE && valid) ? g.gidx[a * np + col] : -1;
-  const int si = (a < NE && valid) ? g.sidx[a * np + col] : -1;
+  for (int k = 0; k < LPT; ++k) {
+    const int i = tid + ASM_THREADS * k;
+    stg[k] = i < nw ? src[i] : double2{0.0, 0.0};
+  }
+  const int c = tid / NE, a = tid - c * NE;
+  const bool act = c < EB && c < t.count;
+  const int64_t col = t.elem_begin + (act ? c : 0);
+  const int id = act ? g.gidx[a * (int64_t)g.npad + col] : -1;
+  const int si = act ? g.sidx[a * (int64_t)g.npad + col] : -1;
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = tid + ASM_THREADS * k;
+    if (i < NB2) bs2[i] = stg[k];
+  }
+  // row a of the packed triangle: entry (min(a, b), max(a, b)) at
+  // b < a: packed(b, a) = cb + a, b >= a: packed(a, b) = ra + b
+  const int ra = a * NE - (a * (a - 1)) / 2 - a;
+  const double* __restrict__ brow = bs + (act ? c : 0) * NTP;
   for (int l0 = 0; l0 < nsys; l0 += ASM_SYS) {
+    const int np = min(ASM_SYS, nsys - l0);
     bool run[ASM_SYS];
 #pragma unroll
     for (int l = 0; l < ASM_SYS; ++l) {  // the same addresses in every lane: one load each
-      const int sys = t.sys + l0 + (l0 + l < nsys ? l : 0);
-      const bool st = s.status[sys] == SYS_RUNNING;
-      run[l] = l0 + l < nsys && st;
+      const int sys = t.sys + l0 + (l < np ? l : 0);
+      run[l] = l < np && s.status[sys] == SYS_RUNNING;
     }
-    if (a < NE) {
+    if (act) {
 #pragma unroll
       for (int l = 0; l < ASM_SYS; ++l) {
-        if (!run[l]) continue;
-        const SysDesc& sd = s.sys[t.sys + l0 + l];
+        if (l >= np) break;
         double x = 0.0;
-        if (id >= 0) {
+        if (run[l] && id >= 0) {
+          const SysDesc& sd = s.sys[t.sys + l0 + l];
           const double* __restrict__ vsys = v + sd.dof_off;
           x = resid ? vsys[id] - slot_sum(s.slots + sd.slot_off, id, sd.nfv, sd.nfe) : vsys[id];
         }
-        vs[l][a][c] = x;
+        vs[l][c][a] = x;
       }
     }
-    __syncthreads();
-    if (a < NE) {
+    __syncthreads();  // the triangles (first pass) and the element vectors are in LDS
+    if (act) {
+      double acc[ASM_SYS] = {0.0, 0.0, 0.0, 0.0};
+      const double* __restrict__ vc = &vs[0][c][0];
+      auto row = [&](auto nl) {
+        constexpr int NL = decltype(nl)::value;
+#pragma unroll 10
+        for (int b = 0; b < NE; ++b) {
+          const int cb = b * NE - (b * (b - 1)) / 2 - b;
+          const double e = brow[b < a ? cb + a : ra + b];
 #pragma unroll
-      for (int l = 0; l < ASM_SYS; ++l) {
-        if (!run[l]) continue;
-        double acc = 0.0;
-#pragma unroll
-        for (int b = 0; b < H; ++b) acc = fma(brow[b], vs[l][b][c], acc);
-        if constexpr (H < NE) {
-#pragma unroll 5
-          for (int b = H; b < NE; ++b) acc = fma(entry(b), vs[l][b][c], acc);
+          for (int l = 0; l < NL; ++l) acc[l] = fma(e, vc[l * EB * NE + b], acc[l]);
         }
-        if (si >= 0) out_slots[s.sys[t.sys + l0 + l].slot_off + si] = omega * acc;
+      };
+      switch (np) {  // uniform over the block
+        case 1: row(std::integral_constant<int, 1>{}); break;
+        case 2: row(std::integral_constant<int, 2>{}); break;
+        case 3: row(std::integral_constant<int, 3>{}); break;
+        default: row(std::integral_constant<int, 4>{}); break;
       }
+#pragma unroll
+      for (int l = 0; l < ASM_SYS; ++l)
+        if (l < np && run[l] && si >= 0) out_slots[s.sys[t.sys + l0 + l].slot_off + si] = omega * acc[l];
     }
     if (l0 + ASM_SYS < nsys) __syncthreads();  // vs is rewritten by the next pass
   }
@@ -1257,24 +1276,12 @@ void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const i
 void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, int resid,
                       const PcgDev& s, double* slots2, double omega, hipStream_t st) {
   if (g.ms_n_tiles == 0) return;
-  const dim3 grid(g.ms_n_tiles, g.ncol);  // tiles hold at most 16 ncol columns
+  const dim3 grid(g.ms_n_tiles), block(ASM_THREADS);  // tiles hold asm_cols_of(p) columns
   switch (g.p) {
-    case 1:
-      hipLaunchKernelGGL(k_asm_apply<1>, grid, dim3(16 * asm_rows<1>()), 0, st, g, tiles, binv, v, s, slots2, omega,
-                         resid);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_asm_apply<2>, grid, dim3(16 * asm_rows<2>()), 0, st, g, tiles, binv, v, s, slots2, omega,
-                         resid);
-      break;
-    case 3:
-      hipLaunchKernelGGL(k_asm_apply<3>, grid, dim3(16 * asm_rows<3>()), 0, st, g, tiles, binv, v, s, slots2, omega,
-                         resid);
-      break;
-    default:
-      hipLaunchKernelGGL(k_asm_apply<4>, grid, dim3(16 * asm_rows<4>()), 0, st, g, tiles, binv, v, s, slots2, omega,
-                         resid);
-      break;
+    case 1: hipLaunchKernelGGL(k_asm_apply<1>, grid, block, 0, st, g, tiles, binv, v, s, slots2, omega, resid); break;
+    case 2: hipLaunchKernelGGL(k_asm_apply<2>, grid, block, 0, st, g, tiles, binv, v, s, slots2, omega, resid); break;
+    case 3: hipLaunchKernelGGL(k_asm_apply<3>, grid, block, 0, st, g, tiles, binv, v, s, slots2, omega, resid); break;
+    default: hipLaunchKernelGGL(k_asm_apply<4>, grid, block, 0, st, g, tiles, binv, v, s, slots2, omega, resid); break;
   }
 }
 void launch_asm_z(const PcgDev& s, const double* slots2, hipStream_t st) {

@@ -66,6 +66,7 @@ struct GroupHost {
   // per instance: element range [inst_begin[i], inst_begin[i+1]) in the group arrays
   std::vector<int32_t> inst_begin;
   double* kfrag = nullptr;
+  double* kfrags = nullptr;  // null without a vector-ALU tail (kfrag serves the LDS-staged kernel then)
   double* kfragv = nullptr;
   double* ks = nullptr;
   double* kdiag = nullptr;
@@ -235,6 +236,7 @@ struct mto_plan {
     o.ms_tile_begin = g.ms_tile_begin;
     o.ms_n_tiles = g.ms_n_tiles;
     o.kfrag = g.kfrag;
+    o.kfrags = g.kfrags ? g.kfrags : g.kfrag;
     o.kfragv = g.kfragv;
     o.ks = g.ks;
     o.kdiag = g.kdiag;
@@ -295,7 +297,7 @@ int rebuild_tiles(mto_plan* P) {
       g.lds_n_tiles = 0;
       continue;
     }
-    const int tile_cols = pass == 1 ? 64 * g.lds_nc : 16 * g.ncol;
+    const int tile_cols = pass == 1 ? 64 * g.lds_nc : pass == 2 ? asm_cols_of(g.p) : 16 * g.ncol;
     (pass == 0 ? g.tile_begin : pass == 1 ? g.lds_tile_begin : g.ms_tile_begin) = (int)P->tiles.size();
     for (int i = 0; i < P->n_inst; ++i) {
       const int a = g.inst_begin[i], b = g.inst_begin[i + 1];
@@ -665,7 +667,7 @@ int build_asm(mto_plan* P, const std::vector<InstanceHost>& I) {
     }
     if ((int64_t)G.ne * (G.ne + 1) / 2 * G.npad >= ((int64_t)1 << 31))
       return fail(MTO_EINVAL, "Schwarz smoother: too many elements of one (p, d) group for 32-bit block offsets");
-    if ((rc = dev_upload(P, &G.nbr, nbr)) || (rc = dev_alloc(P, &G.binv, (size_t)G.ne * (G.ne + 1) / 2 * G.npad))) return rc;
+    if ((rc = dev_upload(P, &G.nbr, nbr)) || (rc = dev_alloc(P, &G.binv, (size_t)asm_ntp_of(G.p) * G.npad))) return rc;
     gd.push_back(P->gdev(G));
   }
   if ((rc = dev_upload(P, &P->d_groups, gd)) || (rc = dev_upload(P, &P->d_el_group, el_group)) ||
@@ -860,6 +862,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     if ((rc = dev_upload(P, &g.gidx, gidx)) || (rc = dev_upload(P, &g.sidx, sidx)) ||
         (rc = dev_upload(P, &g.cell, cell)) || (rc = dev_upload(P, &g.ks, ks)) || (rc = dev_upload(P, &g.kfrag, kfr)) ||
         (rc = dev_upload(P, &g.kfragv, kfv)) ||
+        (valu_tail(g.p) && (rc = dev_upload(P, &g.kfrags, staged_fragments(ks, g.p, g.d)))) ||
         (rc = dev_upload(P, &g.kdiag, kdiag)) || (rc = dev_upload(P, &g.kabs, kabs)))
       return cleanup(rc);
     double per_col = 2.0 * g.S * g.ne * g.ne;

@@ -174,6 +174,26 @@ std::vector<double> mfma_fragments(const std::vector<double>& ks, int p, int d) 
   return fr;
 }
 
+std::vector<double> staged_fragments(const std::vector<double>& ks, int p, int d) {
+  const int ne = ne_of(p), nj = nep_of(p) / 4, mbm = mbm_of(p), tr = tr_of(p), frj = frj_of(p), S = d * d;
+  std::vector<double> fr((size_t)S * nj * frj, 0.0);
+  for (int s = 0; s < S; ++s)
+    for (int jj = 0; jj < nj; ++jj) {
+      double* f = &fr[((size_t)s * nj + jj) * frj];
+      for (int b = 0; b < mbm; ++b)
+        for (int l = 0; l < 64; ++l) {
+          const int row = b * 16 + (l % 16), j = 4 * jj + l / 16;
+          f[b * 64 + l] = (row < ne && j < ne) ? ks[(size_t)s * ne * ne + row * ne + j] : 0.0;
+        }
+      for (int kq = 0; kq < 4; ++kq)
+        for (int r = 0; r < tr; ++r) {
+          const int row = 16 * mbm + r, j = 4 * jj + kq;
+          f[mbm * 64 + kq * tr + r] = (row < ne && j < ne) ? ks[(size_t)s * ne * ne + row * ne + j] : 0.0;
+        }
+    }
+  return fr;
+}
+
 std::vector<double> vertex_fragments(const std::vector<double>& ks, int p, int d) {
   const int ne = ne_of(p), mb = mb_of(p), S = d * d;
   std::vector<double> fr((size_t)S * 2 * mb * 64, 0.0);
