@@ -1018,6 +1018,8 @@ __global__ __launch_bounds__(BLOCK) void k_sys_setup(PcgDev s, double rtol2) {
 __global__ __launch_bounds__(VBLOCK) void k_dof1(PcgDev s, int it_k) {
   __shared__ double lds[VWAVES + 4];
   const Chunk ch = s.chunks[blockIdx.x];
+  // a stopped system loads nothing (most of the batch, late in a solve)
+  if (s.status[ch.sys] != SYS_RUNNING) return;
   const int i = ch.begin + threadIdx.x;
   const bool in = i < ch.end;
   const int64_t o = ch.dof_off;
@@ -1063,6 +1065,7 @@ __global__ __launch_bounds__(VBLOCK) void k_dof1(PcgDev s, int it_k) {
 __global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
   __shared__ double lds[VWAVES + 4];
   const Chunk ch = s.chunks[blockIdx.x];
+  if (s.status[ch.sys] != SYS_RUNNING) return;  // a stopped system loads nothing
   const int i = ch.begin + threadIdx.x;
   const bool in = i < ch.end;
   const int64_t o = ch.dof_off;
