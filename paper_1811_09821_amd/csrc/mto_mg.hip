@@ -1036,9 +1036,14 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
     __syncthreads();
     const double piv = prow[par][kk];
     // When NE divides the block size a thread's entries share one column, so
-    // its scaled pivot-row entry is one division per step.
-    double rk0 = 0.0;
-    if constexpr (ASM_BLOCK % NE == 0) rk0 = (aj[0] == kk ? 1.0 : prow[par][aj[0]]) / piv;
+    // its scaled pivot-row entry is one division per step; otherwise each
+    // entry's is its pivot-row entry times the pivot's reciprocal (one FP64
+    // division per step instead of one per entry).
+    double rk0 = 0.0, rpiv = 0.0;
+    if constexpr (ASM_BLOCK % NE == 0)
+      rk0 = (aj[0] == kk ? 1.0 : prow[par][aj[0]]) / piv;
+    else
+      rpiv = 1.0 / piv;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (ai[r] < 0) continue;
@@ -1047,7 +1052,7 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
       if constexpr (ASM_BLOCK % NE == 0)
         rk = rk0;
       else
-        rk = (j == kk ? 1.0 : prow[par][j]) / piv;
+        rk = (j == kk ? 1.0 : prow[par][j]) * rpiv;
       av[r] = i == kk ? rk : (j == kk ? 0.0 : av[r]) - pcol[par][i] * rk;
     }
   }
