@@ -300,6 +300,7 @@ size_t chol_lds_bytes(int b) {
 }
 
 typedef double chol_d4 __attribute__((ext_vector_type(4)));
+typedef double d4m __attribute__((ext_vector_type(4)));
 
 // Q panel rows per lane of wave 0: 1 when the panel (chol_panel_rows) fits in
 // 64 rows, else 2.
@@ -863,7 +864,10 @@ __global__ __launch_bounds__(1024) void k_mg_post0(PcgDev s, int it_k, int init)
 // convergent, symmetric smoother and keeps the V-cycle SPD.
 
 namespace {
-constexpr int ASM_BLOCK = 256;
+// threads of k_asm_block: fewer for the small blocks of p <= 2, so more
+// elements are in flight per CU
+template <int P>
+constexpr int asm_block_threads() { return P == 1 ? 64 : P == 2 ? 128 : 256; }
 
 // Position of (a, b), a <= b, in the row-packed upper triangle of an NE x NE matrix.
 template <int NE>
@@ -873,16 +877,14 @@ __device__ __forceinline__ int packed_index(int a, int b) {
 }
 
 template <int P>
-__global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restrict__ groups, int gi,
+__global__ __launch_bounds__(asm_block_threads<P>()) void k_asm_block(const GroupDev* __restrict__ groups, int gi,
                                                          const int32_t* __restrict__ nbr,
                                                          const int32_t* __restrict__ el_group,
                                                          const int32_t* __restrict__ el_col,
                                                          const double* __restrict__ E, double* __restrict__ binv) {
-  constexpr int NE = ne_of(P);
+  constexpr int NE = ne_of(P), ASM_BLOCK = asm_block_threads<P>();
   constexpr int NEMAX = ne_of(MTO_MAX_P);
   __shared__ double A[NE][NE + 1];
-  __shared__ double prow[2][NE], pcol[2][NE];
-  __shared__ double sc[NE];
   __shared__ int gid[NE];
   __shared__ int posn[8][NEMAX];                       // each neighbour's DOFs in this element, or -1
   __shared__ double Esn[8][MTO_MAX_D * MTO_MAX_D];     // each neighbour's cell moduli
@@ -995,80 +997,152 @@ __global__ __launch_bounds__(ASM_BLOCK) void k_asm_block(const GroupDev* __restr
     __syncthreads();
   }
   // absent or supported DOFs, and DOFs with no stiffness at all (E_min = 0
-  // around them): identity rows, zero in the result; then symmetric scaling
+  // around them): marked by a diagonal of -1 and a zero row and column
   for (int a = tid; a < NE; a += ASM_BLOCK)
     if (!(A[a][a] > 0.0)) gid[a] = -1;
   __syncthreads();
-  for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
-    const int a = idx / NE, b = idx - a * NE;
-    if (gid[a] < 0 || gid[b] < 0) A[a][b] = a == b ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int a = tid; a < NE; a += ASM_BLOCK) sc[a] = 1.0 / sqrt(A[a][a]);
-  __syncthreads();
-  for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
-    const int a = idx / NE, b = idx - a * NE;
-    A[a][b] *= sc[a] * sc[b];
-  }
-  __syncthreads();
-  // Gauss-Jordan inverse, no pivoting (the block is SPD).  Each thread keeps
-  // its entries (idx = tid + r ASM_BLOCK) in registers for all NE steps; per
-  // step only the pivot row and column pass through LDS, double-buffered, so
-  // one barrier per step.  Each entry is updated by the same expression as
-  // with the whole matrix in LDS.
-  constexpr int R = (NE * NE + ASM_BLOCK - 1) / ASM_BLOCK;
-  double av[R];
-  int ai[R], aj[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int idx = tid + r * ASM_BLOCK;
-    ai[r] = idx < NE * NE ? idx / NE : -1;
-    aj[r] = idx < NE * NE ? idx - ai[r] * NE : 0;
-    av[r] = idx < NE * NE ? A[ai[r]][aj[r]] : 0.0;
-  }
-  for (int kk = 0; kk < NE; ++kk) {
-    const int par = kk & 1;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (ai[r] == kk) prow[par][aj[r]] = av[r];   // the pivot row
-      if (aj[r] == kk && ai[r] >= 0) pcol[par][ai[r]] = av[r];  // the pivot column
-    }
-    __syncthreads();
-    const double piv = prow[par][kk];
-    // When NE divides the block size a thread's entries share one column, so
-    // its scaled pivot-row entry is one division per step; otherwise each
-    // entry's is its pivot-row entry times the pivot's reciprocal (one FP64
-    // division per step instead of one per entry).
-    double rk0 = 0.0, rpiv = 0.0;
-    if constexpr (ASM_BLOCK % NE == 0)
-      rk0 = (aj[0] == kk ? 1.0 : prow[par][aj[0]]) / piv;
-    else
-      rpiv = 1.0 / piv;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (ai[r] < 0) continue;
-      const int i = ai[r], j = aj[r];
-      double rk;  // the scaled pivot row at column j
-      if constexpr (ASM_BLOCK % NE == 0)
-        rk = rk0;
-      else
-        rk = (j == kk ? 1.0 : prow[par][j]) * rpiv;
-      av[r] = i == kk ? rk : (j == kk ? 0.0 : av[r]) - pcol[par][i] * rk;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (ai[r] >= 0) A[ai[r]][aj[r]] = av[r];
-  __syncthreads();
-  // upper triangle, packed by rows (the inverse is symmetric)
+  // upper triangle, packed by rows (the assembled block is symmetric: both
+  // triangles are the same sums in the same order)
   for (int idx = tid; idx < NE * NE; idx += ASM_BLOCK) {
     const int a = idx / NE, b = idx - a * NE;
     if (b < a) continue;
-    double v = 0.5 * (A[a][b] + A[b][a]) * sc[a] * sc[b];
-    if (gid[a] < 0 || gid[b] < 0) v = 0.0;
+    const double v = (gid[a] < 0 || gid[b] < 0) ? (a == b ? -1.0 : 0.0) : A[a][b];
     binv[(int64_t)k * asm_ntp_of(P) + packed_index<NE>(a, b)] = v;
   }
+}
+
+// In-place inverse of the element blocks by blocked Gauss-Jordan elimination
+// on the matrix cores, one wave per element column: binv holds on entry the
+// packed upper triangle written by k_asm_block (a marked DOF: diagonal -1,
+// zero row) and on exit that of omega-free B_e, zero at marked DOFs.
+//   The block, symmetrically scaled to unit diagonal (marked and padding DOFs:
+//   identity rows), sits in MB x MB accumulator tiles of
+//   v_mfma_f64_16x16x4f64 (tile (bi, bj), register r: row 16 bi + l/16 + 4 r,
+//   column 16 bj + l%16 in lane l).  Step kb eliminates pivot rows
+//   4 kb .. 4 kb + 3 (no pivoting: the block is SPD).  Their row panel Rr
+//   is register r = kb % 4 of tile row kb / 4, in the B-operand layout as
+//   it stands; the pivot block P is gathered from it with lane shuffles and
+//   inverted in every lane.  Gauss-Jordan keeps the matrix symmetric between
+//   rows and columns of the same kind (both eliminated or both not) and
+//   antisymmetric between the kinds, so the column panel C in the A-operand
+//   layout is Rr of the same lane with the sign of the eliminated rows
+//   flipped.  Then, all on MFMA: R = P^-1 Rr, the rank-4 update A -= C R of
+//   every tile, the new pivot columns -C P^-1; the pivot rows become R and
+//   the pivot block P^-1.
+template <int P>
+__global__ __launch_bounds__(64, 2) void k_asm_invert(double* __restrict__ binv) {
+  constexpr int NE = ne_of(P), NTP = asm_ntp_of(P), MB = mb_of(P), NB = (NE + 3) / 4;
+  __shared__ double dg[16 * MB];
+  const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
+  double* __restrict__ bp = binv + (int64_t)blockIdx.x * NTP;
+  auto pk = [](int a, int b) { return a <= b ? packed_index<NE>(a, b) : packed_index<NE>(b, a); };
+  d4m acc[MB][MB];
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < MB; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * bi + lr + 4 * r, b = 16 * bj + lc;
+        acc[bi][bj][r] = (a < NE && b < NE) ? bp[pk(a, b)] : (a == b ? 1.0 : 0.0);
+      }
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (lc == lr + 4 * r) dg[16 * bi + lc] = acc[bi][bi][r];
+  __syncthreads();
+  // symmetric scaling to unit diagonal (factor 0 at marked DOFs, whose
+  // rows become identity rows); the factors are kept in LDS for the end
+  __syncthreads();
+  if (lane < 16 * MB) dg[lane] = dg[lane] > 0.0 ? 1.0 / sqrt(dg[lane]) : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < MB; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * bi + lr + 4 * r, b = 16 * bj + lc;
+        const double sa = dg[a];
+        const double v = acc[bi][bj][r] * sa * dg[b];
+        acc[bi][bj][r] = (a == b && !(sa > 0.0)) ? 1.0 : v;
+      }
+  const d4m zero = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kb = 0; kb < NB; ++kb) {
+    const int bk = kb / 4, rk = kb % 4, pc0 = 4 * (kb % 4);
+    double Rr[MB];
+#pragma unroll
+    for (int bj = 0; bj < MB; ++bj) Rr[bj] = acc[bk][bj][rk];
+    // the pivot block, then its inverse (Gauss-Jordan on 4 x 4, every lane)
+    double M[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) M[q][c] = __shfl(Rr[bk], 16 * q + pc0 + c);
+#pragma unroll
+    for (int t0 = 0; t0 < 4; ++t0) {
+      const double ip = 1.0 / M[t0][t0];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j != t0) M[t0][j] *= ip;
+      M[t0][t0] = ip;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i == t0) continue;
+        const double f = M[i][t0];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j != t0) M[i][j] -= f * M[t0][j];
+        M[i][t0] = -f * ip;
+      }
+    }
+    // P^-1 as an A operand (rows 0..3) and as a B operand at the pivot columns
+    double piA = 0.0, piB = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (lc == q && lr == c) piA = M[q][c];
+        if (lr == q && lc == pc0 + c) piB = M[q][c];
+      }
+    const bool pcol = lc >= pc0 && lc < pc0 + 4;
+    double RB[MB], CA[MB];
+#pragma unroll
+    for (int bj = 0; bj < MB; ++bj) {
+      const d4m t = __builtin_amdgcn_mfma_f64_16x16x4f64(piA, Rr[bj], zero, 0, 0, 0);
+      RB[bj] = t[0];  // R = P^-1 Rr: lane l holds R[l/16][16 bj + l%16]
+      CA[bj] = (16 * bj + lc < 4 * kb) ? Rr[bj] : -Rr[bj];  // -C, eliminated rows sign-flipped
+    }
+    // the new pivot columns -C P^-1 first; the update below then leaves them
+    // alone (R is taken as zero there)
+#pragma unroll
+    for (int bi = 0; bi < MB; ++bi) {
+      const d4m x = __builtin_amdgcn_mfma_f64_16x16x4f64(CA[bi], piB, zero, 0, 0, 0);
+      if (pcol) acc[bi][bk] = x;
+    }
+    const double rbk = RB[bk];
+    if (pcol) RB[bk] = 0.0;
+#pragma unroll
+    for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < MB; ++bj) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(CA[bi], RB[bj], acc[bi][bj], 0, 0, 0);
+    // the pivot rows become R, the pivot block P^-1
+    RB[bk] = pcol ? piB : rbk;
+#pragma unroll
+    for (int bj = 0; bj < MB; ++bj) acc[bk][bj][rk] = RB[bj];
+  }
+  // unscale; upper triangle, packed by rows
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+    for (int bj = bi; bj < MB; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * bi + lr + 4 * r, b = 16 * bj + lc;
+        if (a <= b && b < NE) bp[packed_index<NE>(a, b)] = acc[bi][bj][r] * dg[a] * dg[b];
+      }
 }
 
 // slots2 = omega * B_e v_e.  One block of 256 threads per tile of
@@ -1270,12 +1344,18 @@ void launch_mg_post0(const PcgDev& s, int it_k, int init, hipStream_t st) {
 void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const int32_t* nbr, const int32_t* el_group,
                       const int32_t* el_col, const double* E, double* binv, hipStream_t st) {
   if (g.n_elems == 0) return;
-  const dim3 grid(g.n_elems), block(ASM_BLOCK);
+  const dim3 grid(g.n_elems);
   switch (g.p) {
-    case 1: hipLaunchKernelGGL(k_asm_block<1>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
-    case 2: hipLaunchKernelGGL(k_asm_block<2>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
-    case 3: hipLaunchKernelGGL(k_asm_block<3>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
-    default: hipLaunchKernelGGL(k_asm_block<4>, grid, block, 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+    case 1: hipLaunchKernelGGL(k_asm_block<1>, grid, dim3(asm_block_threads<1>()), 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+    case 2: hipLaunchKernelGGL(k_asm_block<2>, grid, dim3(asm_block_threads<2>()), 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+    case 3: hipLaunchKernelGGL(k_asm_block<3>, grid, dim3(asm_block_threads<3>()), 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+    default: hipLaunchKernelGGL(k_asm_block<4>, grid, dim3(asm_block_threads<4>()), 0, st, groups, gi, nbr, el_group, el_col, E, binv); break;
+  }
+  switch (g.p) {
+    case 1: hipLaunchKernelGGL(k_asm_invert<1>, grid, dim3(64), 0, st, binv); break;
+    case 2: hipLaunchKernelGGL(k_asm_invert<2>, grid, dim3(64), 0, st, binv); break;
+    case 3: hipLaunchKernelGGL(k_asm_invert<3>, grid, dim3(64), 0, st, binv); break;
+    default: hipLaunchKernelGGL(k_asm_invert<4>, grid, dim3(64), 0, st, binv); break;
   }
 }
 void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, int resid,
