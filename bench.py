@@ -233,7 +233,7 @@ def tile_shapes(report):
     out = []
     for ln in report.strip().splitlines():
         if ln.endswith(": chosen"):
-            kv = dict(t.split("=") for t in ln.split(":")[0].split())
+            kv = dict(t.split("=") for t in ln.split(":")[0].split() if "=" in t)
             out.append(f"{kv['p']} {kv['d']} {kv['ncol']} {kv['ks']}")
     return sorted(out)
 
@@ -290,6 +290,37 @@ def contraction_roofline(plan, rho, stats, config, path_name, shapes):
             "tile_shapes": shapes}
 
 
+def time_stored(mto, args, prs, rho, precond, shapes):
+    """The same step with stored element matrices (K_e assembled in the set-up,
+    each product reading it: HBM-bound) for the p = 4 groups and the timed
+    contraction shapes elsewhere, outside the headline: the alternative to the
+    MFMA contraction that the autotuner takes with stored_matrices = 1."""
+    import numpy as np
+    import torch
+
+    plan = mto.Plan(prs, precond=precond, stored_matrices=1)
+    plan.autotune(rho, cache=args.tile_cache or None)
+    for s in shapes:
+        p, d = (int(v) for v in s.split()[:2])
+        if p == 4:
+            plan.set_tile(1, -2, p=p, d=d)
+    plan.capture(rho)
+    plan.replay()
+    torch.cuda.synchronize()
+    reps = max(2, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st = plan.replay()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    its = st["iterations"]
+    ms = plan.time_contraction(rho, reps=50)
+    del plan
+    return {"s_per_design": el / len(prs), "ms_per_step": 1e3 * el, "product_ms": round(ms, 5),
+            "pcg_iterations": {"mean": round(float(np.mean(its)), 2), "max": max(its)},
+            "kernel": "k_elem_stored (p = 4 groups) + the contraction of the other groups"}
+
+
 def contraction_only(args, prs, desc):
     """Plan, cached tile shapes, then 100 back-to-back launches of the element
     contraction (after the solve set-up), optionally followed by one device
@@ -336,6 +367,8 @@ def main():
                     help="tile-shape cache file of the autotuner ('' times every shape)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-element GPU path")
+    ap.add_argument("--no-stored", action="store_true",
+                    help="skip the step with stored element matrices for the p = 4 groups")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workload (config 2)")
     ap.add_argument("--filter-radius", type=float, default=0.3,
                     help="density-filter radius in element edge lengths for the filter timing (0 skips it)")
@@ -413,6 +446,10 @@ def main():
     }
     if res["report"]:
         out["autotune"] = res["report"].strip().splitlines()
+
+    if not args.no_stored and path == mto.PATH_MFMA and any(int(s.split()[0]) == 4 for s in shapes):
+        progress("stored element matrices for the p = 4 groups")
+        out["stored_element_matrices"] = time_stored(mto, args, prs, rho, precond, shapes)
 
     if not args.no_plain and path == mto.PATH_MFMA:
         progress("plain per-element path")

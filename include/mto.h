@@ -135,6 +135,9 @@ typedef struct {
                                the nine-colouring of element blocks guarantees */
   int32_t mg_coarse_max;    /* multigrid: coarsen until the largest instance's grid has at most this
                                many DOFs, solved exactly (<= 0: 3000, the most allowed) */
+  int32_t stored_matrices;  /* 1: mto_autotune may give a group of order p >= 3 stored element
+                               matrices (mto_set_tile ks = -2) when they are faster than its
+                               contraction; 0: it chooses among contraction shapes only */
 } mto_params;
 
 /* A linear spring from one vertex DOF to ground, stiffness k > 0: adds k to
@@ -317,7 +320,9 @@ int mto_jacobi_diagonal(mto_plan* plan, const double* rho, double* diag, void* s
  * shape without timing, and the shapes timed in this call are added to the
  * file (a missing file is created; MTO_EINVAL if it cannot be parsed).
  * report (host, may be NULL) receives a text summary of at most report_len
- * bytes.  Blocks until the timing is done. */
+ * bytes.  With mto_params.stored_matrices = 1 the stored element matrices
+ * (mto_set_tile ks = -2) are a candidate for the groups of p >= 3.  Blocks
+ * until the timing is done. */
 int mto_autotune(mto_plan* plan, const double* rho, const char* cache_path, void* stream, char* report,
                  int32_t report_len);
 
@@ -330,8 +335,16 @@ int mto_autotune(mto_plan* plan, const double* rho, const char* cache_path, void
  * their shape).  ks = -1 (p, d, ncol ignored): the product of every group in
  * one launch (the LDS-staged contraction of 64-column tiles from all groups,
  * the long ones first); any other call returns to one launch per group.
- * mto_autotune picks between the two by timing.  MTO_EINVAL if the shape
- * needs more LDS than the kernel takes (64 KB; 160 KB for ks = 0).
+ * mto_autotune picks between the two by timing.  ks = -2 (ncol ignored):
+ * stored element matrices for the group(s): K_e = sum_s E_s K_s (the
+ * operator of Eq. (2) with the composite integration of Appendix B, per
+ * element) is assembled once per solve set-up and mto_apply_stiffness call,
+ * its packed upper triangle kept on the device (n_e (n_e + 1) / 2 doubles per
+ * element, allocated on first use), and each product reads it instead of
+ * contracting the cell tables; every load case of an instance shares one
+ * read.  The product is HBM-bound instead of MFMA-bound; it is not part of
+ * the one-launch product.  MTO_EINVAL if the shape needs more LDS than the
+ * kernel takes (64 KB; 160 KB for ks = 0) or no group matches (ks = -2).
  * Invalidates captured graphs. */
 int mto_set_tile(mto_plan* plan, int32_t p, int32_t d, int32_t ncol, int32_t ks);
 

@@ -21,6 +21,8 @@
 // see bit-identical alpha, beta and convergence decisions.
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <hip/hip_ext.h>
 
 #include "mto_kernels.hpp"
@@ -768,6 +770,169 @@ __global__ __launch_bounds__(64) void k_elem_vertex(GroupDev g, const Tile* __re
 }
 
 // ---------------------------------------------------------------------------
+// Stored element matrices.  For a group whose contraction costs more than
+// reading its element matrix (p = 4, d = 5: 2 S n_e^2 = 125 kflop per column
+// against 10.2 KB per element, shared by the element's load cases; FP64 MFMA
+// on gfx950 sustains about 10 flop per byte of HBM), K_e = sum_s E_s K_s is
+// assembled once per design (its packed upper triangle, element-major,
+// asm_ntp_of(p) doubles per column) and each product reads it: the same
+// operator, rounded once per entry instead of once per product.
+
+__device__ __forceinline__ int packed_row_start(int ne, int a) { return a * ne - (a * (a - 1)) / 2; }
+
+// K_e for EA consecutive element columns per block: each thread takes
+// entries (a, b <= ...) of the packed triangle, reads K_s[a][b] once for all
+// EA elements and accumulates E_s K_s[a][b] in the order of s.
+constexpr int ASSEMBLE_EA = 16;
+template <int P>
+__global__ __launch_bounds__(256) void k_elem_assemble(GroupDev g, const double* __restrict__ E,
+                                                       double* __restrict__ kst) {
+  constexpr int NE = ne_of(P), NTP = asm_ntp_of(P), EA = ASSEMBLE_EA;
+  __shared__ double es[EA][MTO_MAX_D * MTO_MAX_D];
+  const int e0 = blockIdx.x * EA, cnt = min(EA, g.n_elems - e0);
+  for (int i = threadIdx.x; i < EA * g.S; i += 256) {
+    const int e = i / g.S, sc = i - e * g.S;
+    es[e][sc] = e < cnt ? E[g.cell[e0 + e] + sc] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NE * NE; idx += 256) {
+    const int a = idx / NE, b = idx - a * NE;
+    if (b < a) continue;
+    const double* __restrict__ kab = g.ks + (int64_t)a * NE + b;
+    double v[EA];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) v[e] = 0.0;
+    for (int sc = 0; sc < g.S; ++sc) {
+      const double k = kab[(int64_t)sc * NE * NE];
+#pragma unroll
+      for (int e = 0; e < EA; ++e) v[e] = fma(es[e][sc], k, v[e]);
+    }
+    const int pi = packed_row_start(NE, a) + (b - a);
+#pragma unroll
+    for (int e = 0; e < EA; ++e)
+      if (e < cnt) kst[(int64_t)(e0 + e) * NTP + pi] = v[e];
+  }
+}
+
+// The product with stored element matrices: slots = K_e (x_e - rigid motion)
+// for every system of an instance from one read of K_e.  One block of 256
+// threads per tile of EB = asm_cols_of(P) element columns of an instance's
+// first system (the tiles of the Schwarz application), thread (column c,
+// row a) for the first NE EB threads.  The tile's triangles are one
+// contiguous range, loaded with 16-byte loads and staged in LDS while the
+// element vectors are gathered (PCG mode: p = z + beta p_old formed as
+// k_dof1 stores it, beta and the running test of each system reduced by one
+// wave each); row a then sums K_e(a, b) w_b in order of b, w the element
+// vector with its rigid motion removed as in the contraction kernels.
+constexpr int STORED_SYS = 4;  // systems per pass over a tile (one wave reduces each one's scalars)
+template <int P>
+__global__ __launch_bounds__(256) void k_elem_stored(GroupDev g, const Tile* __restrict__ tiles,
+                                                     const double* __restrict__ xin, PcgDev s, int mode, int it_k) {
+  constexpr int NE = ne_of(P), NTP = asm_ntp_of(P), EB = asm_cols_of(P);
+  static_assert(NE * EB <= 256, "one thread per row and column");
+  constexpr int NB2 = EB * NTP / 2, LPT = (NB2 + 255) / 256;
+  __shared__ double2 ks2[NB2];
+  __shared__ double vs[STORED_SYS][EB][NE];
+  __shared__ double sbeta[STORED_SYS];
+  __shared__ int sact[STORED_SYS];
+  const double* ksh = (const double*)ks2;
+  const Tile t = tiles[g.ms_tile_begin + blockIdx.x];
+  const int nsys = t.pc_begin;  // the instance's systems follow its first one
+  const bool pcg = mode == ELEM_PCG;
+  if (mode != ELEM_APPLY) {  // nothing to do once every system has stopped (no matrix read)
+    bool any = false;
+    for (int l = 0; l < nsys; ++l) any |= s.status[t.sys + l] == SYS_RUNNING;
+    if (!any) return;  // uniform over the block
+  }
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const double2* __restrict__ src = (const double2*)(g.kst + (int64_t)t.elem_begin * NTP);
+  const int nw = t.count * (NTP / 2);
+  double2 stg[LPT];
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = tid + 256 * k;
+    stg[k] = i < nw ? src[i] : double2{0.0, 0.0};
+  }
+  const int c = tid / NE, a = tid - c * NE;
+  const bool act = c < EB && c < t.count;
+  const int64_t col = t.elem_begin + (act ? c : 0);
+  const int id = act ? g.gidx[a * (int64_t)g.npad + col] : -1;
+  const int si = act ? g.sidx[a * (int64_t)g.npad + col] : -1;
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = tid + 256 * k;
+    if (i < NB2) ks2[i] = stg[k];
+  }
+  const int ra = packed_row_start(NE, a) - a;
+  const double* __restrict__ krow = ksh + (act ? c : 0) * NTP;
+  for (int l0 = 0; l0 < nsys; l0 += STORED_SYS) {
+    const int np = min(STORED_SYS, nsys - l0);
+    if (wave < np) {  // this pass's systems: beta and whether each runs
+      const int sys = t.sys + l0 + wave;
+      bool run;
+      double beta = 0.0;
+      if (pcg) {
+        const SysDesc& sd = s.sys[sys];
+        const Scal sc = pcg_state(s, sys, sd.chunk_begin, sd.chunk_end, *s.it_base + it_k, true);
+        run = sc.active;
+        beta = sc.beta;
+      } else {
+        run = mode == ELEM_APPLY || s.status[sys] == SYS_RUNNING;
+      }
+      if (lane == 0) {
+        sbeta[wave] = beta;
+        sact[wave] = run ? 1 : 0;
+      }
+    }
+    __syncthreads();  // the scalars (and, on the first pass, the matrices)
+    if (act) {
+#pragma unroll
+      for (int l = 0; l < STORED_SYS; ++l) {
+        if (l >= np) break;
+        double x = 0.0;
+        if (sact[l] && id >= 0) {
+          const SysDesc& sd = s.sys[t.sys + l0 + l];
+          const double xv = xin[sd.dof_off + id];
+          x = pcg ? fma(sbeta[l], xv, s.z[sd.dof_off + id]) : xv;
+        }
+        vs[l][c][a] = x;
+      }
+    }
+    __syncthreads();  // the element vectors
+    if (act) {
+      double acc[STORED_SYS] = {0.0, 0.0, 0.0, 0.0};
+      double x0[STORED_SYS], x1[STORED_SYS], th[STORED_SYS];
+#pragma unroll
+      for (int l = 0; l < STORED_SYS; ++l) {
+        x0[l] = vs[l][c][0];
+        x1[l] = vs[l][c][1];
+        th[l] = vs[l][c][3] - x1[l];
+      }
+      auto row = [&](auto nl) {
+        constexpr int NL = decltype(nl)::value;
+#pragma unroll 10
+        for (int b = 0; b < NE; ++b) {
+          const int cb = packed_row_start(NE, b) - b;
+          const double e = krow[b < a ? cb + a : ra + b];
+#pragma unroll
+          for (int l = 0; l < NL; ++l) acc[l] = fma(e, rigid_free<P>(vs[l][c][b], b, x0[l], x1[l], th[l]), acc[l]);
+        }
+      };
+      switch (np) {  // uniform over the block
+        case 1: row(std::integral_constant<int, 1>{}); break;
+        case 2: row(std::integral_constant<int, 2>{}); break;
+        case 3: row(std::integral_constant<int, 3>{}); break;
+        default: row(std::integral_constant<int, 4>{}); break;
+      }
+#pragma unroll
+      for (int l = 0; l < STORED_SYS; ++l)
+        if (l < np && sact[l] && si >= 0) s.slots[s.sys[t.sys + l0 + l].slot_off + si] = acc[l];
+    }
+    if (l0 + STORED_SYS < nsys) __syncthreads();  // vs and the scalars are rewritten by the next pass
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Comparison path: one thread per element column, FP64 VALU, K_s read from
 // memory.  Block = 64 threads = one tile (at most 64 columns).
 template <int P>
@@ -1346,6 +1511,29 @@ void launch_elem_fused(const GroupDev* groups, const Tile* tiles, int tile_begin
   if (n_tiles == 0) return;
   launch_timed(k_elem_fused, dim3(n_tiles), dim3(256), (uint32_t)lds_bytes, st, ev0, ev1, groups, tiles, tile_begin,
                n_tiles, xcd_run, E, xin, s, mode, it_k);
+}
+
+void launch_elem_stored(const GroupDev& g, const Tile* tiles, const double* xin, const PcgDev& s, int mode, int it_k,
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (g.ms_n_tiles == 0) return;
+  const dim3 grid(g.ms_n_tiles), block(256);
+  switch (g.p) {
+    case 1: launch_timed(k_elem_stored<1>, grid, block, 0u, st, ev0, ev1, g, tiles, xin, s, mode, it_k); break;
+    case 2: launch_timed(k_elem_stored<2>, grid, block, 0u, st, ev0, ev1, g, tiles, xin, s, mode, it_k); break;
+    case 3: launch_timed(k_elem_stored<3>, grid, block, 0u, st, ev0, ev1, g, tiles, xin, s, mode, it_k); break;
+    default: launch_timed(k_elem_stored<4>, grid, block, 0u, st, ev0, ev1, g, tiles, xin, s, mode, it_k); break;
+  }
+}
+
+void launch_elem_assemble(const GroupDev& g, const double* E, double* kst, hipStream_t st) {
+  if (g.n_elems == 0) return;
+  const dim3 grid((g.n_elems + ASSEMBLE_EA - 1) / ASSEMBLE_EA), block(256);
+  switch (g.p) {
+    case 1: hipLaunchKernelGGL(k_elem_assemble<1>, grid, block, 0, st, g, E, kst); break;
+    case 2: hipLaunchKernelGGL(k_elem_assemble<2>, grid, block, 0, st, g, E, kst); break;
+    case 3: hipLaunchKernelGGL(k_elem_assemble<3>, grid, block, 0, st, g, E, kst); break;
+    default: hipLaunchKernelGGL(k_elem_assemble<4>, grid, block, 0, st, g, E, kst); break;
+  }
 }
 
 void launch_elem_vertex(const GroupDev& g, const Tile* tiles, const double* E, const double* dz, const PcgDev& s,

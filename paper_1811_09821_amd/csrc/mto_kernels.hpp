@@ -22,6 +22,8 @@ struct GroupDev {
   int32_t ms_n_tiles;      //   which the Schwarz application serves all systems of the instance
   const double* kfrag;     // MFMA A fragments [S*NEP/4][MB][64]
   const double* kfrags;    // the LDS-staged contraction's tables [S][NEP/4][frj_of(p)] (staged_fragments)
+  const double* kst;       // stored element matrices K_e (stored != 0): [npad][asm_ntp_of(p)] packed upper triangles
+  int32_t stored;          // products of this group read kst (k_elem_stored) instead of contracting K_s
   const double* kfragv;    // the vertex columns of K_s as A fragments [S][2][MB][64] (vertex_fragments)
   const double* ks;        // plain K_s [S][ne][ne]
   const double* kdiag;     // diag(K_s) [S][ne]
@@ -167,6 +169,13 @@ void launch_elem(const GroupDev& g, int path, const Tile* tiles, const double* E
 void launch_elem_fused(const GroupDev* groups, const Tile* tiles, int tile_begin, int n_tiles, int xcd_run,
                        size_t lds_bytes, const double* E, const double* xin, const PcgDev& s, int mode, int it_k,
                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// K_e = sum_s E_s K_s of every column of the group, packed upper triangles
+// [npad][asm_ntp_of(p)] (stored element matrices)
+void launch_elem_assemble(const GroupDev& g, const double* E, double* kst, hipStream_t st);
+// y-slots of the stored element matrices g.kst applied as launch_elem does
+// (every system of each instance from one read of its matrices)
+void launch_elem_stored(const GroupDev& g, const Tile* tiles, const double* xin, const PcgDev& s, int mode, int it_k,
+                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // slots += K[:, vertex DOFs] dz for the running systems (dz in the free-DOF
 // layout, read at vertex DOFs only; the slots hold K z before the call)
 void launch_elem_vertex(const GroupDev& g, const Tile* tiles, const double* E, const double* dz, const PcgDev& s,

@@ -67,6 +67,9 @@ struct GroupHost {
   std::vector<int32_t> inst_begin;
   double* kfrag = nullptr;
   double* kfrags = nullptr;  // null without a vector-ALU tail (kfrag serves the LDS-staged kernel then)
+  // stored element matrices (mto_set_tile ks = -2): K_e assembled per design, products read them
+  int stored = 0;
+  double* kst = nullptr;
   double* kfragv = nullptr;
   double* ks = nullptr;
   double* kdiag = nullptr;
@@ -237,6 +240,8 @@ struct mto_plan {
     o.ms_n_tiles = g.ms_n_tiles;
     o.kfrag = g.kfrag;
     o.kfrags = g.kfrags ? g.kfrags : g.kfrag;
+    o.kst = g.kst;
+    o.stored = g.stored;
     o.kfragv = g.kfragv;
     o.ks = g.ks;
     o.kdiag = g.kdiag;
@@ -423,15 +428,25 @@ int size_class(double columns) {
 bool read_tile_cache(const char* path, std::map<TileKey, TileChoice>& out) {
   FILE* fh = fopen(path, "r");
   if (!fh) return true;
-  char line[256];
+  char line[1024];
   bool ok = true;
   while (fgets(line, sizeof line, fh)) {
+    if (!std::strchr(line, '\n') && !feof(fh)) {  // longer than the buffer: a comment may be, an entry not
+      const bool comment = line[0] == '#';
+      int ch;
+      while ((ch = fgetc(fh)) != EOF && ch != '\n') {
+      }
+      if (comment) continue;
+      ok = false;
+      break;
+    }
     if (line[0] == '#' || line[0] == '\n') continue;
     char arch[64];
     TileKey k;
     TileChoice v;
     if (sscanf(line, "%63s %d %d %d %d %d %lf", arch, &k.p, &k.d, &k.size_class, &v.ncol, &v.ks, &v.us) != 7 ||
-        (v.ncol != 1 && v.ncol != 2 && v.ncol != 4) || v.ks < 0 || v.ks > 8 || k.p < 0 || k.p > MTO_MAX_P ||
+        (v.ncol != 1 && v.ncol != 2 && v.ncol != 4) || v.ks < -2 || v.ks == -1 || v.ks > 8 || k.p < 0 ||
+        k.p > MTO_MAX_P || (v.ks == -2 && (k.p == 0 || v.ncol != 1)) ||
         k.d < 0 || k.d > MTO_MAX_D * MTO_MAX_P || (k.p > 0 && k.d < 1) || (k.p > 0 && k.d > MTO_MAX_D) ||
         (k.p > 0 && v.ks == 0 && (k.p < 3 || v.ncol == 4)) || (k.p == 0 && (v.ks != 0 || v.ncol == 4))) {
       ok = false;
@@ -448,9 +463,9 @@ bool write_tile_cache(const char* path, const std::map<TileKey, TileChoice>& c) 
   const std::string tmp = std::string(path) + ".tmp";
   FILE* fh = fopen(tmp.c_str(), "w");
   if (!fh) return false;
-  fprintf(fh, "# element-contraction tile shapes: arch p d size_class(log2 columns) ncol ks us_per_launch"
-              " (ks 0: LDS-staged tables, 64 ncol columns per tile; p 0: the plan's choice between one launch"
-              " for all its d groups (ncol 1) and one per group (ncol 2))\n");
+  fprintf(fh, "# element-contraction tile shapes: arch p d size_class(log2 columns) ncol ks us_per_launch\n"
+              "# ks 0: LDS-staged tables, 64 ncol columns per tile; ks -2: stored element matrices\n"
+              "# p 0: the plan's choice between one launch for all its d groups (ncol 1) and one per group (ncol 2)\n");
   for (auto& kv : c)
     fprintf(fh, "%s %d %d %d %d %d %.3f\n", kv.first.arch.c_str(), kv.first.p, kv.first.d, kv.first.size_class,
             kv.second.ncol, kv.second.ks, kv.second.us);
@@ -689,6 +704,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     return fail(MTO_EINVAL, "unknown kernel_path");
   if (prm->precond != MTO_PRECOND_JACOBI && prm->precond != MTO_PRECOND_MG && prm->precond != MTO_PRECOND_MG_ASM)
     return fail(MTO_EINVAL, "unknown precond");
+  if (prm->stored_matrices != 0 && prm->stored_matrices != 1) return fail(MTO_EINVAL, "stored_matrices must be 0 or 1");
   if (prm->precond == MTO_PRECOND_MG_ASM && !(prm->mg_omega < 2.0 / 9.0))
     return fail(MTO_EINVAL, "Schwarz smoother weight must be below 2/9 (<= 0 selects the default)");
   std::vector<InstanceHost> I(n);
@@ -949,6 +965,33 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
 
 // ---- enqueue helpers (all launches on st; usable under stream capture) ----
 
+// One group's product: its stored element matrices when it has them (they
+// hold this design's moduli once the set-up or mto_autotune assembled them),
+// else the contraction.
+void enq_elem_group(mto_plan* P, const GroupHost& g, const double* xin, int mode, int it_k, hipStream_t st,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+  if (g.stored && P->prm.kernel_path == MTO_PATH_MFMA)
+    launch_elem_stored(P->gdev(g), P->d_tiles, xin, P->pcg(), mode, it_k, st, ev0, ev1);
+  else
+    launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, xin, P->pcg(), mode, it_k, st, ev0, ev1);
+}
+
+// Switches a group to stored element matrices (allocated on first use).
+int ensure_stored(mto_plan* P, GroupHost& g) {
+  if (!g.kst) {
+    int rc = dev_alloc(P, &g.kst, (size_t)asm_ntp_of(g.p) * g.npad);
+    if (rc) return rc;
+  }
+  g.stored = 1;
+  return MTO_OK;
+}
+
+void enq_assemble_stored(mto_plan* P, hipStream_t st) {
+  if (P->prm.kernel_path != MTO_PATH_MFMA) return;
+  for (auto& g : P->groups)
+    if (g.stored) launch_elem_assemble(P->gdev(g), P->E, g.kst, st);
+}
+
 void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_t st) {
   const PcgDev s = P->pcg();
   if (P->fused && P->prm.kernel_path == MTO_PATH_MFMA) {
@@ -956,7 +999,7 @@ void enq_elem_all(mto_plan* P, const double* xin, int mode, int it_k, hipStream_
                       P->fused_lds, P->E, xin, s, mode, it_k, st);
     return;
   }
-  for (auto& g : P->groups) launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, xin, s, mode, it_k, st);
+  for (auto& g : P->groups) enq_elem_group(P, g, xin, mode, it_k, st);
 }
 
 void enq_residual(mto_plan* P, hipStream_t st);
@@ -1042,6 +1085,7 @@ void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st)
   // the densities are checked here; k_sys_setup then stops every system if one is invalid
   launch_fill_i32(P->bad_rho, 0, 1, st);
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st, P->bad_rho);
+  enq_assemble_stored(P, st);
   const bool mg = P->prm.precond != MTO_PRECOND_JACOBI;
   // l1-Jacobi level-0 smoother of MTO_PRECOND_MG unless a damping factor is set
   const bool l1 = P->prm.precond == MTO_PRECOND_MG && !(P->prm.mg_omega > 0.0);
@@ -1449,6 +1493,7 @@ int mto_apply_stiffness(mto_plan* P, const double* rho, const double* x, double*
   hipStream_t st = (hipStream_t)stream;
   const PcgDev s = P->pcg();
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st);
+  enq_assemble_stored(P, st);
   launch_gather_free(s, P->f2f, x, P->q, st);
   enq_elem_all(P, P->q, ELEM_APPLY, 0, st);
   launch_fill(y, 0.0, P->n_u, st);
@@ -1707,8 +1752,20 @@ int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol, int32_t ks) {
     P->fused = true;
     return rebuild_tiles(P);
   }
+  if (P && ks == -2) {  // stored element matrices for the group(s)
+    P->fused = false;
+    bool any = false;
+    for (auto& g : P->groups)
+      if (p <= 0 || (g.p == p && g.d == d)) {
+        int rc = ensure_stored(P, g);
+        if (rc) return rc;
+        any = true;
+      }
+    if (!any) return fail(MTO_EINVAL, "no group with this (p, d)");
+    return rebuild_tiles(P);
+  }
   if (!P || (ncol != 1 && ncol != 2 && ncol != 4) || ks < 0 || ks > 8)
-    return fail(MTO_EINVAL, "ncol must be 1, 2 or 4 and ks -1..8");
+    return fail(MTO_EINVAL, "ncol must be 1, 2 or 4 and ks -2..8");
   P->fused = false;
   if (ks == 0 && ncol == 4) return fail(MTO_EINVAL, "the LDS-staged contraction takes ncol 1 or 2");
   for (auto& g : P->groups)
@@ -1721,6 +1778,7 @@ int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol, int32_t ks) {
         if (elem_lds_staged_bytes(g.p, ncol) > ELEM_LDS_STAGED_LIMIT)
           return fail(MTO_EINVAL, "tile shape exceeds the LDS limit");
         g.lds_nc = ncol;
+        g.stored = 0;
         continue;
       }
       const int k = std::min<int>(ks, g.S);
@@ -1728,6 +1786,7 @@ int mto_set_tile(mto_plan* P, int32_t p, int32_t d, int32_t ncol, int32_t ks) {
       g.ncol = ncol;
       g.waves = k;
       g.lds_nc = 0;
+      g.stored = 0;
     }
   return rebuild_tiles(P);
 }
@@ -1762,6 +1821,18 @@ int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* s
   for (auto& g : P->groups) {
     const TileKey key{arch, g.p, g.d, size_class(g.flops / (2.0 * g.S * g.ne * g.ne))};
     auto hit = cache.find(key);
+    if (hit != cache.end() && hit->second.ks == -2 && P->prm.stored_matrices) {
+      int rc = ensure_stored(P, g);
+      if (rc) return rc;
+      char line[200];
+      snprintf(line, sizeof line,
+               "p=%d d=%d ncol=1 ks=-2: cached (stored element matrices; %s, %d columns class, %.3f us when tuned)\n",
+               g.p, g.d, arch.c_str(), key.size_class, hit->second.us);
+      rep += line;
+      continue;
+    }
+    g.stored = 0;
+    if (hit != cache.end() && hit->second.ks == -2) hit = cache.end();  // stored matrices not allowed: time shapes
     if (hit != cache.end() && hit->second.ks == 0 && g.p >= 3 &&
         elem_lds_staged_bytes(g.p, hit->second.ncol) <= ELEM_LDS_STAGED_LIMIT) {
       g.lds_nc = hit->second.ncol;
@@ -1815,13 +1886,41 @@ int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* s
           best_ks = ks;
         }
       }
+    if (g.p >= 3 && P->prm.stored_matrices) {  // stored element matrices: assembled for these moduli, then timed
+      int rc = ensure_stored(P, g);
+      if (rc) return rc;
+      rc = rebuild_tiles(P);
+      if (rc) return rc;
+      launch_elem_assemble(P->gdev(g), P->E, g.kst, st);
+      for (int w = 0; w < 3; ++w) enq_elem_group(P, g, P->q, ELEM_APPLY, 0, st);
+      const int reps = 20;
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int w = 0; w < reps; ++w) enq_elem_group(P, g, P->q, ELEM_APPLY, 0, st);
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      const double tt = ms / reps;
+      char line[160];
+      snprintf(line, sizeof line, "p=%d d=%d ncol=1 ks=-2: %.3f us (stored element matrices)\n", g.p, g.d, 1e3 * tt);
+      rep += line;
+      g.stored = 0;
+      if (tt < best) {
+        best = tt;
+        best_nc = 1;
+        best_ks = -2;
+      }
+    }
+    g.stored = best_ks == -2 ? 1 : 0;
     g.lds_nc = best_ks == 0 ? best_nc : 0;
-    g.ncol = best_ks == 0 ? 1 : best_nc;
-    g.waves = best_ks == 0 ? 1 : best_ks;
+    g.ncol = best_ks <= 0 ? 1 : best_nc;
+    g.waves = best_ks <= 0 ? 1 : best_ks;
     cache[key] = TileChoice{best_nc, best_ks, 1e3 * best};
     changed = true;
   }
-  // one launch for all groups (the fused product) or one per group
+  // one launch for all groups (the fused product) or one per group (the
+  // stored element matrices, when chosen, for these moduli)
+  enq_assemble_stored(P, st);
   {
     int64_t cols = 0;
     for (auto& g : P->groups) cols += (int64_t)(g.flops / (2.0 * g.S * g.ne * g.ne));
@@ -1863,8 +1962,11 @@ int mto_autotune(mto_plan* P, const double* rho, const char* cache_path, void* s
   }
   for (auto& g : P->groups) {
     char line[96];
-    snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=%d: chosen\n", g.p, g.d, g.lds_nc ? g.lds_nc : g.ncol,
-             g.lds_nc ? 0 : g.waves);
+    if (g.stored)
+      snprintf(line, sizeof line, "p=%d d=%d ncol=1 ks=-2: chosen\n", g.p, g.d);
+    else
+      snprintf(line, sizeof line, "p=%d d=%d ncol=%d ks=%d: chosen\n", g.p, g.d, g.lds_nc ? g.lds_nc : g.ncol,
+               g.lds_nc ? 0 : g.waves);
     rep += line;
   }
   int rc = rebuild_tiles(P);
@@ -1924,7 +2026,7 @@ int mto_time_contraction(mto_plan* P, const double* rho, int32_t reps, int32_t i
       for (size_t gi = 0; gi < ng; ++gi) {
         auto& g = P->groups[gi];
         hipEvent_t* e = &ev[2 * (ng * i + gi)];
-        launch_elem(P->gdev(g), P->prm.kernel_path, P->d_tiles, P->E, P->p, s, ELEM_PCG, k, st, e[0], e[1]);
+        enq_elem_group(P, g, P->p, ELEM_PCG, k, st, e[0], e[1]);
       }
     }
     launch_dof1(s, k, st);
@@ -1935,7 +2037,8 @@ int mto_time_contraction(mto_plan* P, const double* rho, int32_t reps, int32_t i
   HIP_TRY(hipStreamSynchronize(st));
   double total = 0.0;
   for (size_t j = 0; j < ng * (size_t)reps; ++j) {
-    if (fused ? (j % ng != 0 || P->fused_n_tiles == 0) : P->groups[j % ng].n_tiles == 0)
+    const GroupHost& gj = P->groups[j % ng];
+    if (fused ? (j % ng != 0 || P->fused_n_tiles == 0) : (gj.stored ? gj.ms_n_tiles : gj.n_tiles) == 0)
       continue;  // nothing launched, events never recorded
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));

@@ -48,7 +48,8 @@ class _Params(ctypes.Structure):
                 ("q", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("kernel_path", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("mg_omega", ctypes.c_double), ("mg_coarse_max", ctypes.c_int32)]
+                ("mg_omega", ctypes.c_double), ("mg_coarse_max", ctypes.c_int32),
+                ("stored_matrices", ctypes.c_int32)]
 
 
 class _Spring(ctypes.Structure):
@@ -188,7 +189,7 @@ def _f64_cuda(t, n, name):
 def default_params(**kw):
     prm = dict(E0=1.0, Emin=1e-9, nu=0.3, q=3.0, rtol=1e-11, max_iter=0, kernel_path=PATH_MFMA,
                iters_per_launch=0, max_restarts=3, precond=PRECOND_MG_ASM,
-               mg_omega=0.0, mg_coarse_max=0)
+               mg_omega=0.0, mg_coarse_max=0, stored_matrices=0)
     prm.update(kw)
     return prm
 
@@ -233,7 +234,7 @@ class Plan:
         arr, self._keep = _problem_array(problems)
         cp = _Params(prm["E0"], prm["Emin"], prm["nu"], prm["q"], prm["rtol"], prm["max_iter"],
                      prm["kernel_path"], prm["iters_per_launch"], prm["max_restarts"], prm["precond"],
-                     prm["mg_omega"], prm["mg_coarse_max"])
+                     prm["mg_omega"], prm["mg_coarse_max"], prm["stored_matrices"])
         h = ctypes.c_void_p()
         _check(_lib.mto_batch_plan_create(arr, len(problems), ctypes.byref(cp), ctypes.byref(h)))
         self._keep = []

@@ -470,6 +470,20 @@ def test_autotune_cache(cuda, tmp_path):
     ua, ca, ga, _ = a.solve(rho)
     ub, cb, gb, _ = b.solve(rho)
     assert torch.equal(ua, ub) and torch.equal(ca, cb) and torch.equal(ga, gb)
+    # a stored-matrix choice (ks = -2) in the file is taken as well
+    st_path = tmp_path / "stored.txt"
+    fields = [ln.split() for ln in path.read_text().splitlines() if not ln.startswith("#")]
+    for f in fields:
+        if f[1] == "4":
+            f[4], f[5] = "1", "-2"
+        if f[1] == "0":  # one launch per group, so the stored choice is used
+            f[4] = "2"
+    st_path.write_text("".join(" ".join(f) + "\n" for f in fields))
+    c = m.Plan(pr, stored_matrices=1)
+    rep_c = c.autotune(rho, cache=str(st_path))
+    assert "p=4 d=5 ncol=1 ks=-2: chosen" in rep_c, rep_c
+    uc, cc, gc, stc = c.solve(rho)
+    check_solution(c, [pr], uc, cc, gc, stc)
     bad = tmp_path / "bad.txt"
     bad.write_text("gfx950 3 4 nonsense\n")
     with pytest.raises(m.MtoError) as ei:
@@ -511,6 +525,61 @@ def test_lds_staged_product_many_tiles(cuda):
         y = plan.apply_stiffness(rho, xt).cpu().numpy()
         assert rel(y, yref.ravel()) < 1e-13, (nc, rel(y, yref.ravel()))
         assert rel(y, y1) < 1e-14
+
+
+@pytest.mark.parametrize("precond", ["schwarz", "jacobi"])
+@pytest.mark.parametrize("name", ["uniform_p1d3", "uniform_p2d2", "uniform_p3d4", "uniform_p4d5", "uniform_p4d8_max",
+                                  "mixed16x8", "mixed_3loads"])
+def test_solve_parity_stored(cuda, name, precond):
+    """Solves with stored element matrices (K_e = sum_s E_s K_s assembled in
+    the set-up, each product reading it) on every group, against the oracle."""
+    m = mto()
+    prs = CASES[name]()
+    plan = m.Plan(prs, precond=m.PRECOND_MG_ASM if precond == "schwarz" else m.PRECOND_JACOBI)
+    plan.set_tile(1, -2)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
+
+
+def test_stored_batch_many_loads(cuda):
+    """Stored element matrices over a batch of uneven instances, one with six
+    load cases (two passes of four systems over each tile), one with one;
+    solved twice with different densities (the matrices are reassembled),
+    against the oracle."""
+    m = mto()
+    loads = [(12, k, 0.0, -1.0, k) for k in range(6)]
+    prs = [P.uniform_random(12, 6, 4, 5, seed=71, loads=loads, n_load_cases=6), P.small_mixed(10, 5, seed=72)]
+    plan = m.Plan(prs)
+    plan.set_tile(1, -2, p=4, d=5)
+    for seed in (0, 1):
+        if seed:
+            for pr in prs:
+                pr.rho = np.clip(pr.rho * np.random.default_rng(seed).uniform(0.5, 1.0, pr.rho.size), 1e-3, 1.0)
+        rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+        u, c, g, st = plan.solve(rho)
+        check_solution(plan, prs, u, c, g, st)
+
+
+def test_stored_product_apply(cuda):
+    """mto_apply_stiffness with stored element matrices (assembled from the
+    given densities) on a 40 x 23 p = 4, d = 5 mesh with two load cases
+    equals the oracle's K x and the contraction to 1e-13."""
+    pr = P.uniform_random(40, 23, 4, 5, seed=91, loads=[(40, 11, 0.0, -1.0, 0), (40, 3, 1.0, 0.0, 1)], n_load_cases=2)
+    K, space, *_ = assemble(pr.nelx, pr.nely, pr.p, pr.d, pr.rho, pr.E0, pr.Emin, pr.q, pr.nu)
+    free = free_mask(space, pr.supports)
+    x = np.random.default_rng(6).standard_normal((2, space.n_dof))
+    x[:, ~free] = 0.0
+    yref = (K @ x.T).T
+    yref[:, ~free] = 0.0
+    plan = mto().Plan(pr)
+    rho = torch.tensor(pr.rho, device=cuda)
+    xt = torch.tensor(x.ravel(), device=cuda)
+    y1 = plan.apply_stiffness(rho, xt).cpu().numpy()
+    plan.set_tile(1, -2)
+    y = plan.apply_stiffness(rho, xt).cpu().numpy()
+    assert rel(y, yref.ravel()) < 1e-13, rel(y, yref.ravel())
+    assert rel(y, y1) < 1e-13
 
 
 @pytest.mark.parametrize("name", ["mixed16x8", "mixed_3loads", "uniform_p4d5"])
