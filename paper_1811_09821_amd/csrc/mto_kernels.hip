@@ -485,6 +485,20 @@ __global__ __launch_bounds__(512) void k_elem_mfma(GroupDev g, const Tile* __res
 // each lane's B value with the 2 table entries of its reduction index,
 // summed over the 4 lanes that share a column at the end, instead of a
 // 16-row MFMA block of which 14 rows are padding.
+// Copies the FR doubles of one cell's tables from global memory to LDS with
+// the direct global-to-LDS loads of gfx950 (16 bytes per lane, no registers):
+// 1 KB chunks, chunk k by wave k % 4; the caller waits on vmcnt before the
+// barrier that publishes them.  src and dst are 16-byte aligned (FR is even).
+template <int FR>
+__device__ __forceinline__ void stage_tables(const double* __restrict__ src, double* dst, int wave, int lane) {
+  constexpr int NCH = (FR + 127) / 128;
+  for (int ch = wave; ch < NCH; ch += 4) {
+    const int off = ch * 128 + 2 * lane;
+    if (off < FR)  // lane l fills dst[ch * 128 + 2 l ..]
+      __builtin_amdgcn_global_load_lds(src + off, (__attribute__((address_space(3))) void*)(dst + ch * 128), 16, 0, 0);
+  }
+}
+
 template <int P, int NC>
 __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, const double* __restrict__ E,
                                               const double* __restrict__ xin, const PcgDev& s, int mode, int it_k,
@@ -492,42 +506,26 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
   constexpr int NE = ne_of(P), NEP = nep_of(P), NJ = NEP / 4, WC = 16 * NC, TC = 4 * WC;
   constexpr int MB = mbm_of(P), TR = tr_of(P), FRJ = frj_of(P);
   constexpr int FR = NJ * FRJ;             // doubles of one cell's tables
-  constexpr int FPT = (FR + 255) / 256;    // of those, per thread
   constexpr int NT = NEP * TC, GPT = (NT + 255) / 256;  // gathered entries, per thread
+  // LDS: two cell-table buffers; the element vectors overlay the second one
+  // (and beyond) until they are in registers
   double* afr = lds;                // [2][FR]
-  double* ush = lds + 2 * FR;       // [NEP][TC] element vectors
-  double* scal = ush + NT;          // [2] beta, active
+  double* ush = lds + FR;           // [NEP][TC] element vectors
+  double* scal = lds + (2 * FR > FR + NT ? 2 * FR : FR + NT);  // [2] beta, active
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   // a stopped system has nothing to do (PCG mode also checks this iteration's residual below)
   if (mode != ELEM_APPLY && s.status[t.sys] != SYS_RUNNING) return;
   const bool pcg = mode == ELEM_PCG;
   const int n = lane & 15, kq = lane >> 4;
-  // this wave's columns: cell offsets and scatter slots, requested first
+  const double* __restrict__ kf = g.kfrags;
+  stage_tables<FR>(kf, afr, wave, lane);  // cell 0, in flight during the gather
   int cellb[NC];
   bool valid[NC];
-  int sidx[NC][MB][4];
-  int sidt[NC];  // the tail row 16 MB + kq (kq < TR)
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int col = wave * WC + c * 16 + n;
     valid[c] = col < t.count;
     cellb[c] = valid[c] ? g.cell[t.elem_begin + col] : 0;
-#pragma unroll
-    for (int b = 0; b < MB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = b * 16 + kq + 4 * r;
-        sidx[c][b][r] = (valid[c] && row < NE) ? g.sidx[row * g.npad + t.elem_begin + col] : -1;
-      }
-    sidt[c] = (TR > 0 && valid[c] && kq < TR) ? g.sidx[(16 * MB + kq) * g.npad + t.elem_begin + col] : -1;
-  }
-  // cell 0's tables: global loads now, LDS stores after the gather loads are issued
-  const double* __restrict__ kf = g.kfrags;
-  double stg[FPT];
-#pragma unroll
-  for (int k = 0; k < FPT; ++k) {
-    const int i = tid + 256 * k;
-    stg[k] = kf[i < FR ? i : FR - 1];
   }
   // the element vectors: clamped, unconditional loads (column to the tile's
   // last element, DOF to the system's first), zeroed where absent
@@ -556,11 +554,6 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < FPT; ++k) {
-    const int i = tid + 256 * k;
-    if (i < FR) afr[i] = stg[k];
-  }
   if (pcg && wave == 0) {
     const Scal sc = pcg_state(s, t.sys, t.pc_begin, t.pc_end, *s.it_base + it_k, true);
     if (lane == 0) {
@@ -569,13 +562,17 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
     }
   }
   __syncthreads();
-  if (pcg && scal[1] == 0.0) return;  // system stopped: uniform over the block
+  if (pcg && scal[1] == 0.0) {  // system stopped: uniform over the block
+    __builtin_amdgcn_s_waitcnt(0);  // no table copy outlives the block
+    return;
+  }
   const double beta = pcg ? scal[0] : 0.0;
 #pragma unroll
   for (int k = 0; k < GPT; ++k) {  // p = z + beta p_old, formed as k_dof1 stores it
     const int e = tid + 256 * k;
     if (e < NT) ush[e] = pcg ? fma(beta, gv[k], gz[k]) : gv[k];
   }
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's share of cell 0's tables has landed
   __syncthreads();
   double u[NC][NJ];
 #pragma unroll
@@ -585,6 +582,7 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) u[c][jj] = rigid_free<P>(ush[(4 * jj + kq) * TC + col], 4 * jj + kq, x0, x1, th);
   }
+  __syncthreads();  // the element vectors are in registers: the second table buffer is free
   d4 acc[MB][NC];
 #pragma unroll
   for (int b = 0; b < MB; ++b)
@@ -600,16 +598,11 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
   for (int c = 0; c < NC; ++c) e[c] = valid[c] ? E[cellb[c]] : 0.0;
   for (int sc = 0; sc < g.S; ++sc) {
     const double* __restrict__ cur = afr + (sc & 1) * FR;
-    double* __restrict__ nxt = afr + ((sc + 1) & 1) * FR;
+    double* nxt = afr + ((sc + 1) & 1) * FR;
     const bool more = sc + 1 < g.S;
     double en[NC];
-    if (more) {  // next cell: tables and moduli in flight during this cell's MFMAs
-      const double* __restrict__ kn = kf + (size_t)(sc + 1) * FR;
-#pragma unroll
-      for (int k = 0; k < FPT; ++k) {
-        const int i = tid + 256 * k;
-        stg[k] = kn[i < FR ? i : FR - 1];
-      }
+    if (more) {  // next cell: tables (straight to LDS) and moduli in flight during this cell's MFMAs
+      stage_tables<FR>(kf + (size_t)(sc + 1) * FR, nxt, wave, lane);
 #pragma unroll
       for (int c = 0; c < NC; ++c) en[c] = valid[c] ? E[cellb[c] + sc + 1] : 0.0;
     }
@@ -632,28 +625,33 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
     }
     if (more) {
 #pragma unroll
-      for (int k = 0; k < FPT; ++k) {
-        const int i = tid + 256 * k;
-        if (i < FR) nxt[i] = stg[k];
-      }
-#pragma unroll
       for (int c = 0; c < NC; ++c) e[c] = en[c];
     }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's share of the next cell's tables has landed
     __syncthreads();  // the next cell's tables are in; this cell's buffer may be overwritten
   }
+  // the scatter slots, requested now (not held in registers through the loop)
   double* __restrict__ sl = s.slots + t.slot_off;
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+  for (int c = 0; c < NC; ++c) {
+    const int col = wave * WC + c * 16 + n;
+    int sidx[MB][4];
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = b * 16 + kq + 4 * r;
+        sidx[b][r] = (valid[c] && row < NE) ? g.sidx[row * g.npad + t.elem_begin + col] : -1;
+      }
+    const int sidt = (TR > 0 && valid[c] && kq < TR) ? g.sidx[(16 * MB + kq) * g.npad + t.elem_begin + col] : -1;
 #pragma unroll
     for (int b = 0; b < MB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (sidx[c][b][r] >= 0) sl[sidx[c][b][r]] = acc[b][c][r];
-  if constexpr (TR > 0) {
-    // tail rows: sum over the 4 lanes of each column ((a + b) + (c + d), the
-    // same value in all four), lane kq writes row 16 MB + kq
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
+        if (sidx[b][r] >= 0) sl[sidx[b][r]] = acc[b][c][r];
+    if constexpr (TR > 0) {
+      // tail rows: sum over the 4 lanes of each column ((a + b) + (c + d), the
+      // same value in all four), lane kq writes row 16 MB + kq
       double mine = 0.0;
 #pragma unroll
       for (int r = 0; r < TR; ++r) {
@@ -662,7 +660,7 @@ __device__ __forceinline__ void elem_lds_tile(const GroupDev& g, const Tile& t, 
         v += __shfl_xor(v, 32);
         if (kq == r) mine = v;
       }
-      if (sidt[c] >= 0) sl[sidt[c]] = mine;
+      if (sidt >= 0) sl[sidt] = mine;
     }
   }
 }

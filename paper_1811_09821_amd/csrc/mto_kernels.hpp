@@ -149,10 +149,11 @@ inline size_t elem_lds_bytes(int p, int ncol, int ks) {
 constexpr size_t ELEM_LDS_LIMIT = 64 * 1024;
 
 // Dynamic LDS of the LDS-staged contraction k_elem_mfma_lds<P, nc>: the A
-// fragments of two cells, the tile's 64 nc element vectors and two scalars.
+// fragments of two cells, the tile's 64 nc element vectors overlaying the
+// second (and beyond, where larger), and two scalars.
 inline size_t elem_lds_staged_bytes(int p, int nc) {
-  const size_t fr = (size_t)(nep_of(p) / 4) * frj_of(p);
-  return 8 * (2 * fr + (size_t)nep_of(p) * 64 * nc + 2);
+  const size_t fr = (size_t)(nep_of(p) / 4) * frj_of(p), nt = (size_t)nep_of(p) * 64 * nc;
+  return 8 * ((2 * fr > fr + nt ? 2 * fr : fr + nt) + 2);
 }
 constexpr size_t ELEM_LDS_STAGED_LIMIT = 160 * 1024;
 
