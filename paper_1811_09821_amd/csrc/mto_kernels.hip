@@ -62,43 +62,55 @@ __device__ __forceinline__ double wave_sum(const double* __restrict__ arr, int a
   return v;
 }
 
-// Three wave_sum reductions over the same chunk range in one pass: each
+// N wave_sum reductions over the same chunk range in one pass: each
 // array's terms are added in wave_sum's order, so the results are identical
-// to three calls, at one memory round trip instead of three.
-__device__ __forceinline__ void wave_sum3(const double* __restrict__ x, const double* __restrict__ y,
-                                          const double* __restrict__ z, int a, int b, double& sx, double& sy,
-                                          double& sz) {
+// to N calls, at one memory round trip instead of N.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(const double* const (&arr)[N], int a, int b, double (&out)[N]) {
   const int lane = threadIdx.x & 63;
-  double vx = 0.0, vy = 0.0, vz = 0.0;
+  double v[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = 0.0;
   for (int k = a + lane; k < b; k += 256) {
-    double tx[4], ty[4], tz[4];
+    double tv[N][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {  // unconditional (clamped) loads, absent terms zeroed after
       const int kk = min(k + 64 * u, b - 1);
       const bool in = k + 64 * u < b;
-      const double a0 = x[kk], a1 = y[kk], a2 = z[kk];
-      tx[u] = in ? a0 : 0.0;
-      ty[u] = in ? a1 : 0.0;
-      tz[u] = in ? a2 : 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const double x = arr[j][kk];
+        tv[j][u] = in ? x : 0.0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      vx += tx[u];
-      vy += ty[u];
-      vz += tz[u];
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < N; ++j) v[j] += tv[j][u];
   }
-  for (int m = 32; m >= 1; m >>= 1) {
-    vx += __shfl_xor(vx, m);
-    vy += __shfl_xor(vy, m);
-    vz += __shfl_xor(vz, m);
-  }
-  sx = vx;
-  sy = vy;
-  sz = vz;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] += __shfl_xor(v[j], m);
+#pragma unroll
+  for (int j = 0; j < N; ++j) out[j] = v[j];
 }
 
-// Deterministic block sum (NW waves), valid in thread 0.
+// The stop threshold of a PCG cycle on r.r: rtol^2 f.f, or, when larger, the
+// rounding floor of the cycle's residual recurrence, (4 eps ||D x||)^2 with
+// D = diag(K) (xx = sum of (D x)_i^2 over the system).  Below that floor the
+// recursive residual keeps falling but the true residual of x does not (the
+// FP64 product K x carries errors of about eps |K| |x|, large where regions
+// joined to the supports through void material move far); the cycle stops
+// there and the refinement restart, from the double-double true residual,
+// continues with a small correction.  4 eps ||D x|| is about the floor
+// measured on the mixed batch (its true residual after the cycle is 2.6 to
+// 3.9 times eps ||D x||), and far below rtol ||f|| where x stays moderate.
+__device__ __forceinline__ double stop_thr2(const PcgDev& s, int sys, double xx) {
+  constexpr double G2 = 16.0 * 0x1p-106;  // (4 eps)^2, eps = 2^-53
+  return fmax(s.tol2[sys], G2 * xx);
+}
+
 template <int NW>
 __device__ __forceinline__ double block_sum(double v, double* lds) {
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
@@ -124,16 +136,25 @@ __device__ __forceinline__ Scal pcg_state(const PcgDev& s, int sys, int pc_begin
                                           bool want_beta) {
   const int pi = it & 1;
   const int st = s.status[sys];
-  const double tol2 = s.tol2[sys];
-  double rr, rz_new = 0.0, rz_old = 1.0;
+  double rr, xx, rz_new = 0.0, rz_old = 1.0;
   if (want_beta && it > 0) {
-    wave_sum3(s.part_rr + pi * s.n_chunks, s.part_rz + pi * s.n_chunks, s.part_rz + (pi ^ 1) * s.n_chunks,
-              pc_begin, pc_end, rr, rz_new, rz_old);
+    const double* const arr[4] = {s.part_rr + pi * s.n_chunks, s.part_rz + pi * s.n_chunks,
+                                  s.part_rz + (pi ^ 1) * s.n_chunks, s.part_xx + pi * s.n_chunks};
+    double out[4];
+    wave_sum_n<4>(arr, pc_begin, pc_end, out);
+    rr = out[0];
+    rz_new = out[1];
+    rz_old = out[2];
+    xx = out[3];
   } else {
-    rr = wave_sum(s.part_rr + pi * s.n_chunks, pc_begin, pc_end);
+    const double* const arr[2] = {s.part_rr + pi * s.n_chunks, s.part_xx + pi * s.n_chunks};
+    double out[2];
+    wave_sum_n<2>(arr, pc_begin, pc_end, out);
+    rr = out[0];
+    xx = out[1];
   }
   Scal o;
-  o.active = (st == SYS_RUNNING) && !(rr <= tol2);
+  o.active = (st == SYS_RUNNING) && !(rr <= stop_thr2(s, sys, xx));
   o.beta = (want_beta && it > 0) ? rz_new / rz_old : 0.0;
   return o;
 }
@@ -1155,6 +1176,8 @@ __global__ __launch_bounds__(VBLOCK) void k_init(PcgDev s, int use_slots) {
     s.part_rz[s.n_chunks + blockIdx.x] = 1.0;  // rz of iteration -1: unused (beta_0 = 0)
     s.part_rr[blockIdx.x] = arr;
     s.part_rr[s.n_chunks + blockIdx.x] = arr;
+    s.part_xx[blockIdx.x] = 0.0;  // x = 0 at the start of a cycle
+    s.part_xx[s.n_chunks + blockIdx.x] = 0.0;
     s.part_aux[blockIdx.x] = aff;
   }
 }
@@ -1240,11 +1263,13 @@ __global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
   const double xi = s.x[o + ic], pi_ = s.p[o + ic], qi = s.q[o + ic], ri = s.r[o + ic];
   const double di = s.dinv[ch.inst_free_off + ic];
   if (threadIdx.x < 64) {
-    // r.r (convergence), r.z and p.q of this system in one pass
-    double rr, rz, pq;
-    wave_sum3(s.part_rr + par * s.n_chunks, s.part_rz + par * s.n_chunks, s.part_pq, ch.pc_begin, ch.pc_end, rr, rz,
-              pq);
-    const bool active = s.status[ch.sys] == SYS_RUNNING && !(rr <= s.tol2[ch.sys]);
+    // r.r and |D x|^2 (convergence), r.z and p.q of this system in one pass
+    const double* const arr[4] = {s.part_rr + par * s.n_chunks, s.part_rz + par * s.n_chunks, s.part_pq,
+                                  s.part_xx + par * s.n_chunks};
+    double out[4];
+    wave_sum_n<4>(arr, ch.pc_begin, ch.pc_end, out);
+    const double rr = out[0], rz = out[1], pq = out[2];
+    const bool active = s.status[ch.sys] == SYS_RUNNING && !(rr <= stop_thr2(s, ch.sys, out[3]));
     if (threadIdx.x == 0) {
       lds[VWAVES] = rz;
       lds[VWAVES + 1] = pq;
@@ -1259,21 +1284,26 @@ __global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
     return;
   }
   const double alpha = rz / pq;
-  double arz = 0.0, arr = 0.0;
+  double arz = 0.0, arr = 0.0, axx = 0.0;
   if (in) {
-    s.x[o + i] = fma(alpha, pi_, xi);
+    const double xn = fma(alpha, pi_, xi);
+    s.x[o + i] = xn;
     const double rn = fma(-alpha, qi, ri);
     const double zn = di * rn;
     s.r[o + i] = rn;
     s.z[o + i] = zn;
     arz = rn * zn;
     arr = rn * rn;
+    const double dx = xn / di;  // (D x)_i, D = diag(K) (dinv = 1 / diag, or its l1 variant)
+    axx = dx * dx;
   }
   arz = block_sum<VWAVES>(arz, lds);
   arr = block_sum<VWAVES>(arr, lds);
+  axx = block_sum<VWAVES>(axx, lds);
   if (threadIdx.x == 0) {
     s.part_rz[(par ^ 1) * s.n_chunks + blockIdx.x] = arz;
     s.part_rr[(par ^ 1) * s.n_chunks + blockIdx.x] = arr;
+    s.part_xx[(par ^ 1) * s.n_chunks + blockIdx.x] = axx;
     if (blockIdx.x == ch.pc_begin) s.iters[ch.sys] = it + 1;
   }
 }
@@ -1287,14 +1317,17 @@ __global__ __launch_bounds__(BLOCK) void k_advance(PcgDev s, int G) {
   double far = 0.0;  // largest rr / tol2 of a running system (how far it is from stopping)
   for (int sys = wave; sys < s.n_sys; sys += WAVES) {
     const SysDesc& sd = s.sys[sys];
-    const double rr = wave_sum(s.part_rr + (it_new & 1) * s.n_chunks, sd.chunk_begin, sd.chunk_end);
+    const double* const arr[2] = {s.part_rr + (it_new & 1) * s.n_chunks, s.part_xx + (it_new & 1) * s.n_chunks};
+    double out[2];
+    wave_sum_n<2>(arr, sd.chunk_begin, sd.chunk_end, out);
+    const double rr = out[0], thr = stop_thr2(s, sys, out[1]);
     const int st = s.status[sys];
     if (st == SYS_RUNNING) {
-      if (rr <= s.tol2[sys]) {
+      if (rr <= thr) {
         if (lane == 0) s.status[sys] = SYS_CONVERGED;
       } else {
         ++active;
-        far = fmax(far, rr / s.tol2[sys]);
+        far = fmax(far, rr / thr);
       }
     }
   }

@@ -125,6 +125,7 @@ struct PcgDev {
   double* part_pq;         // [n_chunks]
   double* part_rz;         // [2][n_chunks]
   double* part_rr;         // [2][n_chunks]
+  double* part_xx;         // [2][n_chunks]: sum of (x_i / dinv_i)^2 (rounding floor of the cycle, see pcg_state)
   double* part_aux;        // [3][n_chunks]: f.f, f.x, |f - Kx|^2
   int32_t* status;         // [n_sys]
   int32_t* iters;          // [n_sys]

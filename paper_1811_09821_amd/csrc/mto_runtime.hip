@@ -141,7 +141,7 @@ struct mto_plan {
   double* slots = nullptr;
   double* slots_lo = nullptr;  // low parts of the double-double residual contraction
   double *xs_hi = nullptr, *xs_lo = nullptr;  // refined solution, double-double
-  double *part_pq = nullptr, *part_rz = nullptr, *part_rr = nullptr, *part_aux = nullptr;
+  double *part_pq = nullptr, *part_rz = nullptr, *part_rr = nullptr, *part_aux = nullptr, *part_xx = nullptr;
   // per-system results in one block, fetched with one copy: status and
   // iteration count (int32 each, one double's width per system), then
   // sys_out [n_sys][4]
@@ -211,6 +211,7 @@ struct mto_plan {
     s.part_pq = part_pq;
     s.part_rz = part_rz;
     s.part_rr = part_rr;
+    s.part_xx = part_xx;
     s.part_aux = part_aux;
     s.status = status;
     s.iters = iters;
@@ -909,6 +910,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_alloc(P, &P->xs_lo, P->n_vec)) ||
       (rc = dev_alloc(P, &P->part_pq, nch)) || (rc = dev_alloc(P, &P->part_rz, 2 * nch)) ||
       (rc = dev_alloc(P, &P->part_rr, 2 * nch)) || (rc = dev_alloc(P, &P->part_aux, 3 * nch)) ||
+      (rc = dev_alloc(P, &P->part_xx, 2 * nch)) ||
       (rc = dev_alloc(P, &P->sysblk, 5 * (size_t)P->n_sys)) ||
       (rc = dev_alloc(P, &P->it_base, 1)) || (rc = dev_alloc(P, &P->progress, 2)) ||
       (rc = dev_alloc(P, &P->bad_rho, 1)) ||
