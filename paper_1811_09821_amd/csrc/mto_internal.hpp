@@ -184,7 +184,9 @@ struct MgChunk {
   int32_t cnx, cny;     // coarser grid
   int32_t nfv, nfe;     // level 1 only: level-0 slot layout
   int32_t level;
-  int32_t pad;
+  int32_t nsys;         // systems served from this chunk: 1 for a system chunk; in an instance-system
+                        // chunk the instance's systems sys .. sys + nsys - 1, whose vectors follow each
+                        // other (each the level's node count of the instance further on)
 };
 
 // Per instance element data for the level-1 (vertex-grid) assembly.

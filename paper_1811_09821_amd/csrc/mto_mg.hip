@@ -590,70 +590,95 @@ __global__ __launch_bounds__(MGB) void k_mg_restrict0(const MgChunk* __restrict_
 // Going up: e~ = e + P~ e2_coarse, then one l1-Jacobi sweep
 // e2 = e~ + D^-1 (r - A e~).  Lane `sub` (< 9) of a node's 16-lane group
 // forms e~ at stencil neighbour sub and its block product; the group sums the
-// products with shuffles and the centre lane (sub 4) writes the node.
-__device__ __forceinline__ void mg_prolong_smooth_node(const MgChunk& ch, int n, int sub, bool node_ok,
-                                                       const double* __restrict__ A,
+// products with shuffles and the centre lane (sub 4) writes the node.  The
+// chunk serves the systems sys .. sys + nsys - 1 of its instance: the
+// neighbour's parents, weights, mask and the operator block are read once and
+// used for every running system, whose vectors lie a level's node count apart.
+// (The body of k_mg_prolong_smooth; ex0, ex1 receive the centre's result of
+// system l for the level-1 injection.)
+template <typename F>
+__device__ __forceinline__ void mg_prolong_smooth_node(const MgChunk& ch, const PcgDev& s, int n, int sub,
+                                                       bool node_ok, const double* __restrict__ A,
                                                        const double* __restrict__ mask,
                                                        const double* __restrict__ dinv,
                                                        const double* __restrict__ r, const double* __restrict__ e,
-                                                       double* __restrict__ e2, double& out0, double& out1) {
+                                                       double* __restrict__ e2, F&& centre) {
   const int nx = ch.nx, ny = ch.ny, cnx = ch.cnx;
-  double et0 = 0.0, et1 = 0.0, c0 = 0.0, c1 = 0.0;
+  const int64_t NN = (int64_t)(nx + 1) * (ny + 1), CN = (int64_t)(cnx + 1) * (ch.cny + 1);
+  bool have = false;
+  int64_t jo = 0, jn = 0, cvi[2][2];
+  double wv[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, m0 = 0.0, m1 = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (node_ok && sub < 9) {
     const int ix = n % (nx + 1), iy = n / (nx + 1);
     const int jx = ix + sub % 3 - 1, jy = iy + sub / 3 - 1;
     if (jx >= 0 && jx <= nx && jy >= 0 && jy <= ny) {
-      const int64_t jo = (int64_t)jy * (nx + 1) + jx;
+      have = true;
+      jo = (int64_t)jy * (nx + 1) + jx;
+      jn = ch.op + jo;
       int px0, px1, py0, py1;
       double vx0, vx1, vy0, vy1;
       parents1d(jx, nx, px0, vx0, px1, vx1);
       parents1d(jy, ny, py0, vy0, py1, vy1);
-      // the four parents' loads are issued together: a missing second
-      // parent (index -1, weight 0) reads the first one and adds 0
-      double p0 = 0.0, p1 = 0.0;
+      // a missing second parent (index -1, weight 0) reads the first one and adds 0
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a2_ = 0; a2_ < 2; ++a2_) {
+          const int py = b == 0 || py1 < 0 ? py0 : py1;
+          const int px = a2_ == 0 || px1 < 0 ? px0 : px1;
+          cvi[b][a2_] = (int64_t)py * (cnx + 1) + px;
+          const int pyw = b == 0 ? py0 : py1, pxw = a2_ == 0 ? px0 : px1;
+          wv[b][a2_] = (pyw >= 0 && pxw >= 0) ? (a2_ == 0 ? vx0 : vx1) * (b == 0 ? vy0 : vy1) : 0.0;
+        }
+      m0 = mask[jn * 2];
+      m1 = mask[jn * 2 + 1];
+      const double* a = A + (ch.op + n) * 36 + sub * 4;
+      a0 = a[0];
+      a1 = a[1];
+      a2 = a[2];
+      a3 = a[3];
+    }
+  }
+  for (int l = 0; l < ch.nsys; ++l) {
+    if (!sys_running(s, ch.sys + l)) continue;  // uniform over the block
+    const int64_t cvec = ch.cvec + l * CN, vec = ch.vec + l * NN;
+    double et0 = 0.0, et1 = 0.0, c0 = 0.0, c1 = 0.0;
+    if (have) {
       double c2[2][2][2];
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2) {
-          const int py = b == 0 || py1 < 0 ? py0 : py1;
-          const int px = a2 == 0 || px1 < 0 ? px0 : px1;
-          const int64_t cv = ch.cvec + (int64_t)py * (cnx + 1) + px;
-          c2[b][a2][0] = e2[cv * 2];
-          c2[b][a2][1] = e2[cv * 2 + 1];
+        for (int a2_ = 0; a2_ < 2; ++a2_) {
+          const int64_t cv = cvec + cvi[b][a2_];
+          c2[b][a2_][0] = e2[cv * 2];
+          c2[b][a2_][1] = e2[cv * 2 + 1];
         }
+      double p0 = 0.0, p1 = 0.0;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int py = b == 0 ? py0 : py1;
-        const double vy = b == 0 ? vy0 : vy1;
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2) {
-          const int px = a2 == 0 ? px0 : px1;
-          const double vx = a2 == 0 ? vx0 : vx1;
-          const double wv = (py >= 0 && px >= 0) ? vx * vy : 0.0;  // a missing parent adds 0
-          p0 += wv * c2[b][a2][0];
-          p1 += wv * c2[b][a2][1];
+        for (int a2_ = 0; a2_ < 2; ++a2_) {
+          p0 += wv[b][a2_] * c2[b][a2_][0];
+          p1 += wv[b][a2_] * c2[b][a2_][1];
         }
-      }
-      const int64_t jn = ch.op + jo, jv = ch.vec + jo;
-      et0 = e[jv * 2] + mask[jn * 2] * p0;
-      et1 = e[jv * 2 + 1] + mask[jn * 2 + 1] * p1;
-      const double* a = A + (ch.op + n) * 36 + sub * 4;
-      c0 = a[0] * et0 + a[1] * et1;
-      c1 = a[2] * et0 + a[3] * et1;
+      const int64_t jv = vec + jo;
+      et0 = e[jv * 2] + m0 * p0;
+      et1 = e[jv * 2 + 1] + m1 * p1;
+      c0 = a0 * et0 + a1 * et1;
+      c1 = a2 * et0 + a3 * et1;
     }
-  }
-  for (int o = 8; o > 0; o >>= 1) {
-    c0 += __shfl_xor(c0, o, 16);
-    c1 += __shfl_xor(c1, o, 16);
-  }
-  out0 = out1 = 0.0;
-  if (node_ok && sub == 4) {
-    const int64_t node = ch.op + n, v = ch.vec + n;
-    out0 = et0 + dinv[node * 2] * (r[v * 2] - c0);
-    out1 = et1 + dinv[node * 2 + 1] * (r[v * 2 + 1] - c1);
-    e2[v * 2] = out0;
-    e2[v * 2 + 1] = out1;
+    for (int o = 8; o > 0; o >>= 1) {
+      c0 += __shfl_xor(c0, o, 16);
+      c1 += __shfl_xor(c1, o, 16);
+    }
+    if (node_ok && sub == 4) {
+      const int64_t node = ch.op + n, v = vec + n;
+      const double out0 = et0 + dinv[node * 2] * (r[v * 2] - c0);
+      const double out1 = et1 + dinv[node * 2 + 1] * (r[v * 2 + 1] - c1);
+      e2[v * 2] = out0;
+      e2[v * 2 + 1] = out1;
+      centre(l, out0, out1);
+    }
   }
 }
 
@@ -673,54 +698,78 @@ __global__ __launch_bounds__(256) void k_mg_resid_restrict(const MgChunk* __rest
                                                            const double* __restrict__ dinv, double* __restrict__ r,
                                                            double* __restrict__ e) {
   const MgChunk ch = chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;  // whole block
+  {  // the chunk serves systems sys .. sys + nsys - 1 of its instance
+    bool any = false;
+    for (int l = 0; l < ch.nsys; ++l) any |= sys_running(s, ch.sys + l);
+    if (!any) return;  // whole block
+  }
   const int sub = threadIdx.x & 15;
   const int n = ch.node_begin + blockIdx.y * MG_RR_NODES + (threadIdx.x >> 4);
   const bool node_ok = n < ch.node_end;
-  double acc0 = 0.0, acc1 = 0.0;
+  const int fnx = ch.fnx, fny = ch.fny;
+  const int64_t NN = (int64_t)(ch.nx + 1) * (ch.ny + 1), FN = (int64_t)(fnx + 1) * (fny + 1);
+  // this lane's fine node, its weight and operator row: read once for all systems
+  bool have = false;
+  int fx = 0, fy = 0;
+  int64_t fo = 0;
+  double w = 0.0, m0 = 0.0, m1 = 0.0, a[9][4];
   if (node_ok && sub < 9) {
-    const int nx = ch.nx, fnx = ch.fnx, fny = ch.fny;
-    const int cx = n % (nx + 1), cy = n / (nx + 1);
-    const int fx = fine_of(cx, fnx) + sub % 3 - 1, fy = fine_of(cy, fny) + sub / 3 - 1;
+    const int cx = n % (ch.nx + 1), cy = n / (ch.nx + 1);
+    fx = fine_of(cx, fnx) + sub % 3 - 1;
+    fy = fine_of(cy, fny) + sub / 3 - 1;
     if (fx >= 0 && fx <= fnx && fy >= 0 && fy <= fny) {
-      const double w = weight1d(fx, fnx, cx) * weight1d(fy, fny, cy);
-      if (w != 0.0) {
-        const int64_t fo = (int64_t)fy * (fnx + 1) + fx;
-        const int64_t fnode = ch.fop + fo, fv = ch.fvec + fo;
-        double t0 = r[fv * 2], t1 = r[fv * 2 + 1];
-        // all nine neighbours' loads are issued together (a neighbour off the
-        // grid reads a clamped one and counts as 0), then used in order
-        double ej[9][2];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          const int jx = fx + k % 3 - 1, jy = fy + k / 3 - 1;
-          const bool in = jx >= 0 && jx <= fnx && jy >= 0 && jy <= fny;
-          const int64_t jv = ch.fvec + (int64_t)min(max(jy, 0), fny) * (fnx + 1) + min(max(jx, 0), fnx);
-          const double v0 = e[jv * 2], v1 = e[jv * 2 + 1];
-          ej[k][0] = in ? v0 : 0.0;
-          ej[k][1] = in ? v1 : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          const double* a = A + fnode * 36 + k * 4;
-          t0 -= a[0] * ej[k][0] + a[1] * ej[k][1];
-          t1 -= a[2] * ej[k][0] + a[3] * ej[k][1];
-        }
-        acc0 = w * mask[fnode * 2] * t0;
-        acc1 = w * mask[fnode * 2 + 1] * t1;
-      }
+      w = weight1d(fx, fnx, cx) * weight1d(fy, fny, cy);
+      have = w != 0.0;
     }
   }
-  for (int o = 8; o > 0; o >>= 1) {
-    acc0 += __shfl_xor(acc0, o, 16);
-    acc1 += __shfl_xor(acc1, o, 16);
+  if (have) {
+    fo = (int64_t)fy * (fnx + 1) + fx;
+    const int64_t fnode = ch.fop + fo;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[k][q] = A[fnode * 36 + k * 4 + q];
+    m0 = mask[fnode * 2];
+    m1 = mask[fnode * 2 + 1];
   }
-  if (node_ok && sub == 0) {
-    const int64_t node = ch.op + n, v = ch.vec + n;
-    r[v * 2] = acc0;
-    r[v * 2 + 1] = acc1;
-    e[v * 2] = dinv[node * 2] * acc0;
-    e[v * 2 + 1] = dinv[node * 2 + 1] * acc1;
+  for (int l = 0; l < ch.nsys; ++l) {
+    if (!sys_running(s, ch.sys + l)) continue;  // uniform over the block
+    const int64_t fvec = ch.fvec + l * FN, vec = ch.vec + l * NN;
+    double acc0 = 0.0, acc1 = 0.0;
+    if (have) {
+      const int64_t fv = fvec + fo;
+      double t0 = r[fv * 2], t1 = r[fv * 2 + 1];
+      // all nine neighbours' loads are issued together (a neighbour off the
+      // grid reads a clamped one and counts as 0), then used in order
+      double ej[9][2];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int jx = fx + k % 3 - 1, jy = fy + k / 3 - 1;
+        const bool in = jx >= 0 && jx <= fnx && jy >= 0 && jy <= fny;
+        const int64_t jv = fvec + (int64_t)min(max(jy, 0), fny) * (fnx + 1) + min(max(jx, 0), fnx);
+        const double v0 = e[jv * 2], v1 = e[jv * 2 + 1];
+        ej[k][0] = in ? v0 : 0.0;
+        ej[k][1] = in ? v1 : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        t0 -= a[k][0] * ej[k][0] + a[k][1] * ej[k][1];
+        t1 -= a[k][2] * ej[k][0] + a[k][3] * ej[k][1];
+      }
+      acc0 = w * m0 * t0;
+      acc1 = w * m1 * t1;
+    }
+    for (int o = 8; o > 0; o >>= 1) {
+      acc0 += __shfl_xor(acc0, o, 16);
+      acc1 += __shfl_xor(acc1, o, 16);
+    }
+    if (node_ok && sub == 0) {
+      const int64_t node = ch.op + n, v = vec + n;
+      r[v * 2] = acc0;
+      r[v * 2 + 1] = acc1;
+      e[v * 2] = dinv[node * 2] * acc0;
+      e[v * 2 + 1] = dinv[node * 2 + 1] * acc1;
+    }
   }
 }
 
@@ -729,32 +778,59 @@ __global__ __launch_bounds__(256) void k_mg_resid_restrict(const MgChunk* __rest
 __global__ __launch_bounds__(256) void k_mg_coarse_solve(const MgChunk* __restrict__ chunks, PcgDev s,
                                                          const double* __restrict__ dense,
                                                          const double* __restrict__ r, double* __restrict__ e2) {
+  constexpr int NL = 4;  // systems per pass over a row of X
   const MgChunk ch = chunks[blockIdx.y];
-  if (!sys_running(s, ch.sys)) return;
-  const int n = 2 * (ch.node_end - ch.node_begin);
+  const int nn = ch.node_end - ch.node_begin, n = 2 * nn;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (i >= n) return;  // whole wave
   const double* __restrict__ X = dense + ch.dense_off + (int64_t)i * n;
-  const double* __restrict__ rv = r + ch.vec * 2;
-  // eight terms per lane are requested before any is added (an eighth of the
-  // memory round trips); each lane adds its terms in index order, an absent
-  // one as 0 * 0, so the sum is the same as term by term
-  double acc = 0.0;
-  for (int j = lane; j < n; j += 512) {
-    double x[8], y[8];
+  // the row of X is read once for up to NL systems of the instance
+  for (int l0 = 0; l0 < ch.nsys; l0 += NL) {
+    bool run[NL];
+    bool any = false;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {  // unconditional (clamped) loads, absent terms zeroed after
-      const int jj = min(j + 64 * u, n - 1);
-      const bool in = j + 64 * u < n;
-      const double a0 = X[jj], a1 = rv[jj];
-      x[u] = in ? a0 : 0.0;
-      y[u] = in ? a1 : 0.0;
+    for (int l = 0; l < NL; ++l) {
+      run[l] = l0 + l < ch.nsys && sys_running(s, ch.sys + l0 + l);
+      any |= run[l];
+    }
+    if (!any) continue;  // whole wave
+    // eight terms per lane are requested before any is added (an eighth of
+    // the memory round trips); each lane adds its terms in index order, an
+    // absent one as 0 * 0, so each sum is the same as term by term
+    double acc[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) acc[l] = 0.0;
+    for (int j = lane; j < n; j += 512) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {  // unconditional (clamped) loads, absent terms zeroed after
+        const int jj = min(j + 64 * u, n - 1);
+        const double a0 = X[jj];
+        x[u] = j + 64 * u < n ? a0 : 0.0;
+      }
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        if (!run[l]) continue;
+        const double* __restrict__ rv = r + (ch.vec + (int64_t)(l0 + l) * nn) * 2;
+        double y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int jj = min(j + 64 * u, n - 1);
+          const double a1 = rv[jj];
+          y[u] = j + 64 * u < n ? a1 : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[l] = fma(x[u], y[u], acc[l]);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = fma(x[u], y[u], acc);
+    for (int l = 0; l < NL; ++l) {
+      if (!run[l]) continue;
+      double v = acc[l];
+      for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+      if (lane == 0) e2[(ch.vec + (int64_t)(l0 + l) * nn) * 2 + i] = v;
+    }
   }
-  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-  if (lane == 0) e2[ch.vec * 2 + i] = acc;
 }
 
 // vfree != NULL (level 1): also z += e2 at the node's free vertex DOFs
@@ -769,24 +845,32 @@ __global__ __launch_bounds__(256) void k_mg_prolong_smooth(const MgChunk* __rest
                                                            const double* __restrict__ r, const double* __restrict__ e,
                                                            double* __restrict__ e2, const int32_t* __restrict__ vfree) {
   const MgChunk ch = chunks[blockIdx.x];
-  if (!sys_running(s, ch.sys)) return;  // whole block
+  {  // the chunk serves systems sys .. sys + nsys - 1 of its instance
+    bool any = false;
+    for (int l = 0; l < ch.nsys; ++l) any |= sys_running(s, ch.sys + l);
+    if (!any) return;  // whole block
+  }
   const int sub = threadIdx.x & 15;
   const int n = ch.node_begin + blockIdx.y * MG_RR_NODES + (threadIdx.x >> 4);
   const bool node_ok = n < ch.node_end;
-  double o0, o1;
-  mg_prolong_smooth_node(ch, n, sub, node_ok, A, mask, dinv, r, e, e2, o0, o1);
+  int f0 = -1, f1 = -1;
   if (vfree && node_ok && sub == 4) {
     const int64_t node = ch.op + n;
-    const int f0 = vfree[node * 2], f1 = vfree[node * 2 + 1];
+    f0 = vfree[node * 2];
+    f1 = vfree[node * 2 + 1];
+  }
+  mg_prolong_smooth_node(ch, s, n, sub, node_ok, A, mask, dinv, r, e, e2, [&](int l, double o0, double o1) {
+    if (!vfree) return;
+    const int64_t dof = s.sys[ch.sys + l].dof_off;
     if (f0 >= 0) {
-      s.z[ch.dof_off + f0] += o0;
-      s.q[ch.dof_off + f0] = o0;
+      s.z[dof + f0] += o0;
+      s.q[dof + f0] = o0;
     }
     if (f1 >= 0) {
-      s.z[ch.dof_off + f1] += o1;
-      s.q[ch.dof_off + f1] = o1;
+      s.z[dof + f1] += o1;
+      s.q[dof + f1] = o1;
     }
-  }
+  });
 }
 
 // Level 1 -> 0: z += injection^T e2_1 at the free vertex DOFs (and into q, as

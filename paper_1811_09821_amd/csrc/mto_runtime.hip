@@ -96,10 +96,12 @@ struct MgHost {
   int L = 0;
   // per level l (index l-1): chunk ranges in the device chunk arrays
   std::vector<int> sys_begin, sys_count, inst_begin, inst_count;
+  // per level l: chunks of each instance serving all its systems (sys = its first, nsys = its count)
+  std::vector<int> isys_begin, isys_count;
   // whole-grid chunks of the coarsest level (one per system, one per
   // instance) for the dense coarse kernels; the node-parallel kernels use the
   // MG_CHUNK-node chunks above on every level
-  int coarse_sys_begin = 0, coarse_inst_begin = 0;
+  int coarse_sys_begin = 0, coarse_inst_begin = 0, coarse_isys_begin = 0;
   std::vector<MgChunk> chunks;  // all levels: system chunks then instance chunks, per level
   MgChunk* d_chunks = nullptr;
   double *A = nullptr, *dinv = nullptr, *mask = nullptr;  // operators [op nodes]
@@ -115,6 +117,8 @@ struct MgHost {
   const MgChunk* instc(int l) const { return d_chunks + inst_begin[l - 1]; }
   const MgChunk* coarse_sysc() const { return d_chunks + coarse_sys_begin; }
   const MgChunk* coarse_instc() const { return d_chunks + coarse_inst_begin; }
+  const MgChunk* isysc(int l) const { return d_chunks + isys_begin[l - 1]; }
+  const MgChunk* coarse_isysc() const { return d_chunks + coarse_isys_begin; }
 };
 
 struct mto_plan {
@@ -566,9 +570,14 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
   M.sys_count.assign(L, 0);
   M.inst_begin.assign(L, 0);
   M.inst_count.assign(L, 0);
-  auto make = [&](int l, int i, int sys, int nb, int ne) {
+  M.isys_begin.assign(L, 0);
+  M.isys_count.assign(L, 0);
+  std::vector<int> first_sys(n, -1);
+  for (int s = P->n_sys - 1; s >= 0; --s) first_sys[P->sys[s].inst] = s;
+  auto make = [&](int l, int i, int sys, int nb, int ne, int nsys = 1) {
     MgChunk c{};
     c.sys = sys;
+    c.nsys = nsys;
     c.inst = i;
     c.level = l + 1;
     c.node_begin = nb;
@@ -618,6 +627,13 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
       for (int b = 0; b < N; b += MG_CHUNK) M.chunks.push_back(make(l, i, -1, b, std::min(N, b + MG_CHUNK)));
     }
     M.inst_count[l] = (int)M.chunks.size() - M.inst_begin[l];
+    M.isys_begin[l] = (int)M.chunks.size();
+    for (int i = 0; i < n; ++i) {
+      const int N = (dims[i][l].first + 1) * (dims[i][l].second + 1);
+      for (int b = 0; b < N; b += MG_CHUNK)
+        M.chunks.push_back(make(l, i, first_sys[i], b, std::min(N, b + MG_CHUNK), P->L[i]));
+    }
+    M.isys_count[l] = (int)M.chunks.size() - M.isys_begin[l];
   }
   M.coarse_sys_begin = (int)M.chunks.size();
   for (int s = 0; s < P->n_sys; ++s) {
@@ -627,6 +643,10 @@ int build_mg(mto_plan* P, const std::vector<InstanceHost>& I) {
   M.coarse_inst_begin = (int)M.chunks.size();
   for (int i = 0; i < n; ++i)
     M.chunks.push_back(make(L - 1, i, -1, 0, (dims[i][L - 1].first + 1) * (dims[i][L - 1].second + 1)));
+  M.coarse_isys_begin = (int)M.chunks.size();
+  for (int i = 0; i < n; ++i)
+    M.chunks.push_back(
+        make(L - 1, i, first_sys[i], 0, (dims[i][L - 1].first + 1) * (dims[i][L - 1].second + 1), P->L[i]));
   int rc;
   if ((rc = dev_upload(P, &M.d_chunks, M.chunks)) || (rc = dev_alloc(P, &M.A, 36 * (size_t)op_tot)) ||
       (rc = dev_alloc(P, &M.dinv, 2 * (size_t)op_tot)) || (rc = dev_alloc(P, &M.mask, 2 * (size_t)op_tot)) ||
@@ -1038,11 +1058,11 @@ void enq_coarse_correction(mto_plan* P, hipStream_t st) {
   const PcgDev s = P->pcg();
   launch_mg_restrict0(M.sysc(1), M.sys_count[0], s, M.vfree, M.dinv, M.r, M.e, st);
   for (int l = 2; l <= M.L; ++l)
-    launch_mg_resid_restrict(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, st);
-  launch_mg_coarse_solve(M.coarse_sysc(), P->n_sys, M.coarse_nmax, s, M.dense, M.r, M.e2, st);
+    launch_mg_resid_restrict(M.isysc(l), M.isys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, st);
+  launch_mg_coarse_solve(M.coarse_isysc(), P->n_inst, M.coarse_nmax, s, M.dense, M.r, M.e2, st);
   // level 1 also injects its correction into z (with one level, prolong0 does)
   for (int l = M.L - 1; l >= 1; --l)
-    launch_mg_prolong_smooth(M.sysc(l), M.sys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, M.e2,
+    launch_mg_prolong_smooth(M.isysc(l), M.isys_count[l - 1], s, M.A, M.mask, M.dinv, M.r, M.e, M.e2,
                              l == 1 ? M.vfree : nullptr, st);
   if (M.L == 1) launch_mg_prolong0(M.sysc(1), M.sys_count[0], s, M.vfree, M.e2, st);
 }
