@@ -268,24 +268,6 @@ __global__ __launch_bounds__(16 * dd_rows<P>()) void k_elem_dd(GroupDev g, const
   slots_lo[t.slot_off + si] = y.lo;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
-// XCD i mod 8), each with its own L2.  These bijections of [0, T) keep
-// neighbouring elements, which share vertex and edge DOFs in their gathers,
-// in one L2.  run <= 0: each XCD takes one contiguous eighth of the tiles
-// (best for a single system).  run > 0: each XCD takes runs of `run`
-// consecutive tiles dealt round-robin, so that when the tiles of stopped
-// systems return at once the remaining work is still spread over all XCDs
-// (batches whose systems converge at different iterations).
-__device__ __forceinline__ int xcd_tile(int i, int T, int run) {
-  const int x = i & 7, k = i >> 3;
-  if (run <= 0) {
-    const int q = T >> 3, r = T & 7;
-    return x * q + min(x, r) + k;
-  }
-  if (i >= T / (8 * run) * (8 * run)) return i;  // the tail, in order
-  return ((k / run) * 8 + x) * run + k % run;
-}
-
 // Removing an element's rigid motion (exact for the products: K_s annihilates
 // rigid motions, its FP64 rounding does not, and a region joined to the
 // supports through void material moves rigidly by ~1e9 times its

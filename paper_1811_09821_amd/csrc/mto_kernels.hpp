@@ -8,6 +8,24 @@
 
 namespace mto {
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
+// XCD i mod 8), each with its own L2.  These bijections of [0, T) keep
+// neighbouring elements, which share vertex and edge DOFs in their gathers,
+// in one L2.  run <= 0: each XCD takes one contiguous eighth of the tiles
+// (best for a single system).  run > 0: each XCD takes runs of `run`
+// consecutive tiles dealt round-robin, so that when the tiles of stopped
+// systems return at once the remaining work is still spread over all XCDs
+// (batches whose systems converge at different iterations).
+__device__ __forceinline__ int xcd_tile(int i, int T, int run) {
+  const int x = i & 7, k = i >> 3;
+  if (run <= 0) {
+    const int q = T >> 3, r = T & 7;
+    return x * q + min(x, r) + k;
+  }
+  if (i >= T / (8 * run) * (8 * run)) return i;  // the tail, in order
+  return ((k / run) * 8 + x) * run + k % run;
+}
+
 // Device view of one (p, d) element group.
 struct GroupDev {
   int32_t p, d, S, npad;   // npad: stride of the DOF-major descriptor arrays
@@ -30,6 +48,8 @@ struct GroupDev {
   const double* kabs;      // row sums of |K_s| [S][ne] (l1 smoother)
   const int32_t* gidx;     // [NEP][npad] free DOF (instance-local) of local DOF, -1 absent
   const int32_t* sidx;     // [MB*16][npad] slot (instance-local), -1 absent
+  const int32_t* msidx;    // [npad][ne][2]: (free DOF, slot) of local DOF a of column col at 2 (col ne + a),
+                           //   -1 absent: the Schwarz application's gathers, one contiguous run per tile
   const int32_t* cell;     // [npad] first density cell (global)
 };
 

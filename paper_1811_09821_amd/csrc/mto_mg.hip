@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "mto_kernels.hpp"
@@ -1229,110 +1231,203 @@ __global__ __launch_bounds__(64, 2) void k_asm_invert(double* __restrict__ binv)
       }
 }
 
-// slots2 = omega * B_e v_e.  One block of 256 threads per tile of
-// EB = asm_cols_of(P) element columns of an instance's first system; thread
-// (column c, row a) for the first NE EB threads.  The tile's packed
-// triangles are one contiguous range of binv, read once from HBM with 16-byte
-// loads by all threads and staged in LDS (each entry serves rows a and b);
-// the loads are issued before the element vectors are gathered, so the two
-// overlap.  Row a then sums B(a, b) v_b in order of b from LDS.  Up to
-// ASM_SYS systems of the instance per pass: the element blocks are shared by
-// its load cases, so one read of a block serves all of them.
+// slots2 = omega * B_e v_e.  A persistent grid (as many blocks of 256
+// threads as fit on the chip at once) walks the tiles of EB = asm_cols_of(P)
+// element columns of each instance's first system; block b takes the tiles
+// b, b + G, b + 2G, ... (G blocks) whose instance still has a running system,
+// found by all its threads at once and listed in LDS.  Thread (column c,
+// row a) serves the first NE EB threads.  A tile's packed triangles are one
+// contiguous range of binv, read with 16-byte loads by all threads and staged
+// in LDS, where each entry serves rows a and b; row a then sums B(a, b) v_b in
+// order of b.  The loads are software-pipelined: while a tile is computed
+// from LDS, the next tile's triangles and element vectors and the tile after
+// it's gather indices are in flight in registers, so HBM stays busy through
+// the LDS-bound sums.  Up to ASM_SYS systems of the instance per pass: the
+// element blocks are shared by its load cases, so one read of a block serves
+// all of them (an instance with more systems takes further passes, whose
+// element vectors are gathered in place).
 constexpr int ASM_SYS = 4;
 constexpr int ASM_THREADS = 256;
+constexpr int ASM_PERSIST_MIN = 4;
 
 template <int P>
-__global__ __launch_bounds__(ASM_THREADS) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(ASM_THREADS, 3) void k_asm_apply(GroupDev g, const Tile* __restrict__ tiles,
                                                            const double* __restrict__ binv,
                                                            const double* __restrict__ v, PcgDev s,
                                                            double* __restrict__ out_slots, double omega, int resid) {
   constexpr int NE = ne_of(P), NTP = asm_ntp_of(P), EB = asm_cols_of(P);
   static_assert(NE * EB <= ASM_THREADS, "one thread per row and column");
-  constexpr int NB2 = EB * NTP / 2;                          // 16-byte words of the tile's triangles
+  constexpr int NB2 = EB * NTP / 2;                          // 16-byte words of a tile's triangles
   constexpr int LPT = (NB2 + ASM_THREADS - 1) / ASM_THREADS;  // of those, per thread
+  constexpr int NW = ASM_THREADS / 64;
   __shared__ double2 bs2[NB2];
   __shared__ double vs[ASM_SYS][EB][NE];
+  __shared__ int list[ASM_THREADS];
+  __shared__ int wcount[NW];
   const double* bs = (const double*)bs2;
-  // a tile of the first system of its instance; the instance's other systems
-  // follow it (instance-major numbering), their count is in pc_begin
-  const Tile t = tiles[g.ms_tile_begin + blockIdx.x];
-  const int nsys = t.pc_begin;
-  {  // nothing to do once every system of the instance has stopped (no block read)
-    bool any = false;
-    for (int l = 0; l < nsys; ++l) any |= s.status[t.sys + l] == SYS_RUNNING;
-    if (!any) return;  // uniform over the block
-  }
-  const int tid = threadIdx.x;
-  // the triangles of columns [elem_begin, elem_begin + count): the words of
-  // absent columns (a partial last tile) are not read
-  const double2* __restrict__ src = (const double2*)(binv + (int64_t)t.elem_begin * NTP);
-  const int nw = t.count * (NTP / 2);
-  double2 stg[LPT];
-#pragma unroll
-  for (int k = 0; k < LPT; ++k) {
-    const int i = tid + ASM_THREADS * k;
-    stg[k] = i < nw ? src[i] : double2{0.0, 0.0};
-  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = tid / NE, a = tid - c * NE;
-  const bool act = c < EB && c < t.count;
-  const int64_t col = t.elem_begin + (act ? c : 0);
-  const int id = act ? g.gidx[a * (int64_t)g.npad + col] : -1;
-  const int si = act ? g.sidx[a * (int64_t)g.npad + col] : -1;
+  const int64_t n = g.ms_n_tiles;
+  const Tile* __restrict__ tl = tiles + g.ms_tile_begin;  // nsys of the tile's instance in pc_begin
+
+  auto running = [&](const Tile& t) {
+    bool any = false;
+    for (int l = 0; l < t.pc_begin; ++l) any |= s.status[t.sys + l] == SYS_RUNNING;
+    return any;
+  };
+  // gather indices of this thread's row of a tile (-1: no row, or a supported DOF)
+  auto indices = [&](const Tile& t, int& id, int& si) {
+    id = si = -1;
+    if (c < EB && c < t.count) {  // thread tid of the tile's contiguous run
+      const int2 q = ((const int2*)g.msidx)[(int64_t)t.elem_begin * NE + tid];
+      id = q.x;
+      si = q.y;
+    }
+  };
+  // a tile's triangles (words of absent columns of a partial last tile are not read)
+  auto triangles = [&](const Tile& t, double2 (&stg)[LPT]) {
+    const double2* __restrict__ src = (const double2*)(binv + (int64_t)t.elem_begin * NTP);
+    const int nw = t.count * (NTP / 2);
 #pragma unroll
-  for (int k = 0; k < LPT; ++k) {
-    const int i = tid + ASM_THREADS * k;
-    if (i < NB2) bs2[i] = stg[k];
+    for (int k = 0; k < LPT; ++k) {
+      const int i = tid + ASM_THREADS * k;
+      stg[k] = i < nw ? src[i] : double2{0.0, 0.0};
+    }
+  };
+  // element-vector entries of systems l0 .. l0 + ASM_SYS - 1 of a tile's
+  // instance (zero for a stopped system or no DOF); bit l of run: system l0 + l runs
+  auto gather = [&](const Tile& t, int l0, int id, double (&x)[ASM_SYS], unsigned& run) {
+    const int np = min(ASM_SYS, t.pc_begin - l0);
+    run = 0;
+#pragma unroll
+    for (int l = 0; l < ASM_SYS; ++l) {
+      x[l] = 0.0;
+      if (l >= np) continue;
+      const int sys = t.sys + l0 + l;
+      if (s.status[sys] != SYS_RUNNING) continue;  // the same address in every lane: one load
+      run |= 1u << l;
+      if (id >= 0) {
+        const SysDesc& sd = s.sys[sys];
+        const double* __restrict__ vsys = v + sd.dof_off;
+        x[l] = resid ? vsys[id] - slot_sum(s.slots + sd.slot_off, id, sd.nfv, sd.nfe) : vsys[id];
+      }
+    }
+  };
+  // rows of one pass from LDS; slots2 of the running systems
+  const int ra = a * NE - (a * (a - 1)) / 2 - a;  // row a: entry (min, max) at cb + a (b < a) or ra + b
+  auto rows = [&](const Tile& t, int l0, int si, unsigned run) {
+    const int np = min(ASM_SYS, t.pc_begin - l0);
+    if (!(c < EB && c < t.count)) return;
+    const double* __restrict__ brow = bs + c * NTP;
+    double acc[ASM_SYS] = {0.0, 0.0, 0.0, 0.0};
+    const double* __restrict__ vc = &vs[0][c][0];
+    auto sum = [&](auto nl) {
+      constexpr int NL = decltype(nl)::value;
+#pragma unroll 5
+      for (int b = 0; b < NE; ++b) {
+        const int cb = b * NE - (b * (b - 1)) / 2 - b;
+        const double e = brow[b < a ? cb + a : ra + b];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) acc[l] = fma(e, vc[l * EB * NE + b], acc[l]);
+      }
+    };
+    switch (np) {  // uniform over the block
+      case 1: sum(std::integral_constant<int, 1>{}); break;
+      case 2: sum(std::integral_constant<int, 2>{}); break;
+      case 3: sum(std::integral_constant<int, 3>{}); break;
+      default: sum(std::integral_constant<int, 4>{}); break;
+    }
+    if (si < 0) return;
+#pragma unroll
+    for (int l = 0; l < ASM_SYS; ++l)
+      if ((run >> l) & 1u) out_slots[s.sys[t.sys + l0 + l].slot_off + si] = omega * acc[l];
+  };
+  auto put_vectors = [&](const Tile& t, const double (&x)[ASM_SYS]) {
+    if (!(c < EB)) return;
+#pragma unroll
+    for (int l = 0; l < ASM_SYS; ++l) vs[l][c][a] = x[l];
+  };
+
+  // tiles at(0), ..., at(cnt - 1) (uniform tile indices): tile i is summed
+  // from LDS while tile i + 1's data and tile i + 2's indices load
+  auto pipeline = [&](int cnt, auto at) {
+    Tile tn = tl[at(0)];
+    double2 stg[LPT];
+    int id, si, id2 = -1, si2 = -1;
+    double x[ASM_SYS];
+    unsigned run;
+    triangles(tn, stg);
+    indices(tn, id, si);
+    Tile tn2 = tn;
+    if (cnt > 1) {
+      tn2 = tl[at(1)];
+      indices(tn2, id2, si2);
+    }
+    gather(tn, 0, id, x, run);
+    for (int i = 0; i < cnt; ++i) {
+      const Tile t = tn;
+      const int cur_id = id, cur_si = si;
+      const unsigned cur_run = run;
+      __syncthreads();  // the previous tile's sums have finished with bs2 and vs
+#pragma unroll
+      for (int k = 0; k < LPT; ++k) {
+        const int j = tid + ASM_THREADS * k;
+        if (j < NB2) bs2[j] = stg[k];
+      }
+      put_vectors(t, x);
+      if (i + 1 < cnt) {
+        tn = tn2;
+        id = id2;
+        si = si2;
+        triangles(tn, stg);
+        if (i + 2 < cnt) {
+          tn2 = tl[at(i + 2)];
+          indices(tn2, id2, si2);
+        }
+      }
+      __syncthreads();  // the tile's triangles and element vectors are in LDS
+      rows(t, 0, cur_si, cur_run);
+      if (i + 1 < cnt) gather(tn, 0, id, x, run);
+      for (int l0 = ASM_SYS; l0 < t.pc_begin; l0 += ASM_SYS) {  // instances with more systems
+        double xx[ASM_SYS];
+        unsigned rr;
+        gather(t, l0, cur_id, xx, rr);
+        __syncthreads();  // vs is free again
+        put_vectors(t, xx);
+        __syncthreads();
+        rows(t, l0, cur_si, rr);
+      }
+    }
+  };
+
+  if (gridDim.x >= n) {  // one tile per block (small launches): no list
+    if (blockIdx.x >= n) return;  // uniform over the block
+    const int ti = xcd_tile(blockIdx.x, (int)n, g.xcd_run);
+    if (!running(tl[ti])) return;
+    pipeline(1, [&](int) { return ti; });
+    return;
   }
-  // row a of the packed triangle: entry (min(a, b), max(a, b)) at
-  // b < a: packed(b, a) = cb + a, b >= a: packed(a, b) = ra + b
-  const int ra = a * NE - (a * (a - 1)) / 2 - a;
-  const double* __restrict__ brow = bs + (act ? c : 0) * NTP;
-  for (int l0 = 0; l0 < nsys; l0 += ASM_SYS) {
-    const int np = min(ASM_SYS, nsys - l0);
-    bool run[ASM_SYS];
+  for (int64_t w0 = blockIdx.x; w0 < n; w0 += (int64_t)gridDim.x * ASM_THREADS) {
+    // this block's tiles w0 + k G, k = 0 .. 255, that still have work: listed in order
+    __syncthreads();  // list and wcount of the previous window are no longer read
+    // candidate w0 + tid G runs on this block's XCD (G is a multiple of 8);
+    // xcd_tile maps it to a tile so that each XCD takes neighbouring tiles
+    const int64_t vi = w0 + (int64_t)tid * gridDim.x;
+    const int ti = vi < n ? xcd_tile((int)vi, (int)n, g.xcd_run) : 0;
+    const bool on = vi < n && running(tl[ti]);
+    const uint64_t bal = __ballot(on);
+    if (lane == 0) wcount[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0, cnt = 0;
 #pragma unroll
-    for (int l = 0; l < ASM_SYS; ++l) {  // the same addresses in every lane: one load each
-      const int sys = t.sys + l0 + (l < np ? l : 0);
-      run[l] = l < np && s.status[sys] == SYS_RUNNING;
+    for (int w = 0; w < NW; ++w) {
+      off += w < wave ? wcount[w] : 0;
+      cnt += wcount[w];
     }
-    if (act) {
-#pragma unroll
-      for (int l = 0; l < ASM_SYS; ++l) {
-        if (l >= np) break;
-        double x = 0.0;
-        if (run[l] && id >= 0) {
-          const SysDesc& sd = s.sys[t.sys + l0 + l];
-          const double* __restrict__ vsys = v + sd.dof_off;
-          x = resid ? vsys[id] - slot_sum(s.slots + sd.slot_off, id, sd.nfv, sd.nfe) : vsys[id];
-        }
-        vs[l][c][a] = x;
-      }
-    }
-    __syncthreads();  // the triangles (first pass) and the element vectors are in LDS
-    if (act) {
-      double acc[ASM_SYS] = {0.0, 0.0, 0.0, 0.0};
-      const double* __restrict__ vc = &vs[0][c][0];
-      auto row = [&](auto nl) {
-        constexpr int NL = decltype(nl)::value;
-#pragma unroll 10
-        for (int b = 0; b < NE; ++b) {
-          const int cb = b * NE - (b * (b - 1)) / 2 - b;
-          const double e = brow[b < a ? cb + a : ra + b];
-#pragma unroll
-          for (int l = 0; l < NL; ++l) acc[l] = fma(e, vc[l * EB * NE + b], acc[l]);
-        }
-      };
-      switch (np) {  // uniform over the block
-        case 1: row(std::integral_constant<int, 1>{}); break;
-        case 2: row(std::integral_constant<int, 2>{}); break;
-        case 3: row(std::integral_constant<int, 3>{}); break;
-        default: row(std::integral_constant<int, 4>{}); break;
-      }
-#pragma unroll
-      for (int l = 0; l < ASM_SYS; ++l)
-        if (l < np && run[l] && si >= 0) out_slots[s.sys[t.sys + l0 + l].slot_off + si] = omega * acc[l];
-    }
-    if (l0 + ASM_SYS < nsys) __syncthreads();  // vs is rewritten by the next pass
+    if (on) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = ti;
+    __syncthreads();
+    if (cnt == 0) continue;  // uniform over the block
+    pipeline(cnt, [&](int i) { return __builtin_amdgcn_readfirstlane(list[i]); });
   }
 }
 
@@ -1442,10 +1537,47 @@ void launch_asm_block(const GroupDev& g, int gi, const GroupDev* groups, const i
     default: hipLaunchKernelGGL(k_asm_invert<4>, grid, dim3(64), 0, st, binv); break;
   }
 }
+// Blocks of k_asm_apply<p> resident on the current device at once (cached per
+// device and order).
+static int asm_apply_blocks(int p) {
+  static int cache[64][4];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int& nb = cache[dev][p - 1];
+  if (nb > 0) return nb;
+  int per_cu = 0, cus = 0;
+  hipError_t e;
+  switch (p) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_asm_apply<1>, ASM_THREADS, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_asm_apply<2>, ASM_THREADS, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_asm_apply<3>, ASM_THREADS, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_asm_apply<4>, ASM_THREADS, 0); break;
+  }
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  nb = per_cu * cus;
+  return nb;
+}
+
 void launch_asm_apply(const GroupDev& g, const Tile* tiles, const double* binv, const double* v, int resid,
                       const PcgDev& s, double* slots2, double omega, hipStream_t st) {
   if (g.ms_n_tiles == 0) return;
-  const dim3 grid(g.ms_n_tiles), block(ASM_THREADS);  // tiles hold asm_cols_of(p) columns
+  // persistent: the blocks that fit on the device at once, at most one per
+  // tile.  MTO_ASM_GRID (a positive integer) caps the count: the results do
+  // not depend on it (every tile is summed the same way by whichever block
+  // takes it), which lets tests run the pipeline and the tile windows of a
+  // large grid on small meshes.
+  // Launches of fewer than ASM_PERSIST_MIN tiles per resident block take one
+  // block per tile instead (the walk's list costs more than it saves there).
+  int nb = asm_apply_blocks(g.p);
+  if (g.ms_n_tiles < ASM_PERSIST_MIN * nb) nb = g.ms_n_tiles;
+  // a multiple of 8 blocks, so that block b and its candidates b + k G share XCD b mod 8
+  nb = (std::min(g.ms_n_tiles, nb) + 7) / 8 * 8;
+  if (const char* cap = std::getenv("MTO_ASM_GRID")) {
+    const int c = std::atoi(cap);
+    if (c > 0) nb = std::min(nb, c);
+  }
+  const dim3 grid(nb), block(ASM_THREADS);
   switch (g.p) {
     case 1: hipLaunchKernelGGL(k_asm_apply<1>, grid, block, 0, st, g, tiles, binv, v, s, slots2, omega, resid); break;
     case 2: hipLaunchKernelGGL(k_asm_apply<2>, grid, block, 0, st, g, tiles, binv, v, s, slots2, omega, resid); break;

@@ -76,6 +76,7 @@ struct GroupHost {
   double* kabs = nullptr;
   int32_t* gidx = nullptr;
   int32_t* sidx = nullptr;
+  int32_t* msidx = nullptr;
   int32_t* cell = nullptr;
   int tile_begin = 0, n_tiles = 0;
   double flops = 0.0;  // 2 S ne^2 per element column
@@ -253,6 +254,7 @@ struct mto_plan {
     o.kabs = g.kabs;
     o.gidx = g.gidx;
     o.sidx = g.sidx;
+    o.msidx = g.msidx;
     o.cell = g.cell;
     return o;
   }
@@ -866,12 +868,15 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
     }
     g.npad = std::max(64, (g.n_elems + 63) / 64 * 64);
     std::vector<int32_t> gidx((size_t)g.nep * g.npad, -1), sidx((size_t)g.ne * g.npad, -1), cell(g.npad, 0);
+    std::vector<int32_t> msidx((size_t)2 * g.ne * g.npad, -1);
     for (int k = 0; k < g.n_elems; ++k) {
       const int i = elems[k].first, e = elems[k].second;
       const int64_t o = I[i].elem_dof_off[e];
       for (int j = 0; j < g.ne; ++j) {
         gidx[(size_t)j * g.npad + k] = I[i].elem_free[o + j];
         sidx[(size_t)j * g.npad + k] = I[i].elem_slot[o + j];
+        msidx[2 * ((size_t)k * g.ne + j)] = I[i].elem_free[o + j];
+        msidx[2 * ((size_t)k * g.ne + j) + 1] = I[i].elem_slot[o + j];
       }
       cell[k] = (int32_t)(P->cell_off[i] + I[i].cell_off[e]);
     }
@@ -897,6 +902,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
             }
     int rc;
     if ((rc = dev_upload(P, &g.gidx, gidx)) || (rc = dev_upload(P, &g.sidx, sidx)) ||
+        (rc = dev_upload(P, &g.msidx, msidx)) ||
         (rc = dev_upload(P, &g.cell, cell)) || (rc = dev_upload(P, &g.ks, ks)) || (rc = dev_upload(P, &g.kfrag, kfr)) ||
         (rc = dev_upload(P, &g.kfragv, kfv)) ||
         (valu_tail(g.p) && (rc = dev_upload(P, &g.kfrags, staged_fragments(ks, g.p, g.d)))) ||

@@ -592,3 +592,27 @@ def test_solve_parity_fused_product(cuda, name):
     rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
     u, c, g, st = plan.solve(rho)
     check_solution(plan, prs, u, c, g, st)
+
+
+def test_schwarz_persistent_grid(cuda, monkeypatch):
+    """The Schwarz smoother's grid capped at 1, 2 and 5 blocks
+    (MTO_ASM_GRID): each block then walks many tiles through its load/compute
+    pipeline, with 1 block over two 256-tile windows (the 48 x 24 p = 4 mesh
+    has 288 tiles of 4 element columns), and a six-load instance takes two
+    passes of four systems per tile.  Every capped solve equals the uncapped
+    one (one block per tile at this size) bit for bit, and that one equals
+    the oracle."""
+    m = mto()
+    loads = [(48, 4 * k, 0.0, -1.0, k) for k in range(6)]
+    prs = [P.uniform_random(48, 24, 4, 5, seed=81, loads=loads, n_load_cases=6),
+           P.small_mixed(14, 7, seed=82, n_loads=3)]
+    plan = m.Plan(prs)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    monkeypatch.delenv("MTO_ASM_GRID", raising=False)
+    u0, c0, g0, st0 = plan.solve(rho)
+    check_solution(plan, prs, u0, c0, g0, st0)
+    for cap in ("1", "2", "5"):
+        monkeypatch.setenv("MTO_ASM_GRID", cap)
+        u, c, g, st = plan.solve(rho)
+        assert torch.equal(u, u0) and torch.equal(c, c0) and torch.equal(g, g0), cap
+        assert st["iterations"] == st0["iterations"], cap
