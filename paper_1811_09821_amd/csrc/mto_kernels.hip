@@ -220,12 +220,15 @@ __global__ __launch_bounds__(16 * dd_rows<P>()) void k_elem_dd(GroupDev g, const
                                                              const double* __restrict__ xhi,
                                                              const double* __restrict__ xlo,
                                                              double* __restrict__ slots,
-                                                             double* __restrict__ slots_lo) {
+                                                             double* __restrict__ slots_lo,
+                                                             const int32_t* __restrict__ dd_ok) {
   constexpr int NE = ne_of(P);
   __shared__ double uh[NE][17], ul[NE][17];
   const Tile t = tiles[g.tile_begin + blockIdx.x];
   const int c0 = blockIdx.y * 16;
-  if (c0 >= t.count) return;  // uniform over the block
+  // uniform over the block; a system that did not run since its last true
+  // residual still has it in the slots
+  if (c0 >= t.count || dd_ok[t.sys]) return;
   const int c = threadIdx.x & 15, row = threadIdx.x >> 4;
   const bool valid = c0 + c < t.count;
   const int el = t.elem_begin + c0 + (valid ? c : 0);
@@ -1164,7 +1167,11 @@ __global__ __launch_bounds__(VBLOCK) void k_init(PcgDev s, int use_slots) {
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_sys_setup(PcgDev s, double rtol2) {
+// Start of a PCG cycle.  At a restart (iterative refinement) a system whose
+// true residual already meets rtol stays stopped: its cycle would end at
+// iteration 0 with x = 0, so skipping it leaves every result the same, and
+// its double-double residual in the slots stays valid for the next cycle end.
+__global__ __launch_bounds__(BLOCK) void k_sys_setup(PcgDev s, double rtol2, int restart) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // invalid densities (flagged by k_simp): no system runs
   const bool bad = s.bad_rho && *s.bad_rho != 0;
@@ -1172,9 +1179,13 @@ __global__ __launch_bounds__(BLOCK) void k_sys_setup(PcgDev s, double rtol2) {
     const SysDesc& sd = s.sys[sys];
     const double ff = wave_sum(s.part_aux, sd.chunk_begin, sd.chunk_end);
     if (lane == 0) {
-      s.tol2[sys] = rtol2 * ff;
-      s.status[sys] = bad ? SYS_BADINPUT : SYS_RUNNING;
+      const double tol2 = rtol2 * ff;
+      const bool met = restart && s.sys_out[4 * sys + 2] <= tol2;  // NaN runs (and breaks down)
+      const int32_t st = bad ? SYS_BADINPUT : met ? SYS_CONVERGED : SYS_RUNNING;
+      s.tol2[sys] = tol2;
+      s.status[sys] = st;
       s.iters[sys] = 0;
+      if (st != SYS_CONVERGED) s.dd_ok[sys] = 0;
     }
   }
   if (threadIdx.x == 0) *s.it_base = 0;
@@ -1388,6 +1399,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual_sums(PcgDev s) {
       s.sys_out[4 * sys + 0] = ff;
       s.sys_out[4 * sys + 1] = fx;
       s.sys_out[4 * sys + 2] = rs;
+      s.dd_ok[sys] = 1;
     }
   }
 }
@@ -1608,8 +1620,8 @@ void launch_init(const PcgDev& s, int use_slots, hipStream_t st) {
   hipLaunchKernelGGL(k_init, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, use_slots);
 }
 
-void launch_sys_setup(const PcgDev& s, double rtol, hipStream_t st) {
-  hipLaunchKernelGGL(k_sys_setup, dim3(1), dim3(BLOCK), 0, st, s, rtol * rtol);
+void launch_sys_setup(const PcgDev& s, double rtol, int restart, hipStream_t st) {
+  hipLaunchKernelGGL(k_sys_setup, dim3(1), dim3(BLOCK), 0, st, s, rtol * rtol, restart);
 }
 
 void launch_dof1(const PcgDev& s, int it_k, hipStream_t st) {
@@ -1636,16 +1648,16 @@ void launch_residual_dd(const GroupDev* groups, int n_groups, const Tile* tiles,
     const dim3 grid(g.n_tiles, g.ncol);  // tiles hold at most 16 ncol columns
     switch (g.p) {
       case 1:
-        hipLaunchKernelGGL(k_elem_dd<1>, grid, dim3(16 * dd_rows<1>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo);
+        hipLaunchKernelGGL(k_elem_dd<1>, grid, dim3(16 * dd_rows<1>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, s.dd_ok);
         break;
       case 2:
-        hipLaunchKernelGGL(k_elem_dd<2>, grid, dim3(16 * dd_rows<2>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo);
+        hipLaunchKernelGGL(k_elem_dd<2>, grid, dim3(16 * dd_rows<2>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, s.dd_ok);
         break;
       case 3:
-        hipLaunchKernelGGL(k_elem_dd<3>, grid, dim3(16 * dd_rows<3>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo);
+        hipLaunchKernelGGL(k_elem_dd<3>, grid, dim3(16 * dd_rows<3>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, s.dd_ok);
         break;
       default:
-        hipLaunchKernelGGL(k_elem_dd<4>, grid, dim3(16 * dd_rows<4>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo);
+        hipLaunchKernelGGL(k_elem_dd<4>, grid, dim3(16 * dd_rows<4>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, s.dd_ok);
         break;
     }
   }

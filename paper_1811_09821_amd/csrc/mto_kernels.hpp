@@ -151,6 +151,8 @@ struct PcgDev {
   int32_t* iters;          // [n_sys]
   double* tol2;            // [n_sys]
   double* sys_out;         // [n_sys][4]: f.f, f.x, |f-Kx|^2, spare
+  int32_t* dd_ok;          // [n_sys]: 1 while (slots, slots_lo) hold the double-double K x of the system's
+                           //   refined solution (set with the true residual, cleared when the system runs)
   int32_t* it_base;        // [1]
   double* progress;        // [2]: systems still running, largest rr / tol2 among them
   const int32_t* bad_rho;  // [1] or NULL: set by k_simp for an invalid density
@@ -222,7 +224,7 @@ void launch_dinv(const PcgDev& s, double* dinv, double scale, hipStream_t st);
 // r = f (use_slots 0), f - assembled slots (1) or the r already stored (2);
 // then z = dinv r, p = 0, partials
 void launch_init(const PcgDev& s, int use_slots, hipStream_t st);
-void launch_sys_setup(const PcgDev& s, double rtol, hipStream_t st);
+void launch_sys_setup(const PcgDev& s, double rtol, int restart, hipStream_t st);
 void launch_dof1(const PcgDev& s, int it_k, hipStream_t st);
 void launch_dof2(const PcgDev& s, int it_k, hipStream_t st);
 void launch_advance(const PcgDev& s, int G, hipStream_t st);

@@ -155,6 +155,7 @@ struct mto_plan {
   int32_t* bad_rho = nullptr;  // [1]: set by the moduli kernel for an invalid density
   double* progress = nullptr;  // [2], written by each chunk's last kernel
   double *tol2 = nullptr, *sys_out = nullptr;
+  int32_t* dd_ok = nullptr;  // [n_sys]
   double* h_sysblk = nullptr;  // host pinned copy of sysblk
   int32_t* f2f = nullptr;
   double* kspr = nullptr;  // ground springs per instance free DOF (NULL: none)
@@ -222,6 +223,7 @@ struct mto_plan {
     s.iters = iters;
     s.tol2 = tol2;
     s.sys_out = sys_out;
+    s.dd_ok = dd_ok;
     s.it_base = it_base;
     s.progress = progress;
     s.bad_rho = bad_rho;
@@ -940,7 +942,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_alloc(P, &P->sysblk, 5 * (size_t)P->n_sys)) ||
       (rc = dev_alloc(P, &P->it_base, 1)) || (rc = dev_alloc(P, &P->progress, 2)) ||
       (rc = dev_alloc(P, &P->bad_rho, 1)) ||
-      (rc = dev_alloc(P, &P->tol2, P->n_sys)) ||
+      (rc = dev_alloc(P, &P->tol2, P->n_sys)) || (rc = dev_alloc(P, &P->dd_ok, P->n_sys)) ||
       (rc = dev_upload(P, &P->f2f, f2f)))
     return cleanup(rc);
   P->status = reinterpret_cast<int32_t*>(P->sysblk);
@@ -971,6 +973,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
   launch_fill(P->slots, 0.0, P->n_slots_tot, 0);
   launch_fill(P->slots_lo, 0.0, P->n_slots_tot, 0);
   launch_fill(P->x, 0.0, P->n_vec, 0);
+  launch_fill_i32(P->dd_ok, 0, P->n_sys, 0);
   if ((rc = check_launch("fill"))) return cleanup(rc);
   if (hipHostMalloc((void**)&P->h_prog, 2 * N_PROG * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(MTO_ENOMEM, "hipHostMalloc failed"));
@@ -1112,6 +1115,7 @@ void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st)
   const PcgDev s = P->pcg();
   // the densities are checked here; k_sys_setup then stops every system if one is invalid
   launch_fill_i32(P->bad_rho, 0, 1, st);
+  launch_fill_i32(P->dd_ok, 0, P->n_sys, st);  // new moduli: no residual in the slots is valid
   launch_simp(rho, P->E, P->dE, P->n_cells_tot, P->prm.E0, P->prm.Emin, P->prm.q, st, P->bad_rho);
   enq_assemble_stored(P, st);
   const bool mg = P->prm.precond != MTO_PRECOND_JACOBI;
@@ -1152,7 +1156,7 @@ void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st)
     launch_fill(P->xs_hi, 0.0, P->n_vec, st);
     launch_init(s, 0, st);
   }
-  launch_sys_setup(s, P->prm.rtol, st);
+  launch_sys_setup(s, P->prm.rtol, 0, st);
   if (mg) {
     (void)hipStreamWaitEvent(st, P->join_ev, 0);
     enq_vcycle(P, 0, 1, st);
@@ -1189,7 +1193,7 @@ void enq_cycle_end(mto_plan* P, hipStream_t st) {
 // Iterative refinement: PCG continues from x with the accurate residual.
 void enq_restart(mto_plan* P, hipStream_t st) {
   launch_init(P->pcg(), 2, st);
-  launch_sys_setup(P->pcg(), P->prm.rtol, st);
+  launch_sys_setup(P->pcg(), P->prm.rtol, 1, st);
   if (P->prm.precond != MTO_PRECOND_JACOBI) enq_vcycle(P, 0, 1, st);
 }
 
