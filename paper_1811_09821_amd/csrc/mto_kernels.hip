@@ -1282,10 +1282,12 @@ __global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
     const double xn = fma(alpha, pi_, xi);
     s.x[o + i] = xn;
     const double rn = fma(-alpha, qi, ri);
-    const double zn = di * rn;
     s.r[o + i] = rn;
-    s.z[o + i] = zn;
-    arz = rn * zn;
+    if (s.z_jacobi) {
+      const double zn = di * rn;
+      s.z[o + i] = zn;
+      arz = rn * zn;
+    }
     arr = rn * rn;
     const double dx = xn / di;  // (D x)_i, D = diag(K) (dinv = 1 / diag, or its l1 variant)
     axx = dx * dx;
@@ -1294,7 +1296,7 @@ __global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
   arr = block_sum<VWAVES>(arr, lds);
   axx = block_sum<VWAVES>(axx, lds);
   if (threadIdx.x == 0) {
-    s.part_rz[(par ^ 1) * s.n_chunks + blockIdx.x] = arz;
+    if (s.z_jacobi) s.part_rz[(par ^ 1) * s.n_chunks + blockIdx.x] = arz;
     s.part_rr[(par ^ 1) * s.n_chunks + blockIdx.x] = arr;
     s.part_xx[(par ^ 1) * s.n_chunks + blockIdx.x] = axx;
     if (blockIdx.x == ch.pc_begin) s.iters[ch.sys] = it + 1;

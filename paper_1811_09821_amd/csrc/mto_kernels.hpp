@@ -133,6 +133,8 @@ struct PcgDev {
   const Chunk* chunks;
   int32_t n_chunks;
   int32_t n_sys;
+  int32_t z_jacobi;        // 1: the iteration's vector update also forms z = dinv r and r.z (Jacobi and the
+                           //   multigrid of Jacobi-type smoothing start from it); 0: the Schwarz V-cycle forms both
   double* x;
   double* r;
   double* z;

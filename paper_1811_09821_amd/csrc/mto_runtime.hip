@@ -205,6 +205,7 @@ struct mto_plan {
     s.chunks = d_chunks;
     s.n_chunks = (int32_t)chunks.size();
     s.n_sys = n_sys;
+    s.z_jacobi = prm.precond != MTO_PRECOND_MG_ASM;
     s.x = x;
     s.r = r;
     s.z = z;
