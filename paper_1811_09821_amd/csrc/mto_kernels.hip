@@ -199,9 +199,10 @@ __device__ __forceinline__ dd_t dd_scale(double a, dd_t y) {
   return two_sum(p, lo);
 }
 
-// Element contraction in double-double: y_e = sum_s E_s (K_s x_e) with every
-// product and sum carried to ~2^-104, results to (slots, slots_lo).  Used
-// only for the true residual.  One block per 16 element columns of a tile
+// Element contraction in extended precision: y_e = sum_s E_s (K_s x_e), each
+// cell's row sum as a compensated dot product (as if in twice FP64's
+// precision), scaled by E_s and summed over the cells in double-double;
+// results to (slots, slots_lo).  Used only for the true residual.  One block per 16 element columns of a tile
 // (blockIdx.y picks the part), one thread per (row, column); x_e (high and
 // low parts) is gathered once into LDS.
 // The rigid motion r_e through x_e's DOFs 0, 1 (vertex (0,0)) and 3 (vertex
@@ -257,15 +258,27 @@ __global__ __launch_bounds__(16 * dd_rows<P>()) void k_elem_dd(GroupDev g, const
   if (si < 0) return;
   const int cb = g.cell[el];
   dd_t y{0.0, 0.0};
+  // Each cell's row sum is a compensated dot product (Ogita, Rump and Oishi's
+  // Dot2): the running sum p carries the leading part, every product's
+  // rounding error (from an FMA) and every addition's (TwoSum) go into one
+  // FP64 correction s; p + s is then as accurate as a sum in twice the
+  // working precision, rounded.  That bound (relative 2^-53 plus
+  // (n 2^-53)^2 of the sum of |terms|) is far below the rtol of any test
+  // while costing 11 FP64 operations per term.
   for (int sc = 0; sc < g.S; ++sc) {
     const double* __restrict__ kr = g.ks + ((size_t)sc * NE + row) * NE;
-    dd_t tacc{0.0, 0.0};
+    double p = 0.0, s = 0.0;
 #pragma unroll 10
     for (int j = 0; j < NE; ++j) {
-      tacc = dd_fma(tacc, kr[j], uh[j][c]);
-      tacc.lo = fma(kr[j], ul[j][c], tacc.lo);  // low part of x: one rounding at ~2^-106 relative
+      const double a = kr[j], b = uh[j][c];
+      const double h = a * b;
+      const double e = fma(a, b, -h);
+      const dd_t ps = two_sum(p, h);
+      p = ps.hi;
+      s += ps.lo + e;
+      s = fma(a, ul[j][c], s);  // low part of x: one rounding at ~2^-106 relative
     }
-    y = dd_add(y, dd_scale(E[cb + sc], two_sum(tacc.hi, tacc.lo)));
+    y = dd_add(y, dd_scale(E[cb + sc], two_sum(p, s)));
   }
   slots[t.slot_off + si] = y.hi;
   slots_lo[t.slot_off + si] = y.lo;
