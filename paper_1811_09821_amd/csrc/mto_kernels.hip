@@ -222,14 +222,14 @@ __global__ __launch_bounds__(16 * dd_rows<P>()) void k_elem_dd(GroupDev g, const
                                                              const double* __restrict__ xlo,
                                                              double* __restrict__ slots,
                                                              double* __restrict__ slots_lo,
-                                                             const int32_t* __restrict__ dd_ok) {
+                                                             const int32_t* __restrict__ skip) {
   constexpr int NE = ne_of(P);
   __shared__ double uh[NE][17], ul[NE][17];
   const Tile t = tiles[g.tile_begin + blockIdx.x];
   const int c0 = blockIdx.y * 16;
-  // uniform over the block; a system that did not run since its last true
-  // residual still has it in the slots
-  if (c0 >= t.count || dd_ok[t.sys]) return;
+  // uniform over the block; skip[sys] != 0: not wanted (a system that did not
+  // run since its last true residual still has it in the slots)
+  if (c0 >= t.count || skip[t.sys]) return;
   const int c = threadIdx.x & 15, row = threadIdx.x >> 4;
   const bool valid = c0 + c < t.count;
   const int el = t.elem_begin + c0 + (valid ? c : 0);
@@ -1198,6 +1198,7 @@ __global__ __launch_bounds__(BLOCK) void k_sys_setup(PcgDev s, double rtol2, int
       s.tol2[sys] = tol2;
       s.status[sys] = st;
       s.iters[sys] = 0;
+      s.rep_count[sys] = 0;
       if (st != SYS_CONVERGED) s.dd_ok[sys] = 0;
     }
   }
@@ -1360,8 +1361,9 @@ __global__ __launch_bounds__(BLOCK) void k_advance(PcgDev s, int G) {
 // Iterative refinement: the solution is carried as xhi + xlo (double-double)
 // and each PCG cycle's correction x is added exactly, then x restarts at 0.
 __global__ __launch_bounds__(VBLOCK) void k_accumulate(PcgDev s, double* __restrict__ xhi,
-                                                       double* __restrict__ xlo) {
+                                                       double* __restrict__ xlo, const int32_t* __restrict__ skip) {
   const Chunk ch = s.chunks[blockIdx.x];
+  if (skip && skip[ch.sys]) return;  // a system not being refined here
   const int64_t o = ch.dof_off;
   for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK) {
     const dd_t v = dd_add(dd_t{xhi[o + i], xlo[o + i]}, dd_t{s.x[o + i], 0.0});
@@ -1373,6 +1375,21 @@ __global__ __launch_bounds__(VBLOCK) void k_accumulate(PcgDev s, double* __restr
 
 // r = f - K x from double-double slots, rounded once; also writes r into the
 // PCG residual (a restart continues from it) and the partial sums.
+// f_i - (K x)_i for free DOF i of chunk ch from the double-double slots
+// (sh, sl), ground springs from x = xhi + xlo; rounded once.
+__device__ __forceinline__ double residual_dd_at(const PcgDev& s, const Chunk& ch, int i,
+                                                 const double* __restrict__ sh, const double* __restrict__ sl,
+                                                 const double* __restrict__ xhi, const double* __restrict__ xlo) {
+  const int64_t o = ch.dof_off;
+  int64_t base;
+  int cnt;
+  slot_range(i, ch.nfv, ch.nfe, base, cnt);
+  dd_t y{sh[base], sl[base]};
+  for (int k = 1; k < cnt; ++k) y = dd_add(y, dd_t{sh[base + k], sl[base + k]});
+  if (s.kspr) y = dd_add(y, dd_scale(s.kspr[ch.inst_free_off + i], dd_t{xhi[o + i], xlo[o + i]}));
+  return dd_add(dd_t{s.f[o + i], 0.0}, dd_t{-y.hi, -y.lo}).hi;
+}
+
 __global__ __launch_bounds__(VBLOCK) void k_residual_dd(PcgDev s, const double* __restrict__ slots_lo,
                                                         const double* __restrict__ xhi,
                                                         const double* __restrict__ xlo) {
@@ -1383,23 +1400,87 @@ __global__ __launch_bounds__(VBLOCK) void k_residual_dd(PcgDev s, const double* 
   const double* __restrict__ sl = slots_lo + ch.slot_off;
   double afx = 0.0, ares = 0.0;
   for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK) {
-    int64_t base;
-    int cnt;
-    slot_range(i, ch.nfv, ch.nfe, base, cnt);
-    dd_t y{sh[base], sl[base]};
-    for (int k = 1; k < cnt; ++k) y = dd_add(y, dd_t{sh[base + k], sl[base + k]});
-    if (s.kspr) y = dd_add(y, dd_scale(s.kspr[ch.inst_free_off + i], dd_t{xhi[o + i], xlo[o + i]}));
     const double fi = s.f[o + i];
-    const dd_t r = dd_add(dd_t{fi, 0.0}, dd_t{-y.hi, -y.lo});
-    s.r[o + i] = r.hi;
+    const double r = residual_dd_at(s, ch, i, sh, sl, xhi, xlo);
+    s.r[o + i] = r;
     afx = fma(fi, xhi[o + i], afx);
-    ares = fma(r.hi, r.hi, ares);
+    ares = fma(r, r, ares);
   }
   afx = block_sum<VWAVES>(afx, lds);
   ares = block_sum<VWAVES>(ares, lds);
   if (threadIdx.x == 0) {
     s.part_aux[s.n_chunks + blockIdx.x] = afx;
     s.part_aux[2 * s.n_chunks + blockIdx.x] = ares;
+  }
+}
+
+// Residual replacement inside a PCG cycle (van der Vorst and Ye's scheme).
+// The recursive residual r drifts from f - K x by the rounding of the FP64
+// products, about the cycle's floor 4 eps ||D x|| (stop_thr2).  Once |r| has
+// come within REPLACE_MARGIN of that floor (the drift is then at most 1/1000
+// of |r|, too little to disturb the recurrences), the system's correction x
+// is folded into the refined solution, r is replaced by the double-double
+// true residual of the result, and PCG continues with the same search
+// direction: the floor restarts from x = 0, so the cycle can go on to rtol
+// instead of stopping at the floor for a cold restart.  Systems already
+// within rtol, or stopped, are left alone.
+constexpr double REPLACE_MARGIN = 1000.0;
+// At most this many replacements per system and cycle: a true residual that
+// no longer falls (rtol below what the double-double residual resolves) then
+// ends the cycle at the floor as before, and the restarts' stall test decides.
+constexpr int REPLACE_MAX = 8;
+
+// rep_skip[sys] = 0 for the systems to refine now, 1 for the others; from the
+// sums of the partials that iteration it (= *it_base + it_k) just wrote.
+__global__ __launch_bounds__(BLOCK) void k_replace_flag(PcgDev s, int it_k) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int par = (*s.it_base + it_k + 1) & 1;
+  for (int sys = wave; sys < s.n_sys; sys += WAVES) {
+    const SysDesc& sd = s.sys[sys];
+    const double* const arr[2] = {s.part_rr + par * s.n_chunks, s.part_xx + par * s.n_chunks};
+    double out[2];
+    wave_sum_n<2>(arr, sd.chunk_begin, sd.chunk_end, out);
+    const double rr = out[0];
+    const double floor2 = 16.0 * 0x1p-106 * out[1];
+    const bool rep = s.status[sys] == SYS_RUNNING && rr > s.tol2[sys] &&
+                     rr <= REPLACE_MARGIN * REPLACE_MARGIN * floor2 && s.rep_count[sys] < REPLACE_MAX;
+    if (lane == 0) {
+      s.rep_skip[sys] = rep ? 0 : 1;
+      if (rep) ++s.rep_count[sys];
+    }
+  }
+}
+
+// r = f - K x (x now the refined solution) for the flagged systems, with the
+// partial sums the next iteration reads: r.r, |D x|^2 = 0 (the correction
+// restarts from 0) and, where the iteration forms z = dinv r itself, z and r.z.
+__global__ __launch_bounds__(VBLOCK) void k_residual_replace(PcgDev s, const double* __restrict__ slots_lo,
+                                                             const double* __restrict__ xhi,
+                                                             const double* __restrict__ xlo, int it_k) {
+  __shared__ double lds[VWAVES + 4];
+  const Chunk ch = s.chunks[blockIdx.x];
+  if (s.rep_skip[ch.sys]) return;
+  const int par = (*s.it_base + it_k + 1) & 1;
+  const int64_t o = ch.dof_off;
+  const double* __restrict__ sh = s.slots + ch.slot_off;
+  const double* __restrict__ sl = slots_lo + ch.slot_off;
+  double arr = 0.0, arz = 0.0;
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += VBLOCK) {
+    const double r = residual_dd_at(s, ch, i, sh, sl, xhi, xlo);
+    s.r[o + i] = r;
+    arr = fma(r, r, arr);
+    if (s.z_jacobi) {
+      const double z = s.dinv[ch.inst_free_off + i] * r;
+      s.z[o + i] = z;
+      arz = fma(r, z, arz);
+    }
+  }
+  arr = block_sum<VWAVES>(arr, lds);
+  arz = block_sum<VWAVES>(arz, lds);
+  if (threadIdx.x == 0) {
+    s.part_rr[par * s.n_chunks + blockIdx.x] = arr;
+    s.part_xx[par * s.n_chunks + blockIdx.x] = 0.0;
+    if (s.z_jacobi) s.part_rz[par * s.n_chunks + blockIdx.x] = arz;
   }
 }
 
@@ -1652,33 +1733,55 @@ void launch_advance(const PcgDev& s, int G, hipStream_t st) {
 }
 
 void launch_accumulate(const PcgDev& s, double* xhi, double* xlo, hipStream_t st) {
-  hipLaunchKernelGGL(k_accumulate, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, xhi, xlo);
+  hipLaunchKernelGGL(k_accumulate, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, xhi, xlo, nullptr);
+}
+
+namespace {
+void launch_elem_dd(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
+                    const double* xhi, const double* xlo, double* slots_lo, const int32_t* skip, hipStream_t st);
+}
+
+void launch_replace(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
+                    double* xhi, double* xlo, double* slots_lo, int it_k, hipStream_t st) {
+  hipLaunchKernelGGL(k_replace_flag, dim3(1), dim3(BLOCK), 0, st, s, it_k);
+  hipLaunchKernelGGL(k_accumulate, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, xhi, xlo, s.rep_skip);
+  launch_elem_dd(groups, n_groups, tiles, E, s, xhi, xlo, slots_lo, s.rep_skip, st);
+  hipLaunchKernelGGL(k_residual_replace, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, slots_lo, xhi, xlo, it_k);
 }
 
 void launch_residual_dd(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
                         const double* xhi, const double* xlo, double* slots_lo, hipStream_t st) {
+  launch_elem_dd(groups, n_groups, tiles, E, s, xhi, xlo, slots_lo, s.dd_ok, st);
+  hipLaunchKernelGGL(k_residual_dd, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, slots_lo, xhi, xlo);
+  hipLaunchKernelGGL(k_residual_sums, dim3(1), dim3(BLOCK), 0, st, s);
+}
+
+namespace {
+// the double-double element products of every group, skipping the tiles of
+// systems with skip[sys] != 0
+void launch_elem_dd(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
+                    const double* xhi, const double* xlo, double* slots_lo, const int32_t* skip, hipStream_t st) {
   for (int k = 0; k < n_groups; ++k) {
     const GroupDev& g = groups[k];
     if (g.n_tiles == 0) continue;
     const dim3 grid(g.n_tiles, g.ncol);  // tiles hold at most 16 ncol columns
     switch (g.p) {
       case 1:
-        hipLaunchKernelGGL(k_elem_dd<1>, grid, dim3(16 * dd_rows<1>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, s.dd_ok);
+        hipLaunchKernelGGL(k_elem_dd<1>, grid, dim3(16 * dd_rows<1>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, skip);
         break;
       case 2:
-        hipLaunchKernelGGL(k_elem_dd<2>, grid, dim3(16 * dd_rows<2>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, s.dd_ok);
+        hipLaunchKernelGGL(k_elem_dd<2>, grid, dim3(16 * dd_rows<2>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, skip);
         break;
       case 3:
-        hipLaunchKernelGGL(k_elem_dd<3>, grid, dim3(16 * dd_rows<3>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, s.dd_ok);
+        hipLaunchKernelGGL(k_elem_dd<3>, grid, dim3(16 * dd_rows<3>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, skip);
         break;
       default:
-        hipLaunchKernelGGL(k_elem_dd<4>, grid, dim3(16 * dd_rows<4>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, s.dd_ok);
+        hipLaunchKernelGGL(k_elem_dd<4>, grid, dim3(16 * dd_rows<4>()), 0, st, g, tiles, E, xhi, xlo, s.slots, slots_lo, skip);
         break;
     }
   }
-  hipLaunchKernelGGL(k_residual_dd, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, slots_lo, xhi, xlo);
-  hipLaunchKernelGGL(k_residual_sums, dim3(1), dim3(BLOCK), 0, st, s);
 }
+}  // namespace
 
 
 void launch_assemble_to_full(const PcgDev& s, const int32_t* free_to_full, double* yfull, int diag_mode,

@@ -155,6 +155,9 @@ struct PcgDev {
   double* sys_out;         // [n_sys][4]: f.f, f.x, |f-Kx|^2, spare
   int32_t* dd_ok;          // [n_sys]: 1 while (slots, slots_lo) hold the double-double K x of the system's
                            //   refined solution (set with the true residual, cleared when the system runs)
+  int32_t* rep_skip;       // [n_sys]: 0 for the systems whose residual is replaced at this point of the
+                           //   cycle (k_replace_flag), 1 for the others
+  int32_t* rep_count;      // [n_sys]: residual replacements in this cycle
   int32_t* it_base;        // [1]
   double* progress;        // [2]: systems still running, largest rr / tol2 among them
   const int32_t* bad_rho;  // [1] or NULL: set by k_simp for an invalid density
@@ -232,6 +235,11 @@ void launch_dof2(const PcgDev& s, int it_k, hipStream_t st);
 void launch_advance(const PcgDev& s, int G, hipStream_t st);
 // accurate true residual: double-double element contraction of xhi + xlo,
 // then r = f - K x rounded once into the PCG residual, |r|^2 and f.xhi per system
+// Residual replacement after iteration *it_base + it_k (before its V-cycle):
+// flags the systems whose residual has come near the cycle's rounding floor,
+// folds their correction into (xhi, xlo) and replaces r by the true residual.
+void launch_replace(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
+                    double* xhi, double* xlo, double* slots_lo, int it_k, hipStream_t st);
 void launch_residual_dd(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
                         const double* xhi, const double* xlo, double* slots_lo, hipStream_t st);
 // (xhi, xlo) += x exactly, then x = 0

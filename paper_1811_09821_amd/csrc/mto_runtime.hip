@@ -156,6 +156,8 @@ struct mto_plan {
   double* progress = nullptr;  // [2], written by each chunk's last kernel
   double *tol2 = nullptr, *sys_out = nullptr;
   int32_t* dd_ok = nullptr;  // [n_sys]
+  int32_t* rep_skip = nullptr;  // [n_sys]
+  int32_t* rep_count = nullptr;  // [n_sys]
   double* h_sysblk = nullptr;  // host pinned copy of sysblk
   int32_t* f2f = nullptr;
   double* kspr = nullptr;  // ground springs per instance free DOF (NULL: none)
@@ -225,6 +227,8 @@ struct mto_plan {
     s.tol2 = tol2;
     s.sys_out = sys_out;
     s.dd_ok = dd_ok;
+    s.rep_skip = rep_skip;
+    s.rep_count = rep_count;
     s.it_base = it_base;
     s.progress = progress;
     s.bad_rho = bad_rho;
@@ -944,6 +948,7 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
       (rc = dev_alloc(P, &P->it_base, 1)) || (rc = dev_alloc(P, &P->progress, 2)) ||
       (rc = dev_alloc(P, &P->bad_rho, 1)) ||
       (rc = dev_alloc(P, &P->tol2, P->n_sys)) || (rc = dev_alloc(P, &P->dd_ok, P->n_sys)) ||
+      (rc = dev_alloc(P, &P->rep_skip, P->n_sys)) || (rc = dev_alloc(P, &P->rep_count, P->n_sys)) ||
       (rc = dev_upload(P, &P->f2f, f2f)))
     return cleanup(rc);
   P->status = reinterpret_cast<int32_t*>(P->sysblk);
@@ -975,6 +980,8 @@ int build_plan(const mto_problem* probs, int n, const mto_params* prm, mto_plan*
   launch_fill(P->slots_lo, 0.0, P->n_slots_tot, 0);
   launch_fill(P->x, 0.0, P->n_vec, 0);
   launch_fill_i32(P->dd_ok, 0, P->n_sys, 0);
+  launch_fill_i32(P->rep_skip, 1, P->n_sys, 0);
+  launch_fill_i32(P->rep_count, 0, P->n_sys, 0);
   if ((rc = check_launch("fill"))) return cleanup(rc);
   if (hipHostMalloc((void**)&P->h_prog, 2 * N_PROG * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(MTO_ENOMEM, "hipHostMalloc failed"));
@@ -1164,12 +1171,19 @@ void enq_setup(mto_plan* P, const double* rho, const double* u0, hipStream_t st)
   }
 }
 
+// G PCG iterations; the last one checks for residual replacement (systems
+// whose recursive residual has come near its rounding floor) before its
+// V-cycle, which then forms z from the replaced residual.
 void enq_chunk(mto_plan* P, int G, hipStream_t st) {
   const PcgDev s = P->pcg();
+  std::vector<GroupDev> gd;
+  for (auto& g : P->groups) gd.push_back(P->gdev(g));
   for (int k = 0; k < G; ++k) {
     enq_elem_all(P, P->p, ELEM_PCG, k, st);
     launch_dof1(s, k, st);
     launch_dof2(s, k, st);
+    if (k == G - 1)
+      launch_replace(gd.data(), (int)gd.size(), P->d_tiles, P->E, s, P->xs_hi, P->xs_lo, P->slots_lo, k, st);
     if (P->prm.precond != MTO_PRECOND_JACOBI) enq_vcycle(P, k, 0, st);
   }
   launch_advance(s, G, st);

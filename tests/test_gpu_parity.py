@@ -387,15 +387,17 @@ def test_time_contraction_modes_leave_solve_exact(cuda):
 
 def test_stalled_true_residual_is_noconv(cuda):
     """A true residual that misses rtol is MTO_ENOCONV, with finite outputs
-    written: rtol 1e-20 with no restarts (the PCG recurrence meets it, but one
-    FP64 correction cannot bring the double-double true residual there), and
-    rtol 1e-40 with three restarts (below what double-double refinement can
-    reach, so the restarts stall).  The same plan at the default tolerance is
-    MTO_OK."""
+    written: rtol 1e-40 (below what the double-double residual resolves) with
+    no restarts and with three (the in-cycle residual replacements and then
+    the restarts stall).  The same plan at the default tolerance is MTO_OK,
+    and at rtol 1e-20 it converges within one cycle: the residual
+    replacements carry it past the FP64 floor without a restart."""
     m = mto()
     pr = P.small_mixed(10, 5, seed=43)
     rho = torch.tensor(pr.rho, device=cuda)
-    for rtol, restarts in ((1e-20, 0), (1e-40, 3)):
+    u, c, g, st = m.Plan(pr, rtol=1e-20, max_restarts=0, max_iter=3000).solve(rho)
+    assert st["status"] == m.MTO_OK and st["restarts"] == 0 and max(st["true_rel_residual"]) <= 1e-20, st
+    for rtol, restarts in ((1e-40, 0), (1e-40, 3)):
         plan = m.Plan(pr, rtol=rtol, max_restarts=restarts, max_iter=3000)
         with pytest.raises(m.MtoError) as ei:
             plan.solve(rho)
