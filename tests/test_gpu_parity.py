@@ -656,3 +656,17 @@ def test_true_residual_extended_precision(cuda, case):
         ref = float(np.sqrt(np.sum(r[free] ** 2)) / np.sqrt(np.sum(f[lc][free].astype(np.longdouble) ** 2)))
         got = st2["true_rel_residual"][lc]
         assert 0.0 < ref < 1e-9 and abs(got - ref) <= 0.02 * ref, (case, lc, got, ref, st["true_rel_residual"])
+
+
+@pytest.mark.parametrize("ncol", [2, 4])
+@pytest.mark.parametrize("name", ["mixed_3loads", "uniform_p4d5", "uniform_p3d4", "uniform_p2d2"])
+def test_solve_parity_wide_tiles(cuda, name, ncol):
+    """Schwarz-multigrid solves with tiles of 16 ncol columns for every group
+    (the PCG product, the product after the pre-smoothing and the vertex
+    update on them, ragged last tiles included), against the oracle."""
+    prs = CASES[name]()
+    plan = mto().Plan(prs)
+    plan.set_tile(ncol, 1)
+    rho = torch.tensor(np.concatenate([p.rho for p in prs]), device=cuda)
+    u, c, g, st = plan.solve(rho)
+    check_solution(plan, prs, u, c, g, st)
