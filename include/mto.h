@@ -170,7 +170,7 @@ typedef struct {
   int32_t restarts;          /* restarts taken */
   int32_t* iterations;       /* host [n_systems] or NULL: PCG iterations per system */
   double* true_rel_residual; /* host [n_systems] or NULL: ||f - K u|| / ||f|| at exit, with
-                                f - K u evaluated in double-double arithmetic */
+                                f - K u evaluated in extended precision (see mto_solve) */
   double solve_ms;           /* host wall time of the call */
 } mto_solve_stats;
 
@@ -230,9 +230,15 @@ int mto_instance_info(const mto_plan* plan, int32_t inst, int64_t* cell_off, int
  *   g    device [n_g] out (dc/drho per load case) or NULL to skip it
  *   u0   device [n_u] initial guess or NULL (zero)
  *   stats host, may be NULL: iteration counts and true residuals
- * Stop test: ||f - K u||_2 <= rtol ||f||_2 per system, with f - K u evaluated
- * in double-double at the end of each PCG cycle; restarts from that residual
- * (at most max_restarts) continue while it misses rtol and still improves.
+ * Stop test: ||f - K u||_2 <= rtol ||f||_2 per system, with u kept in
+ * double-double and f - K u evaluated in extended precision (compensated
+ * per-cell dot products, double-double over the cells) at the end of each
+ * PCG cycle.  Inside a cycle, a system whose recursive residual nears the
+ * rounding floor of its FP64 recurrence has its correction folded into u and
+ * its residual replaced by that accurate one, PCG continuing with the same
+ * search direction (at most 8 times per cycle); restarts from the final
+ * residual (at most max_restarts) continue while it misses rtol and still
+ * improves.
  * Returns MTO_OK, MTO_ENOCONV (the residual of some system misses rtol) or
  * MTO_EBREAKDOWN (outputs are written in these three cases), MTO_EINVAL, or
  * a HIP error.
