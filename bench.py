@@ -76,7 +76,7 @@ def _oracle_one(pr):
         return time.perf_counter() - t0
 
 
-def cpu_baseline(prs, max_designs=8):
+def cpu_baseline(prs, max_designs=16):
     """The oracle as it is, on the host cores: a sample of whole designs of
     the workload (every len(prs) / max_designs-th design), one design per
     worker process (SuperLU is serial; BLAS limited to one thread per
