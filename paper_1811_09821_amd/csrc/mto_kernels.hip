@@ -1317,28 +1317,49 @@ __global__ __launch_bounds__(VBLOCK) void k_dof2(PcgDev s, int it_k) {
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_advance(PcgDev s, int G) {
-  __shared__ int cnt[WAVES];
-  __shared__ double far_w[WAVES];
+// End of a chunk of G iterations, in two launches: k_advance_sys, one wave
+// per system, latches the systems that have stopped and leaves in
+// sys_out[4 sys + 3] how far a running one is from stopping (rr / tol2 over
+// the floor, or -1 once stopped); k_advance_fin then reports the number of
+// running systems and the largest of those ratios, and advances it_base.
+__global__ __launch_bounds__(BLOCK) void k_advance_sys(PcgDev s, int G) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int it_new = *s.it_base + G;
-  int active = 0;
-  double far = 0.0;  // largest rr / tol2 of a running system (how far it is from stopping)
-  for (int sys = wave; sys < s.n_sys; sys += WAVES) {
+  for (int sys = blockIdx.x * WAVES + wave; sys < s.n_sys; sys += gridDim.x * WAVES) {
     const SysDesc& sd = s.sys[sys];
     const double* const arr[2] = {s.part_rr + (it_new & 1) * s.n_chunks, s.part_xx + (it_new & 1) * s.n_chunks};
     double out[2];
     wave_sum_n<2>(arr, sd.chunk_begin, sd.chunk_end, out);
     const double rr = out[0], thr = stop_thr2(s, sys, out[1]);
-    const int st = s.status[sys];
-    if (st == SYS_RUNNING) {
-      if (rr <= thr) {
-        if (lane == 0) s.status[sys] = SYS_CONVERGED;
-      } else {
-        ++active;
-        far = fmax(far, rr / thr);
+    if (lane == 0) {
+      double far = -1.0;
+      if (s.status[sys] == SYS_RUNNING) {
+        if (rr <= thr)
+          s.status[sys] = SYS_CONVERGED;
+        else
+          far = rr / thr;
       }
+      s.sys_out[4 * sys + 3] = far;
     }
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_advance_fin(PcgDev s, int G) {
+  __shared__ int cnt[WAVES];
+  __shared__ double far_w[WAVES];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int active = 0;
+  double far = 0.0;  // largest rr / tol2 of a running system (how far it is from stopping)
+  for (int sys = threadIdx.x; sys < s.n_sys; sys += BLOCK) {
+    const double f = s.sys_out[4 * sys + 3];
+    if (f >= 0.0) {
+      ++active;
+      far = fmax(far, f);
+    }
+  }
+  for (int m = 32; m >= 1; m >>= 1) {
+    active += __shfl_xor(active, m);
+    far = fmax(far, __shfl_xor(far, m));
   }
   if (lane == 0) {
     cnt[wave] = active;
@@ -1354,7 +1375,7 @@ __global__ __launch_bounds__(BLOCK) void k_advance(PcgDev s, int G) {
     }
     s.progress[0] = (double)tot;
     s.progress[1] = f;
-    *s.it_base = it_new;
+    *s.it_base += G;
   }
 }
 
@@ -1435,7 +1456,7 @@ constexpr int REPLACE_MAX = 8;
 __global__ __launch_bounds__(BLOCK) void k_replace_flag(PcgDev s, int it_k) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int par = (*s.it_base + it_k + 1) & 1;
-  for (int sys = wave; sys < s.n_sys; sys += WAVES) {
+  for (int sys = blockIdx.x * WAVES + wave; sys < s.n_sys; sys += gridDim.x * WAVES) {  // one wave per system
     const SysDesc& sd = s.sys[sys];
     const double* const arr[2] = {s.part_rr + par * s.n_chunks, s.part_xx + par * s.n_chunks};
     double out[2];
@@ -1729,7 +1750,8 @@ void launch_dof2(const PcgDev& s, int it_k, hipStream_t st) {
 }
 
 void launch_advance(const PcgDev& s, int G, hipStream_t st) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(BLOCK), 0, st, s, G);
+  hipLaunchKernelGGL(k_advance_sys, dim3((s.n_sys + WAVES - 1) / WAVES), dim3(BLOCK), 0, st, s, G);
+  hipLaunchKernelGGL(k_advance_fin, dim3(1), dim3(BLOCK), 0, st, s, G);
 }
 
 void launch_accumulate(const PcgDev& s, double* xhi, double* xlo, hipStream_t st) {
@@ -1743,7 +1765,7 @@ void launch_elem_dd(const GroupDev* groups, int n_groups, const Tile* tiles, con
 
 void launch_replace(const GroupDev* groups, int n_groups, const Tile* tiles, const double* E, const PcgDev& s,
                     double* xhi, double* xlo, double* slots_lo, int it_k, hipStream_t st) {
-  hipLaunchKernelGGL(k_replace_flag, dim3(1), dim3(BLOCK), 0, st, s, it_k);
+  hipLaunchKernelGGL(k_replace_flag, dim3((s.n_sys + WAVES - 1) / WAVES), dim3(BLOCK), 0, st, s, it_k);
   hipLaunchKernelGGL(k_accumulate, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, xhi, xlo, s.rep_skip);
   launch_elem_dd(groups, n_groups, tiles, E, s, xhi, xlo, slots_lo, s.rep_skip, st);
   hipLaunchKernelGGL(k_residual_replace, dim3(s.n_chunks), dim3(VBLOCK), 0, st, s, slots_lo, xhi, xlo, it_k);

@@ -152,7 +152,8 @@ struct PcgDev {
   int32_t* status;         // [n_sys]
   int32_t* iters;          // [n_sys]
   double* tol2;            // [n_sys]
-  double* sys_out;         // [n_sys][4]: f.f, f.x, |f-Kx|^2, spare
+  double* sys_out;         // [n_sys][4]: f.f, f.x, |f-Kx|^2, and the last chunk's rr / tol2 of a running
+                           //   system over its floor (-1: stopped; k_advance_sys)
   int32_t* dd_ok;          // [n_sys]: 1 while (slots, slots_lo) hold the double-double K x of the system's
                            //   refined solution (set with the true residual, cleared when the system runs)
   int32_t* rep_skip;       // [n_sys]: 0 for the systems whose residual is replaced at this point of the
